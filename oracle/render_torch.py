@@ -1,0 +1,113 @@
+"""Differentiable FP64 reference of the emission-absorption ray caster.
+
+TEST INFRASTRUCTURE ONLY.  A second, independent implementation of the
+oracle's rendering model (the one in render.c), written with torch CPU
+tensor ops in float64 and vectorised over rays, so that torch autograd gives
+exact derivatives of the discrete sum with respect to the density grid and
+the transfer-function table.  It marches every ray to its exit (no early
+termination).  Used on small grids only: the autograd graph holds every
+sample of every ray.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+
+def rays(cams, W, H):
+    """Origins and unit directions [V*H*W][3] (float64 numpy), pixel centres, row 0 on top."""
+    cams = np.asarray(cams, dtype=np.float64).reshape(-1, 11)
+    jj, ii = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
+                         indexing="ij")
+    nx_ = (2.0 * (ii + 0.5) / W - 1.0) * (W / H)
+    ny_ = 1.0 - 2.0 * (jj + 0.5) / H
+    O, D = [], []
+    for c in cams:
+        eye, tgt, up = c[0:3], c[3:6], c[6:9]
+        f = tgt - eye
+        f = f / np.linalg.norm(f)
+        r = np.cross(f, up)
+        r = r / np.linalg.norm(r)
+        u = np.cross(r, f)
+        off = nx_[..., None] * r + ny_[..., None] * u
+        if c[9] > 0:
+            d = f + math.tan(math.radians(c[9]) / 2.0) * off
+            d = d / np.linalg.norm(d, axis=-1, keepdims=True)
+            o = np.broadcast_to(eye, d.shape)
+        else:
+            o = eye + c[10] * off
+            d = np.broadcast_to(f, o.shape)
+        O.append(o.reshape(-1, 3))
+        D.append(d.reshape(-1, 3))
+    return np.concatenate(O), np.concatenate(D)
+
+
+def render(density: torch.Tensor, tf: torch.Tensor, cams, W, H, step, spacing=(1.0, 1.0, 1.0),
+           bg=(0.0, 0.0, 0.0, 0.0)) -> torch.Tensor:
+    """rgba [V][H][W][4] as a differentiable function of density [nz][ny][nx] and tf [256][4]."""
+    assert density.dtype == torch.float64 and tf.dtype == torch.float64
+    nz, ny, nx = density.shape
+    sp = np.asarray(spacing, dtype=np.float64)
+    ext = np.array([nx, ny, nz], dtype=np.float64) * sp
+    o, d = rays(cams, W, H)
+    R = o.shape[0]
+    # slab test per axis
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ta = (0.0 - o) / d
+        tb = (ext - o) / d
+    lo = np.where(d == 0.0, np.where((o >= 0.0) & (o <= ext), -np.inf, np.inf), np.minimum(ta, tb))
+    hi = np.where(d == 0.0, np.where((o >= 0.0) & (o <= ext), np.inf, -np.inf), np.maximum(ta, tb))
+    t_in = np.maximum(lo.max(axis=1), 0.0)
+    t_out = hi.min(axis=1)
+    hit = t_out > t_in
+    Lr = np.where(hit, t_out - t_in, 0.0)
+    t_in = np.where(hit, t_in, 0.0)
+    n = np.where(hit, np.maximum(1, np.ceil(Lr / step)), 0).astype(np.int64)
+    nmax = int(n.max()) if R else 0
+
+    flat = density.reshape(-1)
+    dims = np.array([nx, ny, nz])
+    T = torch.ones(R, dtype=torch.float64)
+    Cc = torch.zeros(R, 3, dtype=torch.float64)
+    o_t, d_t = torch.from_numpy(o.copy()), torch.from_numpy(d.copy())
+    t_in_t = torch.from_numpy(t_in)
+    n_t = torch.from_numpy(n)
+    L_t = torch.from_numpy(Lr)
+    sp_t = torch.from_numpy(sp)
+    for k in range(nmax):
+        active = n_t > k
+        last = n_t - 1 == k
+        seg = torch.where(last, L_t - (n_t - 1).double() * step, torch.full_like(L_t, step))
+        seg = torch.where(active, seg, torch.zeros_like(seg))
+        t = torch.where(active, t_in_t + k * step + 0.5 * seg, torch.zeros_like(seg))
+        p = o_t + t[:, None] * d_t
+        u = p / sp_t - 0.5
+        i0 = torch.floor(u)
+        w = u - i0
+        i0 = i0.long()
+        s = torch.zeros(R, dtype=torch.float64)
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    xi = (i0[:, 0] + dx).clamp(0, int(dims[0]) - 1)
+                    yi = (i0[:, 1] + dy).clamp(0, int(dims[1]) - 1)
+                    zi = (i0[:, 2] + dz).clamp(0, int(dims[2]) - 1)
+                    wt = ((w[:, 0] if dx else 1 - w[:, 0]) * (w[:, 1] if dy else 1 - w[:, 1])
+                          * (w[:, 2] if dz else 1 - w[:, 2]))
+                    s = s + wt * flat[(zi * ny + yi) * nx + xi]
+        x = s.clamp(0.0, 1.0) * 255.0
+        kk = torch.floor(x).long().clamp(max=254)
+        ww = (x - kk.double())[:, None]
+        q = (1 - ww) * tf[kk] + ww * tf[kk + 1]
+        e = torch.exp(-q[:, 3] * seg)
+        alpha = 1.0 - e
+        Cc = Cc + (T * alpha)[:, None] * q[:, :3]
+        T = T * e
+    bg_t = torch.tensor(bg, dtype=torch.float64)
+    rgb = Cc + T[:, None] * bg_t[:3]
+    a = 1.0 - T * (1.0 - bg_t[3])
+    out = torch.cat([rgb, a[:, None]], dim=1)
+    V = len(np.asarray(cams).reshape(-1, 11))
+    return out.reshape(V, H, W, 4)
