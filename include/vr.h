@@ -1,0 +1,220 @@
+/*
+ * vr.h — C ABI of the MI355X (gfx950) preview library.
+ *
+ * The library computes the data-parallel core of low-latency visual previews
+ * of 16-bit micro-CT volumes (Tan Jerome et al., "Low-latency Visual Previews
+ * of Large Synchrotron Micro-CT Datasets"): histogram filtering and
+ * thresholding of the volume (Sections III-A and III-D), a multi-resolution
+ * box-filtered pyramid (abstract; Section II, interactive preview) packed into
+ * slicemap atlases (Section III), and emission-absorption ray casting of the
+ * reduced volume into turntable frames (Section III-C, rotation about Z),
+ * plus the adjoint of that ray caster.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: VR_OK (0) or a negative VR_ERR_* code.  Argument errors
+ *     are detected before anything is enqueued; launch errors are read back
+ *     with hipGetLastError.  vr_last_error() gives a message for the last
+ *     failing call on the calling host thread.
+ *   - Pointers prefixed d_ are device pointers (hipMalloc'd or equivalent),
+ *     h_ are host pointers read only during the call.  The caller owns every
+ *     buffer; the single-call entry points never allocate or free memory.
+ *   - Every call is asynchronous on `stream` (a hipStream_t, NULL = the
+ *     default stream) and never synchronises the host, so a sequence of calls
+ *     can be captured into a HIP graph.  Output buffers are written entirely
+ *     by the call (including zeroing of accumulated outputs) unless stated
+ *     otherwise.
+ *   - Volumes are C-contiguous [nz][ny][nx] with x fastest: slice z is the
+ *     z-th reconstructed 2D slice of the stack (Section III).  Voxel (x, y, z)
+ *     covers [x, x+1) x [y, y+1) x [z, z+1) times the spacing in world units.
+ *   - Calls are reentrant; concurrent calls on different streams are safe as
+ *     long as their output buffers do not overlap.
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VR_NBINS 65536            /* 16-bit grey values */
+#define VR_KEEP_WORDS 2048        /* keep mask: bin b -> bit (b % 32) of word b / 32 */
+#define VR_MAX_LEVELS 4           /* pyramid levels produced by one call */
+#define VR_MAX_VIEWS_PER_LAUNCH 48
+
+enum {
+    VR_OK = 0,
+    VR_ERR_NULL = -1,          /* a required pointer is NULL */
+    VR_ERR_DIMS = -2,          /* a size is < 1 or too large */
+    VR_ERR_RANGE = -3,         /* a parameter is outside its documented range */
+    VR_ERR_DTYPE = -4,         /* unsupported element type for this call */
+    VR_ERR_HIP = -5,           /* the HIP runtime reported an error */
+    VR_ERR_UNSUPPORTED = -6,   /* valid request this build does not implement */
+    VR_ERR_WORKSPACE = -7      /* workspace too small */
+};
+
+/* threshold rules for vr_select_threshold */
+enum {
+    VR_RULE_VALLEY = 0,        /* first valley above the air peak (param = smoothing radius) */
+    VR_RULE_OTSU = 1,          /* Algorithm 1 (param = log2 of the bin width, 0 or 8 typical) */
+    VR_RULE_ITS = 2,           /* Algorithm 2 (param = log2 of the bin width) */
+    VR_RULE_NONE = 3           /* T = 0: only the top-slice histogram filter applies */
+};
+
+/* volume element types */
+enum { VR_U16_NORM = 0, VR_F32 = 1 };
+
+/*
+ * Histogram of grey values (Section III-D: the volume histogram, and the
+ * histogram of the first three slices that holds the signature of air and
+ * container).  d_hist[b] = number of voxels of value b among slices
+ * z0 <= z < z0 + nz_range of the u16 volume d_vol [nz][ny][nx].
+ *   d_hist: 65536 uint64 counters, overwritten.
+ *   nz_range may be 0 (all counters become 0).
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS (a size < 1), VR_ERR_RANGE (z-range not
+ * inside [0, nz)), VR_ERR_HIP.
+ */
+int vr_histogram(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
+                 int64_t z0, int64_t nz_range, uint64_t* d_hist, void* stream);
+
+/*
+ * Threshold selection and keep mask, entirely on the device (no host sync).
+ * Thresholding classifies each voxel as kept or removed by its grey value
+ * (Section III-A); histogram filtering removes every grey value that occurs
+ * in the top-slice histogram (Section III-D).  The keep mask is
+ *   keep[b] = (b >= T) && (d_hist_top == NULL || d_hist_top[b] == 0).
+ * T is chosen by `rule`:
+ *   VR_RULE_VALLEY: S = d_hist box-smoothed with radius `param` (1..4096);
+ *     p = first argmax of S; T = start of the plateau of the first bin above
+ *     p where 2*S[b] <= S[p] and S[b+1] > S[b]; 65535 if none.
+ *   VR_RULE_OTSU: Algorithm 1 on the histogram with bins of width 2^param
+ *     (param 0..12), between-class variance evaluated in IEEE FP64 in the
+ *     order w_a*w_b*(mu_a-mu_b)^2, classes [0,T) and [T,B-1], lowest T on
+ *     ties; the result is scaled back to 16-bit grey values (T << param).
+ *   VR_RULE_ITS: Algorithm 2 (isodata), T <- floor((mu_1+mu_2)/2) in FP64
+ *     from the middle of the occupied range until T repeats, same bins.
+ *   VR_RULE_NONE: T = 0.
+ *   d_result: 4 uint32 written: [0] = T (16-bit grey value), [1] = the air
+ *     peak p (valley) or the iteration count (ITS), [2] = b* (valley), [3] = 0.
+ *   d_keep_bits: 2048 uint32, overwritten.
+ * Errors: VR_ERR_NULL, VR_ERR_RANGE (rule or param), VR_ERR_HIP.
+ */
+int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_hist_top, int rule, int param,
+                        uint32_t* d_result, uint32_t* d_keep_bits, void* stream);
+
+/*
+ * Thresholding fused with the multi-resolution pyramid (abstract and
+ * Section II: a coarse resolution is delivered before the full data).
+ * f = keep[v] ? v : 0 per voxel (d_keep_bits NULL keeps every voxel); level
+ * k = 1..n_levels has dims ceil(n / 2^k) per axis and
+ *   L_k = (S_k + 2^(3k-1)) >> 3k,
+ * S_k the exact integer sum of f over the 2^k cube at 2^k*(x, y, z), with
+ * voxels past the volume's end counted as 0 (round-half-up mean over the
+ * full cube, each level from its own exact sum).  One pass over the volume.
+ *   h_levels: host array of n_levels device pointers, level k at
+ *     h_levels[k-1], each [nz_k][ny_k][nx_k] u16, overwritten.
+ *   n_levels: 1..VR_MAX_LEVELS.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (n_levels), VR_ERR_HIP.
+ */
+int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
+                            const uint32_t* d_keep_bits, int n_levels,
+                            uint16_t* const* h_levels, void* stream);
+
+/*
+ * Slicemap atlas of a volume level (Section III, slicemaps of the cited
+ * prior work): a 2D image of tiles_y x tiles_x tiles of nx x ny pixels in
+ * which atlas pixel (tx*nx + x, ty*ny + y) = L[z][y][x] with
+ * z = ty*tiles_x + tx; tiles past the last slice are 0.
+ *   d_atlas: [tiles_y*ny][tiles_x*nx] of u16 (out_bits 16) or u8 (out_bits 8,
+ *     value min(255, (L + 128) >> 8)), overwritten.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (tiles_x*tiles_y < nz or
+ * out_bits not 8/16), VR_ERR_HIP.
+ */
+int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz, int tiles_x,
+                     int tiles_y, int out_bits, void* d_atlas, void* stream);
+
+/* A volume to render. dtype VR_U16_NORM (value / 65535) or VR_F32 (value). */
+typedef struct {
+    const void* data;          /* device pointer, [nz][ny][nx] */
+    int32_t dtype;
+    int32_t reserved;
+    int64_t nx, ny, nz;
+    double spacing[3];         /* world units per voxel along x, y, z (> 0) */
+} vr_volume;
+
+/* A pinhole (fov_y_deg > 0) or orthographic (fov_y_deg == 0) camera. */
+typedef struct {
+    double eye[3], target[3], up[3];
+    double fov_y_deg;          /* vertical field of view, 0 < fov < 180, or 0 */
+    double ortho_half_h;       /* half height of the orthographic view (> 0) */
+} vr_camera;
+
+typedef struct {
+    int32_t width, height;     /* pixels, >= 1 */
+    float step;                /* sample spacing along the ray, world units (> 0) */
+    float ert_eps;             /* stop a ray once its transmittance < ert_eps; 0 = never */
+    float bg[4];               /* background RGBA behind the volume */
+} vr_render_opts;
+
+/*
+ * Emission-absorption ray casting (Section III-C renders the reduced data to
+ * 2D images while rotating about Z).  For the pixel centre (i+1/2, j+1/2),
+ * row 0 at the top, with f = normalise(target - eye), r = normalise(f x up),
+ * u = r x f, ndc_x = (2(i+1/2)/W - 1) W/H, ndc_y = 1 - 2(j+1/2)/H:
+ *   perspective: origin eye, direction normalise(f + tan(fov/2)(ndc_x r + ndc_y u));
+ *   orthographic: origin eye + h (ndc_x r + ndc_y u), direction f.
+ * The ray is clipped to the world box [0, n*spacing]^3 giving [t0, t1];
+ * n = max(1, ceil((t1-t0)/step - 2^-10)) midpoint samples of length step, the
+ * last one ending exactly at t1 (shorter than step, or longer by less than
+ * step/1024 when rounding made the segment a hair over a whole number of steps).  Density = trilinear
+ * interpolation of cell-centred voxels with taps clamped to the volume; the
+ * transfer function d_tf (256 x (r, g, b, sigma) f32, sigma = extinction per
+ * world unit) is interpolated linearly at x = 255 clamp(s, 0, 1).  Front to
+ * back: alpha = 1 - exp(-sigma len), C += T alpha rgb, T *= exp(-sigma len);
+ * output RGB = C + T bg_rgb, A = 1 - T (1 - bg_a).  Missing rays get bg.
+ *   d_rgba: [n_views][height][width][4] f32, overwritten.
+ *   d_samples: NULL or one uint64 to which the number of samples taken is
+ *     added (the caller zeroes it).
+ *   h_cams: n_views cameras (any n_views >= 1; views are launched in groups
+ *     of VR_MAX_VIEWS_PER_LAUNCH).
+ * All arithmetic is FP32; per-ray results do not depend on the launch shape.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (step, fov, spacing),
+ * VR_ERR_DTYPE, VR_ERR_HIP.
+ */
+int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams, int n_views,
+               const vr_render_opts* opts, float* d_rgba, uint64_t* d_samples, void* stream);
+
+/*
+ * Adjoint of vr_raycast for an f32 density grid: given dLoss/dRGBA, adds
+ * dLoss/dDensity to d_grad_density ([nz][ny][nx] f32) and dLoss/dTF to
+ * d_grad_tf (256 x 4 f32).  Accumulates: the caller zeroes both first.  Each
+ * ray is re-marched with the same samples and the same early-termination
+ * decisions as the forward pass (nothing is stored per sample); d_rgba_fwd
+ * must be the forward output of the same inputs.
+ * Gradient of sample i (length len, transmittance T_i before it, colour
+ * prefix P_i including it, output I):
+ *   dI_rgb/drgb_i = T_i alpha_i,
+ *   dI_rgb/dsigma_i = len (T_i e_i rgb_i - (I_rgb - P_i)),
+ *   dI_a/dsigma_i = len (1 - I_a),
+ * then through the transfer-function interpolation to the two knots, and
+ * through the trilinear weights to the eight taps (f32 atomics; the
+ * summation order is not deterministic).
+ * Errors: as vr_raycast, VR_ERR_DTYPE unless vol->dtype == VR_F32.
+ */
+int vr_raycast_backward(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams,
+                        int n_views, const vr_render_opts* opts, const float* d_rgba_fwd,
+                        const float* d_grad_rgba, float* d_grad_density, float* d_grad_tf,
+                        void* stream);
+
+/* Message for the last non-zero return on this host thread ("" if none). */
+const char* vr_last_error(void);
+
+/* Library version string. */
+const char* vr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_H */

@@ -8,7 +8,10 @@
  * This file follows the reading used throughout the project:
  *   - emission-absorption model with extinction sigma per world unit;
  *   - front-to-back compositing, midpoint samples of step "step" with a
- *     shortened last step so the steps cover [t0, t_out] exactly;
+ *     last step that ends the steps exactly at t_out; the step count is
+ *     n = max(1, ceil(L/step - 2^-10)), so a segment that is a whole number
+ *     of steps up to rounding of the clipped length is not given an extra
+ *     sliver of a step (the last step then exceeds "step" by < step/1024);
  *   - density = trilinear interpolation of cell-centred voxels, taps clamped
  *     to the volume (clamp-to-edge), u16 voxels scaled by 1/65535;
  *   - 256-entry piecewise-linear (r, g, b, sigma) transfer function.
@@ -159,7 +162,7 @@ long or_march(const or_volume* v, const double* tf, const double o[3], const dou
         return 0;
     }
     double L = t1 - t0;
-    long n = (long)ceil(L / step);
+    long n = (long)ceil(L / step - 1.0 / 1024.0);
     if (n < 1) n = 1;
     double T = 1.0, C[3] = { 0.0, 0.0, 0.0 };
     long counted = 0;

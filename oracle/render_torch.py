@@ -64,7 +64,7 @@ def render(density: torch.Tensor, tf: torch.Tensor, cams, W, H, step, spacing=(1
     hit = t_out > t_in
     Lr = np.where(hit, t_out - t_in, 0.0)
     t_in = np.where(hit, t_in, 0.0)
-    n = np.where(hit, np.maximum(1, np.ceil(Lr / step)), 0).astype(np.int64)
+    n = np.where(hit, np.maximum(1, np.ceil(Lr / step - 1.0 / 1024.0)), 0).astype(np.int64)
     nmax = int(n.max()) if R else 0
 
     flat = density.reshape(-1)

@@ -1,0 +1,473 @@
+// Emission-absorption ray casting of the reduced volume into preview frames
+// (Section III-C: the volume rendered to 2D images while it turns about Z),
+// and its adjoint.
+//
+// Launch shape: a workgroup is a 16 x 16-pixel ray tile made of four 8 x 8
+// waves, so the 64 rays of a wave are neighbours and their trilinear taps
+// share cache lines.  Workgroup ids are remapped so that the tiles of one
+// view that run at the same time sit on the same XCD (consecutive ids are
+// dealt round-robin over the 8 XCDs, each with its own L2).  The transfer
+// function is staged in LDS.  Samples are FP32 with explicit fused
+// multiply-adds (this file builds with contraction off), so the forward and
+// the adjoint replay bit-identical transmittances and stop at the same sample.
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 16;
+constexpr int kMaxViews = VR_MAX_VIEWS_PER_LAUNCH;
+
+struct View {
+    float eye[3];   // perspective origin, or centre of the orthographic view
+    float f[3];     // unit forward
+    float r[3];     // right, scaled by tan(fov/2) or by the orthographic half height
+    float u[3];     // up, scaled likewise
+    float persp;    // 1: perspective, 0: orthographic
+};
+
+struct Views {
+    View v[kMaxViews];
+};
+
+struct Scene {
+    const void* data;
+    int nx, ny, nz;
+    float inv_sp[3];
+    float ext[3];
+    int W, H;
+    float aspect;
+    float step, eps;
+    float bg[4];
+    int view0;
+    int tiles_x, tiles_y;
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+// Everything one sample needs: the eight tap offsets, the trilinear weights
+// and the interpolated (normalised) density.
+struct Sample {
+    uint32_t off[8];   // (x, y, z) taps in order x fastest: 000 100 010 110 001 101 011 111
+    float wx, wy, wz;
+    float s;
+};
+
+template <typename T>
+__device__ __forceinline__ float voxel(const T* p, uint32_t i);
+template <>
+__device__ __forceinline__ float voxel<uint16_t>(const uint16_t* p, uint32_t i) { return (float)p[i]; }
+template <>
+__device__ __forceinline__ float voxel<float>(const float* p, uint32_t i) { return p[i]; }
+
+__device__ __forceinline__ float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
+
+template <typename T>
+__device__ __forceinline__ void sample(const Scene& S, const T* __restrict__ vol, float px, float py,
+                                       float pz, Sample& sm)
+{
+    const float ux = fmaf(px, S.inv_sp[0], -0.5f);
+    const float uy = fmaf(py, S.inv_sp[1], -0.5f);
+    const float uz = fmaf(pz, S.inv_sp[2], -0.5f);
+    const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
+    sm.wx = ux - fx;
+    sm.wy = uy - fy;
+    sm.wz = uz - fz;
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const uint32_t x0 = (uint32_t)min(max(ix, 0), S.nx - 1), x1 = (uint32_t)min(max(ix + 1, 0), S.nx - 1);
+    const uint32_t y0 = (uint32_t)min(max(iy, 0), S.ny - 1), y1 = (uint32_t)min(max(iy + 1, 0), S.ny - 1);
+    const uint32_t z0 = (uint32_t)min(max(iz, 0), S.nz - 1), z1 = (uint32_t)min(max(iz + 1, 0), S.nz - 1);
+    const uint32_t nx = (uint32_t)S.nx, ny = (uint32_t)S.ny;
+    const uint32_t r00 = (z0 * ny + y0) * nx, r10 = (z0 * ny + y1) * nx;
+    const uint32_t r01 = (z1 * ny + y0) * nx, r11 = (z1 * ny + y1) * nx;
+    sm.off[0] = r00 + x0; sm.off[1] = r00 + x1;
+    sm.off[2] = r10 + x0; sm.off[3] = r10 + x1;
+    sm.off[4] = r01 + x0; sm.off[5] = r01 + x1;
+    sm.off[6] = r11 + x0; sm.off[7] = r11 + x1;
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = voxel<T>(vol, sm.off[t]);
+    const float c0 = lerpf(lerpf(v[0], v[1], sm.wx), lerpf(v[2], v[3], sm.wx), sm.wy);
+    const float c1 = lerpf(lerpf(v[4], v[5], sm.wx), lerpf(v[6], v[7], sm.wx), sm.wy);
+    const float s = lerpf(c0, c1, sm.wz);
+    sm.s = (sizeof(T) == 2) ? s * (1.0f / 65535.0f) : s;
+}
+
+struct TfHit {
+    int k;
+    float w;
+    float4 q;
+};
+
+__device__ __forceinline__ TfHit tf_lookup(const float4* tf, float s)
+{
+    TfHit h;
+    const float x = fminf(fmaxf(s, 0.0f), 1.0f) * 255.0f;
+    h.k = min((int)x, 254);
+    h.w = x - (float)h.k;
+    const float4 a = tf[h.k], b = tf[h.k + 1];
+    h.q = make_float4(lerpf(a.x, b.x, h.w), lerpf(a.y, b.y, h.w), lerpf(a.z, b.z, h.w),
+                      lerpf(a.w, b.w, h.w));
+    return h;
+}
+
+// Ray for pixel (i, j): entry point p, unit direction d, segment length L.
+__device__ __forceinline__ bool setup_ray(const View& v, const Scene& S, int i, int j, float p[3],
+                                          float d[3], float& L)
+{
+    const float ndc_x = ((2.0f * ((float)i + 0.5f)) / (float)S.W - 1.0f) * S.aspect;
+    const float ndc_y = 1.0f - (2.0f * ((float)j + 0.5f)) / (float)S.H;
+    float o[3];
+    if (v.persp != 0.0f) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = v.eye[a];
+            d[a] = fmaf(ndc_y, v.u[a], fmaf(ndc_x, v.r[a], v.f[a]));
+        }
+        const float nrm = sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
+        d[0] /= nrm;
+        d[1] /= nrm;
+        d[2] /= nrm;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = fmaf(ndc_y, v.u[a], fmaf(ndc_x, v.r[a], v.eye[a]));
+            d[a] = v.f[a];
+        }
+    }
+    float tin = -INFINITY, tout = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            if (o[a] < 0.0f || o[a] > S.ext[a]) return false;
+            continue;
+        }
+        const float ta = (0.0f - o[a]) / d[a];
+        const float tb = (S.ext[a] - o[a]) / d[a];
+        tin = fmaxf(tin, fminf(ta, tb));
+        tout = fminf(tout, fmaxf(ta, tb));
+    }
+    tin = fmaxf(tin, 0.0f);
+    if (!(tout > tin)) return false;
+    L = tout - tin;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = fmaf(tin, d[a], o[a]);
+    return true;
+}
+
+// n = max(1, ceil(L/step - 2^-10)): a segment that is a whole number of steps
+// up to the rounding of its clipped length gets no extra sliver of a step.
+__device__ __forceinline__ int step_count(float L, float step)
+{
+    return max(1, (int)ceilf(L / step - (1.0f / 1024.0f)));
+}
+
+__device__ __forceinline__ void pixel_of(const Scene& S, int nb, int& view, int& i, int& j)
+{
+    const int b = xcd_remap((int)blockIdx.x, nb);
+    const int per_view = S.tiles_x * S.tiles_y;
+    view = b / per_view;
+    const int t = b - view * per_view;
+    const int tx = t % S.tiles_x, ty = t / S.tiles_x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    i = tx * kTile + (w & 1) * 8 + (lane & 7);
+    j = ty * kTile + (w >> 1) * 8 + (lane >> 3);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4* __restrict__ out,
+            unsigned long long* __restrict__ samples)
+{
+    __shared__ float4 tf_s[256];
+    tf_s[threadIdx.x] = tf[threadIdx.x];
+    __syncthreads();
+    int view, i, j;
+    pixel_of(S, (int)gridDim.x, view, i, j);
+    const T* vol = static_cast<const T*>(S.data);
+    unsigned long long cnt = 0;
+    if (i < S.W && j < S.H) {
+        const View& v = V.v[view];
+        float p[3], d[3], L;
+        float4 res = make_float4(S.bg[0], S.bg[1], S.bg[2], S.bg[3]);
+        if (setup_ray(v, S, i, j, p, d, L)) {
+            const int n = step_count(L, S.step);
+            const float last = L - (float)(n - 1) * S.step;
+            float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+            for (int k = 0; k < n; ++k) {
+                const float len = (k < n - 1) ? S.step : last;
+                const float off = fmaf(0.5f, len, (float)k * S.step);
+                Sample sm;
+                sample<T>(S, vol, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]), sm);
+                const TfHit h = tf_lookup(tf_s, sm.s);
+                const float e = __expf(-(h.q.w * len));
+                const float ta = Tr * (1.0f - e);
+                cr = fmaf(ta, h.q.x, cr);
+                cg = fmaf(ta, h.q.y, cg);
+                cb = fmaf(ta, h.q.z, cb);
+                Tr = Tr * e;
+                ++cnt;
+                if (Tr < S.eps) break;
+            }
+            res = make_float4(fmaf(Tr, S.bg[0], cr), fmaf(Tr, S.bg[1], cg), fmaf(Tr, S.bg[2], cb),
+                              1.0f - Tr * (1.0f - S.bg[3]));
+        }
+        out[((int64_t)(S.view0 + view) * S.H + j) * S.W + i] = res;
+    }
+    if (samples) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(samples, cnt);
+    }
+}
+
+__device__ __forceinline__ void flush_tf(float* g, int k, float4 a0, float4 a1)
+{
+    atomicAdd(g + 4 * k + 0, a0.x);
+    atomicAdd(g + 4 * k + 1, a0.y);
+    atomicAdd(g + 4 * k + 2, a0.z);
+    atomicAdd(g + 4 * k + 3, a0.w);
+    atomicAdd(g + 4 * k + 4, a1.x);
+    atomicAdd(g + 4 * k + 5, a1.y);
+    atomicAdd(g + 4 * k + 6, a1.z);
+    atomicAdd(g + 4 * k + 7, a1.w);
+}
+
+__global__ void __launch_bounds__(kThreads)
+raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
+            const float4* __restrict__ fwd, const float4* __restrict__ grad, float* __restrict__ gvol,
+            float* __restrict__ gtf)
+{
+    __shared__ float4 tf_s[256];
+    __shared__ float gtf_s[256 * 4];
+    tf_s[threadIdx.x] = tf[threadIdx.x];
+    for (int q = threadIdx.x; q < 1024; q += kThreads) gtf_s[q] = 0.0f;
+    __syncthreads();
+    int view, i, j;
+    pixel_of(S, (int)gridDim.x, view, i, j);
+    const float* vol = static_cast<const float*>(S.data);
+    if (i < S.W && j < S.H) {
+        const View& v = V.v[view];
+        float p[3], d[3], L;
+        if (setup_ray(v, S, i, j, p, d, L)) {
+            const int64_t pix = ((int64_t)(S.view0 + view) * S.H + j) * S.W + i;
+            const float4 g = grad[pix];
+            const float4 I = fwd[pix];
+            const float ga = g.w * (1.0f - I.w);
+            const int n = step_count(L, S.step);
+            const float last = L - (float)(n - 1) * S.step;
+            float Tr = 1.0f, Pr = 0.0f, Pg = 0.0f, Pb = 0.0f;
+            int kc = -1;
+            float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+            for (int k = 0; k < n; ++k) {
+                const float len = (k < n - 1) ? S.step : last;
+                const float off = fmaf(0.5f, len, (float)k * S.step);
+                Sample sm;
+                sample<float>(S, vol, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]), sm);
+                const TfHit h = tf_lookup(tf_s, sm.s);
+                const float e = __expf(-(h.q.w * len));
+                const float ta = Tr * (1.0f - e);
+                Pr = fmaf(ta, h.q.x, Pr);
+                Pg = fmaf(ta, h.q.y, Pg);
+                Pb = fmaf(ta, h.q.z, Pb);
+                const float te = Tr * e;
+                // dI/drgb_i = T_i alpha_i;  dI/dsigma_i = len (T_{i+1} rgb_i - (I - P_i)) (+ alpha term)
+                const float gs = len * (g.x * (te * h.q.x - (I.x - Pr)) + g.y * (te * h.q.y - (I.y - Pg)) +
+                                        g.z * (te * h.q.z - (I.z - Pb)) + ga);
+                const float4 G = make_float4(g.x * ta, g.y * ta, g.z * ta, gs);
+                if (h.k != kc) {
+                    if (kc >= 0) flush_tf(gtf_s, kc, a0, a1);
+                    kc = h.k;
+                    a0 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    a1 = a0;
+                }
+                const float w0 = 1.0f - h.w;
+                a0.x = fmaf(w0, G.x, a0.x); a0.y = fmaf(w0, G.y, a0.y);
+                a0.z = fmaf(w0, G.z, a0.z); a0.w = fmaf(w0, G.w, a0.w);
+                a1.x = fmaf(h.w, G.x, a1.x); a1.y = fmaf(h.w, G.y, a1.y);
+                a1.z = fmaf(h.w, G.z, a1.z); a1.w = fmaf(h.w, G.w, a1.w);
+                if (sm.s >= 0.0f && sm.s <= 1.0f) {
+                    const float4 ka = tf_s[h.k], kb = tf_s[h.k + 1];
+                    const float ds = 255.0f * ((kb.x - ka.x) * G.x + (kb.y - ka.y) * G.y +
+                                               (kb.z - ka.z) * G.z + (kb.w - ka.w) * G.w);
+                    if (ds != 0.0f) {
+                        const float ax = 1.0f - sm.wx, ay = 1.0f - sm.wy, az = 1.0f - sm.wz;
+                        const float w[8] = {ax * ay * az, sm.wx * ay * az, ax * sm.wy * az, sm.wx * sm.wy * az,
+                                            ax * ay * sm.wz, sm.wx * ay * sm.wz, ax * sm.wy * sm.wz,
+                                            sm.wx * sm.wy * sm.wz};
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) atomicAdd(gvol + sm.off[t], w[t] * ds);
+                    }
+                }
+                Tr = te;
+                if (Tr < S.eps) break;
+            }
+            if (kc >= 0) flush_tf(gtf_s, kc, a0, a1);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 1024; q += kThreads) {
+        const float x = gtf_s[q];
+        if (x != 0.0f) atomicAdd(gtf + q, x);
+    }
+}
+
+int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams, int n_views,
+                const vr_render_opts* o, Scene& S)
+{
+    VR_REQUIRE(vol && d_tf && h_cams && o, VR_ERR_NULL, "raycast: NULL argument");
+    VR_REQUIRE(vol->data != nullptr, VR_ERR_NULL, "raycast: volume data is NULL");
+    VR_REQUIRE(vol->dtype == VR_U16_NORM || vol->dtype == VR_F32, VR_ERR_DTYPE,
+               "raycast: unknown dtype %d", vol->dtype);
+    VR_REQUIRE(vol->nx >= 1 && vol->ny >= 1 && vol->nz >= 1 && vol->nx < (1 << 30) &&
+                   vol->ny < (1 << 30) && vol->nz < (1 << 30) &&
+                   vol->nx * vol->ny * vol->nz <= (int64_t)0xFFFFFFFFu,
+               VR_ERR_DIMS, "raycast: volume dims %lld x %lld x %lld", (long long)vol->nx,
+               (long long)vol->ny, (long long)vol->nz);
+    for (int a = 0; a < 3; ++a)
+        VR_REQUIRE(std::isfinite(vol->spacing[a]) && vol->spacing[a] > 0.0, VR_ERR_RANGE,
+                   "raycast: spacing[%d] = %g", a, vol->spacing[a]);
+    VR_REQUIRE(n_views >= 1, VR_ERR_DIMS, "raycast: n_views %d", n_views);
+    VR_REQUIRE(o->width >= 1 && o->height >= 1 && o->width <= 32768 && o->height <= 32768,
+               VR_ERR_DIMS, "raycast: image %d x %d", o->width, o->height);
+    VR_REQUIRE(std::isfinite(o->step) && o->step > 0.0f, VR_ERR_RANGE, "raycast: step %g",
+               (double)o->step);
+    VR_REQUIRE(std::isfinite(o->ert_eps) && o->ert_eps >= 0.0f && o->ert_eps < 1.0f, VR_ERR_RANGE,
+               "raycast: ert_eps %g", (double)o->ert_eps);
+    {   // bound the samples per ray: the box diagonal over the step
+        double diag2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double e = (double)(a == 0 ? vol->nx : a == 1 ? vol->ny : vol->nz) * vol->spacing[a];
+            diag2 += e * e;
+        }
+        VR_REQUIRE(std::sqrt(diag2) / (double)o->step <= (double)(1 << 24), VR_ERR_RANGE,
+                   "raycast: step %g gives more than 2^24 samples per ray", (double)o->step);
+    }
+    for (int v = 0; v < n_views; ++v) {
+        const vr_camera& c = h_cams[v];
+        VR_REQUIRE(c.fov_y_deg == 0.0 ? (std::isfinite(c.ortho_half_h) && c.ortho_half_h > 0.0)
+                                      : (c.fov_y_deg > 0.0 && c.fov_y_deg < 180.0),
+                   VR_ERR_RANGE, "raycast: camera %d has fov %g / half height %g", v, c.fov_y_deg,
+                   c.ortho_half_h);
+    }
+    S.data = vol->data;
+    S.nx = (int)vol->nx;
+    S.ny = (int)vol->ny;
+    S.nz = (int)vol->nz;
+    const int64_t n[3] = {vol->nx, vol->ny, vol->nz};
+    for (int a = 0; a < 3; ++a) {
+        S.inv_sp[a] = (float)(1.0 / vol->spacing[a]);
+        S.ext[a] = (float)((double)n[a] * vol->spacing[a]);
+    }
+    S.W = o->width;
+    S.H = o->height;
+    S.aspect = (float)((double)o->width / (double)o->height);
+    S.step = o->step;
+    S.eps = o->ert_eps;
+    for (int c = 0; c < 4; ++c) S.bg[c] = o->bg[c];
+    S.tiles_x = (o->width + kTile - 1) / kTile;
+    S.tiles_y = (o->height + kTile - 1) / kTile;
+    return VR_OK;
+}
+
+int build_views(const vr_camera* cams, int count, Views& V)
+{
+    for (int k = 0; k < count; ++k) {
+        const vr_camera& c = cams[k];
+        double f[3], r[3], u[3];
+        for (int a = 0; a < 3; ++a) f[a] = c.target[a] - c.eye[a];
+        double lf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        VR_REQUIRE(lf > 0.0 && std::isfinite(lf), VR_ERR_RANGE, "raycast: camera eye == target");
+        for (int a = 0; a < 3; ++a) f[a] /= lf;
+        r[0] = f[1] * c.up[2] - f[2] * c.up[1];
+        r[1] = f[2] * c.up[0] - f[0] * c.up[2];
+        r[2] = f[0] * c.up[1] - f[1] * c.up[0];
+        double lr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        VR_REQUIRE(lr > 0.0 && std::isfinite(lr), VR_ERR_RANGE, "raycast: camera up is parallel to the view");
+        for (int a = 0; a < 3; ++a) r[a] /= lr;
+        u[0] = r[1] * f[2] - r[2] * f[1];
+        u[1] = r[2] * f[0] - r[0] * f[2];
+        u[2] = r[0] * f[1] - r[1] * f[0];
+        const bool persp = c.fov_y_deg > 0.0;
+        const double sc = persp ? std::tan(0.5 * c.fov_y_deg * M_PI / 180.0) : c.ortho_half_h;
+        View& v = V.v[k];
+        for (int a = 0; a < 3; ++a) {
+            v.eye[a] = (float)c.eye[a];
+            v.f[a] = (float)f[a];
+            v.r[a] = (float)(sc * r[a]);
+            v.u[a] = (float)(sc * u[a]);
+        }
+        v.persp = persp ? 1.0f : 0.0f;
+    }
+    return VR_OK;
+}
+
+}  // namespace
+
+extern "C" int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams,
+                          int n_views, const vr_render_opts* opts, float* d_rgba,
+                          uint64_t* d_samples, void* stream)
+{
+    vr::clear_error();
+    Scene S{};
+    int rc = build_scene(vol, d_tf, h_cams, n_views, opts, S);
+    if (rc) return rc;
+    VR_REQUIRE(d_rgba != nullptr, VR_ERR_NULL, "vr_raycast: d_rgba is NULL");
+    hipStream_t s = vr::as_stream(stream);
+    for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
+        const int nv = std::min(kMaxViews, n_views - v0);
+        Views V{};
+        rc = build_views(h_cams + v0, nv, V);
+        if (rc) return rc;
+        S.view0 = v0;
+        const int64_t blocks = (int64_t)S.tiles_x * S.tiles_y * nv;
+        VR_REQUIRE(blocks < (int64_t(1) << 31), VR_ERR_DIMS, "vr_raycast: too many tiles");
+        auto* out = reinterpret_cast<float4*>(d_rgba);
+        auto* cnt = reinterpret_cast<unsigned long long*>(d_samples);
+        if (vol->dtype == VR_U16_NORM)
+            raycast_fwd<uint16_t><<<(unsigned)blocks, kThreads, 0, s>>>(
+                V, S, reinterpret_cast<const float4*>(d_tf), out, cnt);
+        else
+            raycast_fwd<float><<<(unsigned)blocks, kThreads, 0, s>>>(
+                V, S, reinterpret_cast<const float4*>(d_tf), out, cnt);
+        rc = vr::check_launch("vr_raycast");
+        if (rc) return rc;
+    }
+    return VR_OK;
+}
+
+extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams,
+                                   int n_views, const vr_render_opts* opts,
+                                   const float* d_rgba_fwd, const float* d_grad_rgba,
+                                   float* d_grad_density, float* d_grad_tf, void* stream)
+{
+    vr::clear_error();
+    Scene S{};
+    int rc = build_scene(vol, d_tf, h_cams, n_views, opts, S);
+    if (rc) return rc;
+    VR_REQUIRE(vol->dtype == VR_F32, VR_ERR_DTYPE, "vr_raycast_backward: density must be VR_F32");
+    VR_REQUIRE(d_rgba_fwd && d_grad_rgba && d_grad_density && d_grad_tf, VR_ERR_NULL,
+               "vr_raycast_backward: NULL buffer");
+    hipStream_t s = vr::as_stream(stream);
+    for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
+        const int nv = std::min(kMaxViews, n_views - v0);
+        Views V{};
+        rc = build_views(h_cams + v0, nv, V);
+        if (rc) return rc;
+        S.view0 = v0;
+        const int64_t blocks = (int64_t)S.tiles_x * S.tiles_y * nv;
+        VR_REQUIRE(blocks < (int64_t(1) << 31), VR_ERR_DIMS, "vr_raycast_backward: too many tiles");
+        raycast_bwd<<<(unsigned)blocks, kThreads, 0, s>>>(
+            V, S, reinterpret_cast<const float4*>(d_tf), reinterpret_cast<const float4*>(d_rgba_fwd),
+            reinterpret_cast<const float4*>(d_grad_rgba), d_grad_density, d_grad_tf);
+        rc = vr::check_launch("vr_raycast_backward");
+        if (rc) return rc;
+    }
+    return VR_OK;
+}

@@ -1,0 +1,238 @@
+"""ctypes binding of libvr.so: the C ABI declared in include/vr.h, same names.
+
+Argument marshalling only: tensors are passed as device pointers, the stream
+is torch's current HIP stream unless one is given, and every step of the path
+runs in the library's HIP kernels.  If libvr.so is missing, or a call is made
+without a GPU, the binding raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvr.so")
+
+NBINS = 65536
+KEEP_WORDS = 2048
+MAX_LEVELS = 4
+MAX_VIEWS_PER_LAUNCH = 48
+RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
+U16_NORM, F32 = 0, 1
+ERRORS = {-1: "VR_ERR_NULL", -2: "VR_ERR_DIMS", -3: "VR_ERR_RANGE", -4: "VR_ERR_DTYPE",
+          -5: "VR_ERR_HIP", -6: "VR_ERR_UNSUPPORTED", -7: "VR_ERR_WORKSPACE"}
+
+
+class VrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class vr_volume(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("reserved", C.c_int32),
+                ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("spacing", C.c_double * 3)]
+
+
+class vr_camera(C.Structure):
+    _fields_ = [("eye", C.c_double * 3), ("target", C.c_double * 3), ("up", C.c_double * 3),
+                ("fov_y_deg", C.c_double), ("ortho_half_h", C.c_double)]
+
+
+class vr_render_opts(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("step", C.c_float),
+                ("ert_eps", C.c_float), ("bg", C.c_float * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if libvr.so has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2311_15038_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+        L.vr_histogram.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp]
+        L.vr_select_threshold.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+        L.vr_threshold_downsample.argtypes = [vp, i64, i64, i64, vp, i32, C.POINTER(vp), vp]
+        L.vr_pack_slicemap.argtypes = [vp, i64, i64, i64, i32, i32, i32, vp, vp]
+        L.vr_raycast.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
+                                 C.POINTER(vr_render_opts), vp, vp, vp]
+        L.vr_raycast_backward.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
+                                          C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
+        L.vr_last_error.restype = C.c_char_p
+        L.vr_version.restype = C.c_char_p
+        for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
+                     "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise VrError(rc, lib().vr_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None, numel=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+_U16 = (torch.uint16, torch.int16)
+
+
+def version() -> str:
+    return lib().vr_version().decode()
+
+
+# ------------------------------------------------------------------ reduction
+def vr_histogram(vol, z0=0, nz_range=None, out=None, stream=None):
+    """uint16 volume [nz][ny][nx] -> 65536 counters (int64 tensor holding the uint64 counts)."""
+    nz, ny, nx = vol.shape
+    if nz_range is None:
+        nz_range = nz - z0
+    if out is None:
+        out = torch.empty(NBINS, dtype=torch.int64, device=vol.device)
+    _check(lib().vr_histogram(_dev(vol, "vol", _U16), nx, ny, nz, z0, nz_range,
+                              _dev(out, "out", torch.int64, NBINS), _stream(stream)))
+    return out
+
+
+def vr_select_threshold(hist, hist_top=None, rule=RULE_VALLEY, param=32, result=None, keep_bits=None,
+                        stream=None):
+    """-> (result int32[4] = T, aux, b*, 0; keep_bits int32[2048] holding the uint32 mask)."""
+    dev = hist.device
+    if result is None:
+        result = torch.empty(4, dtype=torch.int32, device=dev)
+    if keep_bits is None:
+        keep_bits = torch.empty(KEEP_WORDS, dtype=torch.int32, device=dev)
+    top = None if hist_top is None else _dev(hist_top, "hist_top", torch.int64, NBINS)
+    _check(lib().vr_select_threshold(_dev(hist, "hist", torch.int64, NBINS), top, int(rule),
+                                     int(param), _dev(result, "result", torch.int32, 4),
+                                     _dev(keep_bits, "keep_bits", torch.int32, KEEP_WORDS),
+                                     _stream(stream)))
+    return result, keep_bits
+
+
+def level_shape(shape, k):
+    d = 1 << k
+    return tuple(-(-n // d) for n in shape)
+
+
+def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, stream=None):
+    """Filtered pyramid levels 1..n_levels (list of uint16 tensors)."""
+    nz, ny, nx = vol.shape
+    if levels is None:
+        levels = [torch.empty(level_shape((nz, ny, nx), k), dtype=torch.uint16, device=vol.device)
+                  for k in range(1, n_levels + 1)]
+    if len(levels) < n_levels:
+        raise ValueError("need one output tensor per level")
+    ptrs = (C.c_void_p * max(1, n_levels))()
+    for k in range(n_levels):
+        want = level_shape((nz, ny, nx), k + 1)
+        if tuple(levels[k].shape) != want:
+            raise ValueError(f"level {k + 1} has shape {tuple(levels[k].shape)}, expected {want}")
+        ptrs[k] = _dev(levels[k], f"levels[{k}]", _U16).value
+    kb = None if keep_bits is None else _dev(keep_bits, "keep_bits", torch.int32, KEEP_WORDS)
+    _check(lib().vr_threshold_downsample(_dev(vol, "vol", _U16), nx, ny, nz, kb, int(n_levels),
+                                         ptrs, _stream(stream)))
+    return levels
+
+
+def vr_pack_slicemap(level, tiles_x, tiles_y, out_bits=16, out=None, stream=None):
+    nz, ny, nx = level.shape
+    dt = torch.uint16 if out_bits == 16 else torch.uint8
+    if out is None:
+        out = torch.empty((tiles_y * ny, tiles_x * nx), dtype=dt, device=level.device)
+    _check(lib().vr_pack_slicemap(_dev(level, "level", _U16), nx, ny, nz, int(tiles_x),
+                                  int(tiles_y), int(out_bits),
+                                  _dev(out, "out", (dt, torch.int16) if out_bits == 16 else dt,
+                                       tiles_x * tiles_y * nx * ny),
+                                  _stream(stream)))
+    return out
+
+
+# ------------------------------------------------------------------ rendering
+def make_volume(data, spacing=(1.0, 1.0, 1.0)):
+    """vr_volume for a uint16 (normalised) or float32 tensor [nz][ny][nx]."""
+    if data.dtype in _U16:
+        dt = U16_NORM
+    elif data.dtype == torch.float32:
+        dt = F32
+    else:
+        raise TypeError(f"unsupported volume dtype {data.dtype}")
+    nz, ny, nx = data.shape
+    return vr_volume(_dev(data, "volume").value, dt, 0, nx, ny, nz,
+                     (C.c_double * 3)(*[float(s) for s in spacing]))
+
+
+def make_cameras(cams):
+    cams = np.asarray(cams, dtype=np.float64).reshape(-1, 11)
+    arr = (vr_camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k].eye[:] = [float(x) for x in c[0:3]]
+        arr[k].target[:] = [float(x) for x in c[3:6]]
+        arr[k].up[:] = [float(x) for x in c[6:9]]
+        arr[k].fov_y_deg = float(c[9])
+        arr[k].ortho_half_h = float(c[10])
+    return arr, len(cams)
+
+
+def make_opts(width, height, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0)):
+    return vr_render_opts(int(width), int(height), float(step), float(ert_eps),
+                          (C.c_float * 4)(*[float(b) for b in bg]))
+
+
+def vr_raycast(data, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
+               bg=(0.0, 0.0, 0.0, 0.0), out=None, samples=None, stream=None):
+    """RGBA frames [V][H][W][4] float32; `samples` (int64[1]) accumulates the sample count."""
+    vol = make_volume(data, spacing)
+    ca, nv = make_cameras(cams)
+    opts = make_opts(width, height, step, ert_eps, bg)
+    if out is None:
+        out = torch.empty((nv, height, width, 4), dtype=torch.float32, device=data.device)
+    sp = None if samples is None else _dev(samples, "samples", torch.int64, 1)
+    _check(lib().vr_raycast(C.byref(vol), _dev(tf, "tf", torch.float32, 1024), ca, nv,
+                            C.byref(opts), _dev(out, "out", torch.float32, nv * height * width * 4),
+                            sp, _stream(stream)))
+    return out
+
+
+def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba, grad_density,
+                        grad_tf, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
+                        bg=(0.0, 0.0, 0.0, 0.0), stream=None):
+    """Adds dLoss/dDensity and dLoss/dTF into grad_density / grad_tf (zero them first)."""
+    vol = make_volume(data, spacing)
+    ca, nv = make_cameras(cams)
+    opts = make_opts(width, height, step, ert_eps, bg)
+    n = nv * height * width * 4
+    _check(lib().vr_raycast_backward(
+        C.byref(vol), _dev(tf, "tf", torch.float32, 1024), ca, nv, C.byref(opts),
+        _dev(rgba_fwd, "rgba_fwd", torch.float32, n), _dev(grad_rgba, "grad_rgba", torch.float32, n),
+        _dev(grad_density, "grad_density", torch.float32, data.numel()),
+        _dev(grad_tf, "grad_tf", torch.float32, 1024), _stream(stream)))
+    return grad_density, grad_tf

@@ -1,0 +1,79 @@
+"""The C ABI library loads, exports every function include/vr.h declares, and
+rejects bad arguments before touching the device (host logic only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vr.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(vr_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_15038_amd import vr
+    if not os.path.exists(vr.LIB_PATH):
+        from paper_2311_15038_amd import build
+        build.build()
+    return vr.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["vr_histogram", "vr_select_threshold", "vr_threshold_downsample", "vr_pack_slicemap",
+              "vr_raycast", "vr_raycast_backward", "vr_last_error", "vr_version"]:
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_version_and_empty_error(lib):
+    assert lib.vr_version().decode().startswith("vr ")
+    assert lib.vr_last_error().decode() == ""
+
+
+def test_validation_happens_on_the_host(lib):
+    # NULL output, bad dims, bad ranges: rejected before any device work
+    assert lib.vr_histogram(None, 4, 4, 4, 0, 4, None, None) == -1
+    assert "d_hist" in lib.vr_last_error().decode()
+    assert lib.vr_histogram(C.c_void_p(16), 0, 4, 4, 0, 4, C.c_void_p(16), None) == -2
+    assert lib.vr_histogram(C.c_void_p(16), 4, 4, 4, 3, 2, C.c_void_p(16), None) == -3
+    assert lib.vr_select_threshold(C.c_void_p(16), None, 9, 0, C.c_void_p(16), C.c_void_p(16), None) == -3
+    assert lib.vr_select_threshold(C.c_void_p(16), None, 0, 0, C.c_void_p(16), C.c_void_p(16), None) == -3
+    ptrs = (C.c_void_p * 5)(*([16] * 5))
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 5, ptrs, None) == -3
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 0, ptrs, None) == -3
+    assert lib.vr_pack_slicemap(C.c_void_p(16), 4, 4, 10, 3, 3, 16, C.c_void_p(16), None) == -3
+    assert lib.vr_pack_slicemap(C.c_void_p(16), 4, 4, 9, 3, 3, 12, C.c_void_p(16), None) == -3
+
+
+def test_raycast_validation_on_the_host(lib):
+    from paper_2311_15038_amd import vr, synth
+    vol = vr.vr_volume(16, vr.U16_NORM, 0, 8, 8, 8, (C.c_double * 3)(1, 1, 1))
+    cams, nv = vr.make_cameras(synth.turntable_cameras(8, 8, 8, n_views=2))
+    ok = vr.make_opts(8, 8, 0.5)
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), None, None, None) == -1
+    bad = vr.make_opts(8, 8, -1.0)
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(bad), C.c_void_p(16), None, None) == -3
+    bad = vr.make_opts(0, 8, 0.5)
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(bad), C.c_void_p(16), None, None) == -2
+    vol.dtype = 7
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -4
+    vol.dtype = vr.U16_NORM
+    vol.spacing[1] = 0.0
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -3
+    vol.spacing[1] = 1.0
+    # the adjoint differentiates f32 grids only
+    assert lib.vr_raycast_backward(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16),
+                                   C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == -4

@@ -1,0 +1,130 @@
+"""GPU adjoint ray casting against an FP64 autograd reference and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import render as R
+from oracle import render_torch as RT
+from paper_2311_15038_amd import autograd as VA
+from paper_2311_15038_amd import synth
+from paper_2311_15038_amd import vr
+
+from gpu_util import banner, dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _smooth_volume(n, seed, lo=0.05, hi=0.45):
+    rng = np.random.default_rng(seed)
+    idx = np.indices((n, n, n)).astype(np.float64)
+    v = (0.5 + 0.5 * np.sin(idx[0] / 2.7 + 1.0) * np.cos(idx[1] / 3.3) * np.sin(idx[2] / 4.1 + 0.3))
+    v = lo + (hi - lo) * v + 0.02 * rng.random((n, n, n))
+    return v
+
+
+def _ref_grads(dens, tf, cams, W, H, step, target, bg):
+    d = torch.tensor(dens, dtype=torch.float64, requires_grad=True)
+    t = torch.tensor(tf, dtype=torch.float64, requires_grad=True)
+    img = RT.render(d, t, cams, W, H, step, bg=bg)
+    loss = ((img - torch.tensor(target)) ** 2).mean()
+    loss.backward()
+    return img.detach().numpy(), d.grad.numpy(), t.grad.numpy()
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0, 0.0), (0.25, 0.5, 0.125, 0.75)])
+def test_adjoint_matches_fp64_autograd(bg):
+    banner(f"backward 32^3 vs fp64 autograd bg={bg}")
+    n, W, H, step = 32, 24, 20, 0.5
+    dens = _smooth_volume(n, 1)
+    tf = synth.random_tf(2, sigma_max=0.3).astype(np.float64)
+    cams = np.concatenate([synth.turntable_cameras(n, n, n, n_views=3), synth.front_ortho_camera(n, n, n)])
+    target = np.random.default_rng(3).uniform(0, 1, size=(4, H, W, 4))
+    img_ref, gd_ref, gt_ref = _ref_grads(dens, tf, cams, W, H, step, target, bg)
+
+    d = torch.tensor(dens, dtype=torch.float32, device=dev(), requires_grad=True)
+    t = torch.tensor(tf, dtype=torch.float32, device=dev(), requires_grad=True)
+    img = VA.render(d, t, cams, W, H, step, ert_eps=0.0, bg=bg)
+    loss = ((img - torch.tensor(target, dtype=torch.float32, device=dev())) ** 2).mean()
+    loss.backward()
+    assert np.abs(img.detach().cpu().numpy() - img_ref).max() <= 2e-4
+    gd, gt = d.grad.cpu().numpy(), t.grad.cpu().numpy()
+    sd, st = np.abs(gd_ref).max(), np.abs(gt_ref).max()
+    assert sd > 0 and st > 0
+    assert np.abs(gd - gd_ref).max() <= 2e-3 * sd, np.abs(gd - gd_ref).max() / sd
+    assert np.abs(gt - gt_ref).max() <= 2e-3 * st, np.abs(gt - gt_ref).max() / st
+
+
+def test_adjoint_with_early_termination_close_to_full():
+    banner("backward with ERT")
+    n, W, H, step = 32, 24, 24, 0.5
+    dens = _smooth_volume(n, 4, 0.2, 0.9)
+    tf = synth.default_tf(sigma_scale=6.0).astype(np.float64)
+    cams = synth.turntable_cameras(n, n, n, n_views=2)
+    target = np.random.default_rng(5).uniform(0, 1, size=(2, H, W, 4))
+    _, gd_ref, gt_ref = _ref_grads(dens, tf, cams, W, H, step, target, (0, 0, 0, 0))
+    d = torch.tensor(dens, dtype=torch.float32, device=dev(), requires_grad=True)
+    t = torch.tensor(tf, dtype=torch.float32, device=dev(), requires_grad=True)
+    img = VA.render(d, t, cams, W, H, step)            # ERT at 2^-14
+    ((img - torch.tensor(target, dtype=torch.float32, device=dev())) ** 2).mean().backward()
+    gd, gt = d.grad.cpu().numpy(), t.grad.cpu().numpy()
+    assert np.abs(gd - gd_ref).max() <= 1e-2 * np.abs(gd_ref).max()
+    assert np.abs(gt - gt_ref).max() <= 1e-2 * np.abs(gt_ref).max()
+
+
+def test_adjoint_finite_differences():
+    """Central differences of the FP64 oracle (h = 1e-3) at 64 voxels and 16 TF entries.
+
+    The transfer function is the default piecewise-linear one (kinks only at
+    its anchors): with a table that kinks at every knot, h = 1e-3 straddles a
+    kink for a large share of the samples and central differences stop being
+    a reference (the exact FP64 gradient itself then fails the bound).
+    """
+    banner("backward vs finite differences")
+    n, W, H, step = 24, 32, 32, 0.5
+    dens = _smooth_volume(n, 6)
+    tf = synth.default_tf(sigma_scale=2.0).astype(np.float64)
+    cams = synth.turntable_cameras(n, n, n, n_views=2)
+    target = np.random.default_rng(8).uniform(0, 1, size=(2, H, W, 4))
+    d = torch.tensor(dens, dtype=torch.float32, device=dev(), requires_grad=True)
+    t = torch.tensor(tf, dtype=torch.float32, device=dev(), requires_grad=True)
+    img = VA.render(d, t, cams, W, H, step, ert_eps=0.0)
+    ((img - torch.tensor(target, dtype=torch.float32, device=dev())) ** 2).mean().backward()
+    gd, gt = d.grad.cpu().numpy(), t.grad.cpu().numpy()
+    d32 = d.detach().cpu().numpy().astype(np.float64)       # the grid the GPU saw
+    t32 = t.detach().cpu().numpy().astype(np.float64)
+
+    def loss(dd, tt):
+        im, _ = R.render(dd, (1, 1, 1), tt, cams, W, H, step, ert_eps=0.0)
+        return ((im - target) ** 2).mean()
+
+    h = 1e-3
+    rng = np.random.default_rng(9)
+    ok = 0
+    gmax = np.abs(gd).max()
+    for _ in range(64):
+        z, y, x = (int(v) for v in rng.integers(2, n - 2, size=3))
+        dp, dm = d32.copy(), d32.copy()
+        dp[z, y, x] += h
+        dm[z, y, x] -= h
+        fd = (loss(dp, t32) - loss(dm, t32)) / (2 * h)
+        ok += abs(gd[z, y, x] - fd) <= 1e-3 * gmax + 5e-2 * abs(fd)
+    assert ok >= 60, ok
+    tmax = np.abs(gt).max()
+    used = np.argwhere(np.abs(gt).sum(axis=1) > 0)[:, 0]
+    for _ in range(16):
+        k, c = int(rng.choice(used)), int(rng.integers(0, 4))
+        tp, tm = t32.copy(), t32.copy()
+        tp[k, c] += h
+        tm[k, c] -= h
+        fd = (loss(d32, tp) - loss(d32, tm)) / (2 * h)
+        assert abs(gt[k, c] - fd) <= 1e-3 * tmax + 1e-3 * abs(fd), (k, c, gt[k, c], fd)
+
+
+def test_adjoint_rejects_u16():
+    v = torch.zeros((4, 4, 4), dtype=torch.uint16, device=dev())
+    tf = torch.zeros((256, 4), dtype=torch.float32, device=dev())
+    cams = synth.turntable_cameras(4, 4, 4, n_views=1)
+    out = torch.zeros((1, 4, 4, 4), dtype=torch.float32, device=dev())
+    with pytest.raises(vr.VrError):
+        vr.vr_raycast_backward(v, tf, cams, 4, 4, 0.5, out, out, torch.zeros(64, device=dev()),
+                               torch.zeros(1024, device=dev()))
