@@ -1,0 +1,101 @@
+"""The preview pipeline for one volume: buffers plus the ordered library calls.
+
+One step, all on one stream with no host synchronisation:
+  histogram of the volume and of its first three slices (Section III-D),
+  threshold selection and keep mask on the device (Sections III-A, III-D),
+  thresholding fused with the box-filtered pyramid (Section II),
+  slicemap atlas of one level (Section III),
+  turntable frames ray cast from one level (Section III-C).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import synth, vr
+
+
+@dataclass
+class PreviewConfig:
+    n_levels: int = 4
+    atlas_level: int = 2            # level packed into the slicemap atlas
+    render_level: int = 1           # level the frames are rendered from
+    n_views: int = 36
+    width: int = 512
+    height: int = 512
+    step: float = 0.5               # world units of the rendered level (its voxel = 1)
+    rule: int = vr.RULE_VALLEY
+    rule_param: int = 32
+    top_slices: int = 3
+    fov_deg: float = 60.0
+    ortho: bool = False
+    ert_eps: float = 2.0 ** -14
+
+
+def atlas_tiles(nz: int):
+    """Smallest square-ish tile grid holding nz slices."""
+    tx = int(math.ceil(math.sqrt(nz)))
+    ty = int(math.ceil(nz / tx))
+    return tx, ty
+
+
+class PreviewPipeline:
+    def __init__(self, shape, cfg: PreviewConfig, tf: np.ndarray | None = None, device="cuda:0"):
+        self.shape = tuple(shape)
+        self.cfg = cfg
+        dev = torch.device(device)
+        self.device = dev
+        self.hist = torch.empty(vr.NBINS, dtype=torch.int64, device=dev)
+        self.hist_top = torch.empty(vr.NBINS, dtype=torch.int64, device=dev)
+        self.result = torch.empty(4, dtype=torch.int32, device=dev)
+        self.keep = torch.empty(vr.KEEP_WORDS, dtype=torch.int32, device=dev)
+        self.levels = [torch.empty(vr.level_shape(self.shape, k), dtype=torch.uint16, device=dev)
+                       for k in range(1, cfg.n_levels + 1)]
+        az, ay, ax = self.levels[cfg.atlas_level - 1].shape
+        self.tiles = atlas_tiles(az)
+        self.atlas = torch.empty((self.tiles[1] * ay, self.tiles[0] * ax), dtype=torch.uint16,
+                                 device=dev)
+        rz, ry, rx = self.levels[cfg.render_level - 1].shape
+        self.render_shape = (rz, ry, rx)
+        if cfg.ortho:
+            self.cams = synth.front_ortho_camera(rx, ry, rz)
+        else:
+            self.cams = synth.turntable_cameras(rx, ry, rz, n_views=cfg.n_views, fov_deg=cfg.fov_deg)
+        nv = len(self.cams)
+        self.frames = torch.empty((nv, cfg.height, cfg.width, 4), dtype=torch.float32, device=dev)
+        self.tf = torch.from_numpy(synth.default_tf() if tf is None else tf).to(dev)
+        self.samples = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    # the reduction half
+    def reduce(self, vol, stream=None):
+        c = self.cfg
+        vr.vr_histogram(vol, 0, None, self.hist, stream)
+        vr.vr_histogram(vol, 0, c.top_slices, self.hist_top, stream)
+        vr.vr_select_threshold(self.hist, self.hist_top, c.rule, c.rule_param, self.result,
+                               self.keep, stream)
+        vr.vr_threshold_downsample(vol, self.keep, c.n_levels, self.levels, stream)
+        vr.vr_pack_slicemap(self.levels[c.atlas_level - 1], self.tiles[0], self.tiles[1], 16,
+                            self.atlas, stream)
+
+    def render(self, stream=None, count=False):
+        c = self.cfg
+        vr.vr_raycast(self.levels[c.render_level - 1], self.tf, self.cams, c.width, c.height, c.step,
+                      ert_eps=c.ert_eps, out=self.frames, samples=self.samples if count else None,
+                      stream=stream)
+
+    def step(self, vol, stream=None, count=False):
+        self.reduce(vol, stream)
+        self.render(stream, count)
+
+    def reduction_bytes(self) -> int:
+        """Algorithmic HBM bytes of the reduction half: every input read once, every output written once."""
+        nz, ny, nx = self.shape
+        vol = nx * ny * nz * 2
+        top = nx * ny * min(self.cfg.top_slices, nz) * 2
+        lv = sum(l.numel() * 2 for l in self.levels)
+        at_in = self.levels[self.cfg.atlas_level - 1].numel() * 2
+        at_out = self.atlas.numel() * 2
+        return vol + top + vol + lv + at_in + at_out
