@@ -65,6 +65,12 @@ enum {
 /* volume element types */
 enum { VR_U16_NORM = 0, VR_F32 = 1 };
 
+/* volume layouts for rendering */
+enum {
+    VR_LAYOUT_LINEAR = 0,      /* [nz][ny][nx], x fastest */
+    VR_LAYOUT_BRICK4 = 1       /* 4x4x4 bricks, see vr_brick_volume */
+};
+
 /*
  * Histogram of grey values (Section III-D: the volume histogram, and the
  * histogram of the first three slices that holds the signature of air and
@@ -85,7 +91,7 @@ int vr_histogram(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
  * in the top-slice histogram (Section III-D).  The keep mask is
  *   keep[b] = (b >= T) && (d_hist_top == NULL || d_hist_top[b] == 0).
  * T is chosen by `rule`:
- *   VR_RULE_VALLEY: S = d_hist box-smoothed with radius `param` (1..4096);
+ *   VR_RULE_VALLEY: S = d_hist box-smoothed with radius `param` (1..1023);
  *     p = first argmax of S; T = start of the plateau of the first bin above
  *     p where 2*S[b] <= S[p] and S[b+1] > S[b]; 65535 if none.
  *   VR_RULE_OTSU: Algorithm 1 on the histogram with bins of width 2^param
@@ -97,7 +103,7 @@ int vr_histogram(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
  *   VR_RULE_NONE: T = 0.
  *   d_result: 4 uint32 written: [0] = T (16-bit grey value), [1] = the air
  *     peak p (valley) or the iteration count (ITS), [2] = b* (valley), [3] = 0.
- *   d_keep_bits: 2048 uint32, overwritten.
+ *   d_keep_bits: 2048 uint32, overwritten (also used as scratch by the call).
  * Errors: VR_ERR_NULL, VR_ERR_RANGE (rule or param), VR_ERR_HIP.
  */
 int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_hist_top, int rule, int param,
@@ -134,13 +140,36 @@ int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64
 int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz, int tiles_x,
                      int tiles_y, int out_bits, void* d_atlas, void* stream);
 
+/*
+ * Render layout (not in the paper; a memory layout for the ray caster): the
+ * volume as 4 x 4 x 4-voxel bricks, brick (bx, by, bz) at element
+ * ((bz*nby + by)*nbx + bx)*64 with nbx = ceil(nx / 4) (and so on), voxel (x, y, z) at
+ * ((z&3)*16 + (y&3)*4 + (x&3)) inside it (voxels past the volume's end are 0).
+ * Optional occupancy (one byte per brick): non-zero iff a non-zero voxel is
+ * one of the 8 taps of a trilinear fetch whose base (floor, clamped) tap lies
+ * in that brick.  The ray caster passes over samples of unoccupied bricks
+ * when the transfer function's first entry has zero extinction: such samples
+ * have density 0 and change neither colour nor transmittance, so the result
+ * is bit-identical.
+ *   d_src: [nz][ny][nx] of u16 (dtype VR_U16_NORM) or f32 (VR_F32).
+ *   d_bricked: vr_brick_count(...) * 64 elements, overwritten.
+ *   d_occupancy: NULL or vr_brick_count(...) bytes, overwritten.
+ * Errors: VR_ERR_NULL, VR_ERR_DTYPE, VR_ERR_DIMS, VR_ERR_HIP.
+ */
+int vr_brick_volume(const void* d_src, int dtype, int64_t nx, int64_t ny, int64_t nz,
+                    void* d_bricked, uint8_t* d_occupancy, void* stream);
+
+/* Number of 4x4x4 bricks of an nx x ny x nz volume (host only). */
+int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks);
+
 /* A volume to render. dtype VR_U16_NORM (value / 65535) or VR_F32 (value). */
 typedef struct {
-    const void* data;          /* device pointer, [nz][ny][nx] */
+    const void* data;          /* device pointer in `layout` */
     int32_t dtype;
-    int32_t reserved;
+    int32_t layout;            /* VR_LAYOUT_LINEAR or VR_LAYOUT_BRICK4 */
     int64_t nx, ny, nz;
     double spacing[3];         /* world units per voxel along x, y, z (> 0) */
+    const uint8_t* occupancy;  /* NULL, or the brick occupancy (VR_LAYOUT_BRICK4 only) */
 } vr_volume;
 
 /* A pinhole (fov_y_deg > 0) or orthographic (fov_y_deg == 0) camera. */
@@ -178,7 +207,10 @@ typedef struct {
  *     added (the caller zeroes it).
  *   h_cams: n_views cameras (any n_views >= 1; views are launched in groups
  *     of VR_MAX_VIEWS_PER_LAUNCH).
- * All arithmetic is FP32; per-ray results do not depend on the launch shape.
+ * All arithmetic is FP32; per-ray results do not depend on the launch shape,
+ * the layout or the occupancy (bit-identical).  With vol->occupancy set and
+ * tf[0].sigma == 0, samples whose eight taps are all zero are passed over
+ * without being evaluated (they are still counted in d_samples).
  * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (step, fov, spacing),
  * VR_ERR_DTYPE, VR_ERR_HIP.
  */
@@ -200,7 +232,10 @@ int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams,
  * then through the transfer-function interpolation to the two knots, and
  * through the trilinear weights to the eight taps (f32 atomics; the
  * summation order is not deterministic).
- * Errors: as vr_raycast, VR_ERR_DTYPE unless vol->dtype == VR_F32.
+ * The density must be VR_F32 in VR_LAYOUT_LINEAR (VR_ERR_DTYPE,
+ * VR_ERR_UNSUPPORTED otherwise); vol->occupancy is ignored (samples of empty
+ * bricks leave the colour unchanged but do carry gradient).
+ * Errors: as vr_raycast.
  */
 int vr_raycast_backward(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams,
                         int n_views, const vr_render_opts* opts, const float* d_rgba_fwd,

@@ -34,7 +34,9 @@ struct Views {
 
 struct Scene {
     const void* data;
+    const uint8_t* occ;     // brick occupancy or NULL
     int nx, ny, nz;
+    int nbx, nby, nbz;      // 4^3 bricks per axis
     float inv_sp[3];
     float ext[3];
     int W, H;
@@ -68,28 +70,61 @@ __device__ __forceinline__ float voxel<float>(const float* p, uint32_t i) { retu
 
 __device__ __forceinline__ float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
 
-template <typename T>
-__device__ __forceinline__ void sample(const Scene& S, const T* __restrict__ vol, float px, float py,
-                                       float pz, Sample& sm)
+// Offsets of the eight taps (x fastest: 000 100 010 110 001 101 011 111) of
+// the clamped tap corners, in the linear or the 4^3-brick layout.
+template <int LAYOUT>
+__device__ __forceinline__ void tap_offsets(const Scene& S, uint32_t x0, uint32_t x1, uint32_t y0,
+                                            uint32_t y1, uint32_t z0, uint32_t z1, uint32_t off[8])
 {
+    uint32_t ax0, ax1, ay0, ay1, az0, az1;
+    if (LAYOUT == VR_LAYOUT_LINEAR) {
+        const uint32_t nx = (uint32_t)S.nx, nxy = (uint32_t)S.nx * (uint32_t)S.ny;
+        ax0 = x0; ax1 = x1;
+        ay0 = y0 * nx; ay1 = y1 * nx;
+        az0 = z0 * nxy; az1 = z1 * nxy;
+    } else {
+        const uint32_t row = (uint32_t)S.nbx << 6, slab = row * (uint32_t)S.nby;
+        ax0 = ((x0 >> 2) << 6) | (x0 & 3u); ax1 = ((x1 >> 2) << 6) | (x1 & 3u);
+        ay0 = (y0 >> 2) * row + ((y0 & 3u) << 2); ay1 = (y1 >> 2) * row + ((y1 & 3u) << 2);
+        az0 = (z0 >> 2) * slab + ((z0 & 3u) << 4); az1 = (z1 >> 2) * slab + ((z1 & 3u) << 4);
+    }
+    off[0] = az0 + ay0 + ax0; off[1] = az0 + ay0 + ax1;
+    off[2] = az0 + ay1 + ax0; off[3] = az0 + ay1 + ax1;
+    off[4] = az1 + ay0 + ax0; off[5] = az1 + ay0 + ax1;
+    off[6] = az1 + ay1 + ax0; off[7] = az1 + ay1 + ax1;
+}
+
+// Base tap corner (clamped) and trilinear weights of the point p.
+struct Cell {
+    uint32_t x0, x1, y0, y1, z0, z1;
+    float wx, wy, wz;
+};
+
+__device__ __forceinline__ Cell cell_at(const Scene& S, float px, float py, float pz)
+{
+    Cell c;
     const float ux = fmaf(px, S.inv_sp[0], -0.5f);
     const float uy = fmaf(py, S.inv_sp[1], -0.5f);
     const float uz = fmaf(pz, S.inv_sp[2], -0.5f);
     const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
-    sm.wx = ux - fx;
-    sm.wy = uy - fy;
-    sm.wz = uz - fz;
+    c.wx = ux - fx;
+    c.wy = uy - fy;
+    c.wz = uz - fz;
     const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    const uint32_t x0 = (uint32_t)min(max(ix, 0), S.nx - 1), x1 = (uint32_t)min(max(ix + 1, 0), S.nx - 1);
-    const uint32_t y0 = (uint32_t)min(max(iy, 0), S.ny - 1), y1 = (uint32_t)min(max(iy + 1, 0), S.ny - 1);
-    const uint32_t z0 = (uint32_t)min(max(iz, 0), S.nz - 1), z1 = (uint32_t)min(max(iz + 1, 0), S.nz - 1);
-    const uint32_t nx = (uint32_t)S.nx, ny = (uint32_t)S.ny;
-    const uint32_t r00 = (z0 * ny + y0) * nx, r10 = (z0 * ny + y1) * nx;
-    const uint32_t r01 = (z1 * ny + y0) * nx, r11 = (z1 * ny + y1) * nx;
-    sm.off[0] = r00 + x0; sm.off[1] = r00 + x1;
-    sm.off[2] = r10 + x0; sm.off[3] = r10 + x1;
-    sm.off[4] = r01 + x0; sm.off[5] = r01 + x1;
-    sm.off[6] = r11 + x0; sm.off[7] = r11 + x1;
+    c.x0 = (uint32_t)min(max(ix, 0), S.nx - 1); c.x1 = (uint32_t)min(max(ix + 1, 0), S.nx - 1);
+    c.y0 = (uint32_t)min(max(iy, 0), S.ny - 1); c.y1 = (uint32_t)min(max(iy + 1, 0), S.ny - 1);
+    c.z0 = (uint32_t)min(max(iz, 0), S.nz - 1); c.z1 = (uint32_t)min(max(iz + 1, 0), S.nz - 1);
+    return c;
+}
+
+template <typename T, int LAYOUT>
+__device__ __forceinline__ void sample(const Scene& S, const T* __restrict__ vol, const Cell& c,
+                                       Sample& sm)
+{
+    sm.wx = c.wx;
+    sm.wy = c.wy;
+    sm.wz = c.wz;
+    tap_offsets<LAYOUT>(S, c.x0, c.x1, c.y0, c.y1, c.z0, c.z1, sm.off);
     float v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = voxel<T>(vol, sm.off[t]);
@@ -180,7 +215,31 @@ __device__ __forceinline__ void pixel_of(const Scene& S, int nb, int& view, int&
     j = ty * kTile + (w >> 1) * 8 + (lane >> 3);
 }
 
-template <typename T>
+// Index of the first sample past the base-tap region of an empty brick: the
+// ray leaves brick (bx, by, bz) of the base tap where u = u0 + s g crosses a
+// multiple of 4 (the volume's first and last bricks extend to infinity, since
+// taps are clamped).  Samples with offset below the exit minus a margin are in
+// the brick; the sample at the returned index is checked again.
+__device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const float g[3],
+                                       const Cell& c, int k, int n)
+{
+    const uint32_t bi[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
+    const int nb[3] = {S.nbx, S.nby, S.nbz};
+    float s_exit = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (g[a] > 0.0f && (int)bi[a] < nb[a] - 1)
+            s_exit = fminf(s_exit, ((float)(4u * (bi[a] + 1u)) - u0[a]) / g[a]);
+        else if (g[a] < 0.0f && bi[a] > 0u)
+            s_exit = fminf(s_exit, ((float)(4u * bi[a]) - u0[a]) / g[a]);
+    }
+    const float lim = (s_exit - S.step * (1.0f / 256.0f) - 0.5f * S.step) / S.step;
+    int next = n;
+    if (lim < (float)n) next = (int)ceilf(lim);
+    return min(max(next, k + 1), n);
+}
+
+template <typename T, int LAYOUT>
 __global__ void __launch_bounds__(kThreads)
 raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4* __restrict__ out,
             unsigned long long* __restrict__ samples)
@@ -188,6 +247,9 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
     __shared__ float4 tf_s[256];
     tf_s[threadIdx.x] = tf[threadIdx.x];
     __syncthreads();
+    // empty bricks may be passed over only if density 0 has zero extinction
+    const bool skip = S.occ != nullptr && tf_s[0].w == 0.0f && isfinite(tf_s[0].x) &&
+                      isfinite(tf_s[0].y) && isfinite(tf_s[0].z);
     int view, i, j;
     pixel_of(S, (int)gridDim.x, view, i, j);
     const T* vol = static_cast<const T*>(S.data);
@@ -199,12 +261,26 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
         if (setup_ray(v, S, i, j, p, d, L)) {
             const int n = step_count(L, S.step);
             const float last = L - (float)(n - 1) * S.step;
+            float u0[3], g[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u0[a] = fmaf(p[a], S.inv_sp[a], -0.5f);
+                g[a] = d[a] * S.inv_sp[a];
+            }
             float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-            for (int k = 0; k < n; ++k) {
+            int k = 0;
+            while (k < n) {
                 const float len = (k < n - 1) ? S.step : last;
                 const float off = fmaf(0.5f, len, (float)k * S.step);
+                const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
+                if (skip && S.occ[((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2)] == 0) {
+                    const int next = skip_to(S, u0, g, c, k, n);
+                    cnt += (unsigned long long)(next - k);
+                    k = next;
+                    continue;
+                }
                 Sample sm;
-                sample<T>(S, vol, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]), sm);
+                sample<T, LAYOUT>(S, vol, c, sm);
                 const TfHit h = tf_lookup(tf_s, sm.s);
                 const float e = __expf(-(h.q.w * len));
                 const float ta = Tr * (1.0f - e);
@@ -213,6 +289,7 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
                 cb = fmaf(ta, h.q.z, cb);
                 Tr = Tr * e;
                 ++cnt;
+                ++k;
                 if (Tr < S.eps) break;
             }
             res = make_float4(fmaf(Tr, S.bg[0], cr), fmaf(Tr, S.bg[1], cg), fmaf(Tr, S.bg[2], cb),
@@ -239,6 +316,7 @@ __device__ __forceinline__ void flush_tf(float* g, int k, float4 a0, float4 a1)
     atomicAdd(g + 4 * k + 7, a1.w);
 }
 
+template <int LAYOUT>
 __global__ void __launch_bounds__(kThreads)
 raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
             const float4* __restrict__ fwd, const float4* __restrict__ grad, float* __restrict__ gvol,
@@ -269,7 +347,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                 const float len = (k < n - 1) ? S.step : last;
                 const float off = fmaf(0.5f, len, (float)k * S.step);
                 Sample sm;
-                sample<float>(S, vol, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]), sm);
+                sample<float, LAYOUT>(S, vol, cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2])), sm);
                 const TfHit h = tf_lookup(tf_s, sm.s);
                 const float e = __expf(-(h.q.w * len));
                 const float ta = Tr * (1.0f - e);
@@ -325,11 +403,17 @@ int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams
     VR_REQUIRE(vol->data != nullptr, VR_ERR_NULL, "raycast: volume data is NULL");
     VR_REQUIRE(vol->dtype == VR_U16_NORM || vol->dtype == VR_F32, VR_ERR_DTYPE,
                "raycast: unknown dtype %d", vol->dtype);
+    VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4, VR_ERR_RANGE,
+               "raycast: unknown layout %d", vol->layout);
     VR_REQUIRE(vol->nx >= 1 && vol->ny >= 1 && vol->nz >= 1 && vol->nx < (1 << 30) &&
-                   vol->ny < (1 << 30) && vol->nz < (1 << 30) &&
-                   vol->nx * vol->ny * vol->nz <= (int64_t)0xFFFFFFFFu,
+                   vol->ny < (1 << 30) && vol->nz < (1 << 30),
                VR_ERR_DIMS, "raycast: volume dims %lld x %lld x %lld", (long long)vol->nx,
                (long long)vol->ny, (long long)vol->nz);
+    const int64_t nb[3] = {(vol->nx + 3) / 4, (vol->ny + 3) / 4, (vol->nz + 3) / 4};
+    const int64_t elems = vol->layout == VR_LAYOUT_BRICK4 ? nb[0] * nb[1] * nb[2] * 64
+                                                          : vol->nx * vol->ny * vol->nz;
+    VR_REQUIRE(elems <= (int64_t)0xFFFFFFFFu, VR_ERR_DIMS,
+               "raycast: volume of %lld elements exceeds 32-bit offsets", (long long)elems);
     for (int a = 0; a < 3; ++a)
         VR_REQUIRE(std::isfinite(vol->spacing[a]) && vol->spacing[a] > 0.0, VR_ERR_RANGE,
                    "raycast: spacing[%d] = %g", a, vol->spacing[a]);
@@ -357,6 +441,10 @@ int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams
                    c.ortho_half_h);
     }
     S.data = vol->data;
+    S.occ = vol->occupancy;
+    S.nbx = (int)nb[0];
+    S.nby = (int)nb[1];
+    S.nbz = (int)nb[2];
     S.nx = (int)vol->nx;
     S.ny = (int)vol->ny;
     S.nz = (int)vol->nz;
@@ -430,12 +518,15 @@ extern "C" int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_came
         VR_REQUIRE(blocks < (int64_t(1) << 31), VR_ERR_DIMS, "vr_raycast: too many tiles");
         auto* out = reinterpret_cast<float4*>(d_rgba);
         auto* cnt = reinterpret_cast<unsigned long long*>(d_samples);
-        if (vol->dtype == VR_U16_NORM)
-            raycast_fwd<uint16_t><<<(unsigned)blocks, kThreads, 0, s>>>(
-                V, S, reinterpret_cast<const float4*>(d_tf), out, cnt);
-        else
-            raycast_fwd<float><<<(unsigned)blocks, kThreads, 0, s>>>(
-                V, S, reinterpret_cast<const float4*>(d_tf), out, cnt);
+        const auto* tf = reinterpret_cast<const float4*>(d_tf);
+        const bool brick = vol->layout == VR_LAYOUT_BRICK4;
+        if (vol->dtype == VR_U16_NORM) {
+            if (brick) raycast_fwd<uint16_t, VR_LAYOUT_BRICK4><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+            else raycast_fwd<uint16_t, VR_LAYOUT_LINEAR><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+        } else {
+            if (brick) raycast_fwd<float, VR_LAYOUT_BRICK4><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+            else raycast_fwd<float, VR_LAYOUT_LINEAR><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+        }
         rc = vr::check_launch("vr_raycast");
         if (rc) return rc;
     }
@@ -452,6 +543,9 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
     int rc = build_scene(vol, d_tf, h_cams, n_views, opts, S);
     if (rc) return rc;
     VR_REQUIRE(vol->dtype == VR_F32, VR_ERR_DTYPE, "vr_raycast_backward: density must be VR_F32");
+    VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR, VR_ERR_UNSUPPORTED,
+               "vr_raycast_backward: the density gradient is produced for the linear layout only");
+    S.occ = nullptr;   // passing over empty bricks is exact for colours, not for gradients
     VR_REQUIRE(d_rgba_fwd && d_grad_rgba && d_grad_density && d_grad_tf, VR_ERR_NULL,
                "vr_raycast_backward: NULL buffer");
     hipStream_t s = vr::as_stream(stream);
@@ -463,7 +557,7 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
         S.view0 = v0;
         const int64_t blocks = (int64_t)S.tiles_x * S.tiles_y * nv;
         VR_REQUIRE(blocks < (int64_t(1) << 31), VR_ERR_DIMS, "vr_raycast_backward: too many tiles");
-        raycast_bwd<<<(unsigned)blocks, kThreads, 0, s>>>(
+        raycast_bwd<VR_LAYOUT_LINEAR><<<(unsigned)blocks, kThreads, 0, s>>>(
             V, S, reinterpret_cast<const float4*>(d_tf), reinterpret_cast<const float4*>(d_rgba_fwd),
             reinterpret_cast<const float4*>(d_grad_rgba), d_grad_density, d_grad_tf);
         rc = vr::check_launch("vr_raycast_backward");

@@ -1,328 +1,386 @@
 // Threshold selection and keep mask on the device (Sections III-A and III-D).
 //
-// One workgroup of 1024 threads; thread t owns a contiguous run of bins.  The
-// valley rule works on a box-smoothed copy of the 65536-bin histogram that is
-// recomputed by sliding windows (never materialised); Otsu (Algorithm 1) and
-// ITS (Algorithm 2) work on bins of width 2^shift, summed on the fly from the
-// fine histogram.  Floating point that decides a threshold uses IEEE FP64
-// operations written out one by one (no contraction), in the order given
-// alongside each rule, so the integer result is reproducible on any IEEE FP64
-// machine that evaluates the same expressions.
+// Three launches on the caller's stream.  The histogram is cut into chunks of
+// 1024 bins; a chunk workgroup (one bin per thread) loads its bins plus a halo
+// with coalesced reads and works from a block scan in LDS.
+//   1. per chunk: the chunk's maximum of the smoothed histogram (valley), or
+//      its count and grey-value sum (Otsu, ITS);
+//   2. per chunk: valley candidates against the global peak, or the chunk's
+//      best Otsu threshold;
+//   3. one workgroup: combines the chunks (runs the ITS iteration), writes the
+//      result and the keep mask.
+// The caller's keep-mask buffer (8 KiB) carries the per-chunk records between
+// the launches and is overwritten with the mask at the end, so nothing is
+// allocated.  Floating point that decides a threshold uses IEEE FP64
+// operations written out one by one, in the order stated for each rule.
 #include "common.h"
 
 namespace {
 
-constexpr int kT = 1024;
+constexpr int kT = 1024;                  // threads = bins per chunk
 constexpr int kB = VR_NBINS;
+constexpr int kMaxChunks = kB / kT;       // 64
+constexpr int kMaxRadius = kT - 1;
+constexpr int kHalo = kT + 2 * kMaxRadius + 2;   // smoothed-sum window of a chunk
 
-struct Red {
-    uint64_t u[kT];
-    double d[kT];
-    int i[kT];
+struct ValleyChunk {      // launch 1 (valley)
+    uint64_t smax;
+    uint32_t arg;
+    uint32_t pad;
 };
-
-// Block reduction of (key, index): larger key wins, ties -> smaller index.
-// Returns the winner's (key, index) to every thread.
-__device__ void reduce_max_u64(Red& r, uint64_t key, int idx, uint64_t& okey, int& oidx)
-{
-    const int t = threadIdx.x;
-    __syncthreads();
-    r.u[t] = key;
-    r.i[t] = idx;
-    __syncthreads();
-    for (int s = kT / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            uint64_t a = r.u[t], b = r.u[t + s];
-            int ia = r.i[t], ib = r.i[t + s];
-            if (b > a || (b == a && ib < ia)) {
-                r.u[t] = b;
-                r.i[t] = ib;
-            }
-        }
-        __syncthreads();
-    }
-    okey = r.u[0];
-    oidx = r.i[0];
-}
-
-__device__ void reduce_max_f64(Red& r, double key, int idx, double& okey, int& oidx)
-{
-    const int t = threadIdx.x;
-    __syncthreads();
-    r.d[t] = key;
-    r.i[t] = idx;
-    __syncthreads();
-    for (int s = kT / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            double a = r.d[t], b = r.d[t + s];
-            int ia = r.i[t], ib = r.i[t + s];
-            if (b > a || (b == a && ib < ia)) {
-                r.d[t] = b;
-                r.i[t] = ib;
-            }
-        }
-        __syncthreads();
-    }
-    okey = r.d[0];
-    oidx = r.i[0];
-}
-
-// min (or max with sign flip by the caller) of an int over the block
-__device__ int reduce_min_i(Red& r, int v)
-{
-    const int t = threadIdx.x;
-    __syncthreads();
-    r.i[t] = v;
-    __syncthreads();
-    for (int s = kT / 2; s > 0; s >>= 1) {
-        if (t < s && r.i[t + s] < r.i[t]) r.i[t] = r.i[t + s];
-        __syncthreads();
-    }
-    return r.i[0];
-}
-
-// Exclusive block scan of two u64 values; also returns the totals.
-__device__ void scan2(Red& r, uint64_t a, uint64_t b, uint64_t& ea, uint64_t& eb, uint64_t& ta,
-                      uint64_t& tb)
-{
-    __shared__ uint64_t sb[kT];
-    const int t = threadIdx.x;
-    __syncthreads();
-    r.u[t] = a;
-    sb[t] = b;
-    __syncthreads();
-    for (int off = 1; off < kT; off <<= 1) {
-        uint64_t xa = t >= off ? r.u[t - off] : 0, xb = t >= off ? sb[t - off] : 0;
-        __syncthreads();
-        r.u[t] += xa;
-        sb[t] += xb;
-        __syncthreads();
-    }
-    ta = r.u[kT - 1];
-    tb = sb[kT - 1];
-    ea = r.u[t] - a;
-    eb = sb[t] - b;
-    __syncthreads();
-}
+struct ValleyCand {       // launch 2 (valley)
+    int32_t cand;         // first qualifying bin, or kB
+    int32_t chg_below;    // last change point below cand (>= p), or -1
+    int32_t chg_all;      // last change point in the chunk (>= p), or -1
+    int32_t pad;
+};
+struct SumChunk {         // launch 1 (Otsu, ITS)
+    uint64_t n, s;
+};
+struct OtsuChunk {        // launch 2 (Otsu)
+    double sigma;
+    int32_t T;
+    int32_t pad;
+};
+struct ItsChunk {         // launch 1 extra (ITS): occupied range of the chunk
+    int32_t lo, hi;
+};
+// layout of the 8 KiB scratch: [0, 1024) launch-1 records, [1024, 2048) launch-2 records,
+// [2048, 2560) ITS ranges
+static_assert(sizeof(ValleyChunk) * kMaxChunks <= 1024, "scratch");
+static_assert(sizeof(SumChunk) * kMaxChunks <= 1024, "scratch");
+static_assert(sizeof(ValleyCand) * kMaxChunks <= 1024, "scratch");
+static_assert(sizeof(OtsuChunk) * kMaxChunks <= 1024, "scratch");
 
 __device__ __forceinline__ uint64_t hv(const uint64_t* H, int b) { return (b >= 0 && b < kB) ? H[b] : 0; }
 
-__device__ uint64_t window(const uint64_t* H, int b, int r)
-{
-    uint64_t s = 0;
-    for (int k = b - r; k <= b + r; ++k) s += hv(H, k);
-    return s;
-}
-
-// ---------------------------------------------------------------- valley
-// p = first argmax of S; b* = first b > p with 2 S[b] <= S[p] and S[b+1] > S[b];
-// T = first bin of the plateau of S ending at b*; 65535 if there is no b*.
-__device__ void valley(Red& red, const uint64_t* H, int r, uint32_t* out)
-{
-    __shared__ uint64_t s_bstar_val;
-    const int t = threadIdx.x;
-    const int per = kB / kT, b0 = t * per;
-
-    uint64_t S = window(H, b0, r), best = S;
-    int bi = b0;
-    for (int j = 1; j < per; ++j) {
-        const int b = b0 + j;
-        S = S + hv(H, b + r) - hv(H, b - r - 1);
-        if (S > best) { best = S, bi = b; }
-    }
-    uint64_t Sp;
-    int p;
-    reduce_max_u64(red, best, bi, Sp, p);
-
-    // first b > p past half height where S rises
-    int cand = kB;
-    S = window(H, b0, r);
-    for (int j = 0; j < per && b0 + j < kB - 1; ++j) {
-        const int b = b0 + j;
-        const uint64_t Sn = S + hv(H, b + 1 + r) - hv(H, b - r);
-        if (b > p && 2 * S <= Sp && Sn > S && cand == kB) cand = b;
-        S = Sn;
-    }
-    const int bstar = reduce_min_i(red, cand);
-    if (bstar >= kB) {
-        if (t == 0) { out[0] = kB - 1; out[1] = (uint32_t)p; out[2] = 0xFFFFFFFFu; out[3] = 0; }
-        return;
-    }
-    if (t == 0) s_bstar_val = window(H, bstar, r);
-    __syncthreads();
-    const uint64_t Sb = s_bstar_val;
-    // last b in [p, b*) with S[b] != S[b*]; T is the bin after it
-    int last = -1;
-    S = window(H, b0, r);
-    for (int j = 0; j < per; ++j) {
-        const int b = b0 + j;
-        if (j > 0) S = S + hv(H, b + r) - hv(H, b - r - 1);
-        if (b >= p && b < bstar && S != Sb) last = b;
-    }
-    const int neg = reduce_min_i(red, -last);
-    if (t == 0) {
-        out[0] = (uint32_t)(-neg + 1);
-        out[1] = (uint32_t)p;
-        out[2] = (uint32_t)bstar;
-        out[3] = 0;
-    }
-}
-
-// coarse bin b of width 2^shift
+// coarse bin b of width 2^shift, 0 outside [0, B)
 __device__ __forceinline__ uint64_t coarse(const uint64_t* H, int b, int shift)
 {
+    if (b < 0 || b >= (kB >> shift)) return 0;
     uint64_t s = 0;
     const int w = 1 << shift;
     for (int k = 0; k < w; ++k) s += H[(b << shift) + k];
     return s;
 }
 
-// ---------------------------------------------------------------- Otsu
-// Algorithm 1: for T = 0..B-1, class a = [0, T), class b = [T, B-1]:
-//   w_a = n_a / N, w_b = n_b / N, u_a = s_a / n_a, u_b = s_b / n_b,
-//   sigma = (w_a * w_b) * ((u_a - u_b) * (u_a - u_b)); strictly greater wins.
-__device__ void otsu(Red& red, const uint64_t* H, int shift, uint32_t* out)
+// ------------------------------------------------------------ block primitives
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t x = __shfl_up(v, off);
+        if (lane >= off) v += x;
+    }
+    return v;
+}
+
+// Inclusive scan of one value per thread over the block; returns the block total too.
+__device__ uint64_t block_incl_scan(uint64_t v, uint64_t* wsum, uint64_t& total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        uint64_t x = lane < kT / 64 ? wsum[lane] : 0;
+        x = wave_incl_scan(x);
+        if (lane < kT / 64) wsum[lane] = x;
+    }
+    __syncthreads();
+    const uint64_t base = w > 0 ? wsum[w - 1] : 0;
+    total = wsum[kT / 64 - 1];
+    __syncthreads();
+    return v + base;
+}
+
+// (key, index): larger key wins, ties -> smaller index.
+template <typename K>
+__device__ void block_argmax(K key, int idx, K* kbuf, int* ibuf, K& okey, int& oidx)
 {
     const int t = threadIdx.x;
-    const int B = kB >> shift;
-    const int per = (B + kT - 1) / kT;
-    const int b0 = t * per;
-    uint64_t n_loc = 0, s_loc = 0;
-    for (int j = 0; j < per && b0 + j < B; ++j) {
-        const uint64_t h = coarse(H, b0 + j, shift);
-        n_loc += h;
-        s_loc += (uint64_t)(b0 + j) * h;
+    kbuf[t] = key;
+    ibuf[t] = idx;
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            const K a = kbuf[t], b = kbuf[t + s];
+            const int ia = ibuf[t], ib = ibuf[t + s];
+            if (b > a || (b == a && ib < ia)) {
+                kbuf[t] = b;
+                ibuf[t] = ib;
+            }
+        }
+        __syncthreads();
     }
-    uint64_t na, sa, N, Stot;
-    scan2(red, n_loc, s_loc, na, sa, N, Stot);
-    double best = 0.0;
-    int bestT = 0;
-    for (int j = 0; j < per && b0 + j < B; ++j) {
-        const int T = b0 + j;
-        // class a holds bins < T: n_a, s_a are the exclusive prefix at T
+    okey = kbuf[0];
+    oidx = ibuf[0];
+    __syncthreads();
+}
+
+__device__ int block_min_i(int v, int* buf)
+{
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if (t < s && buf[t + s] < buf[t]) buf[t] = buf[t + s];
+        __syncthreads();
+    }
+    const int r = buf[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ int block_max_i(int v, int* buf) { return -block_min_i(-v, buf); }
+
+// Smoothed histogram of this chunk: S[b] for b = base + t and S[b + 1].
+// X holds H over [base - r - 1, base + kT + r] (zero outside [0, B)) and is
+// turned into its inclusive prefix, so S[b] = X[b + r] - X[b - r - 1].
+__device__ void chunk_smoothed(const uint64_t* H, int base, int r, uint64_t* X, uint64_t* wsum,
+                               uint64_t& S0, uint64_t& S1)
+{
+    const int lo = base - r - 1;
+    const int m = kT + 2 * r + 2;
+    const int per = (m + kT - 1) / kT;       // <= 3 consecutive values per thread
+    const int t = threadIdx.x;
+    for (int i = t; i < m; i += kT) X[i] = hv(H, lo + i);
+    __syncthreads();
+    uint64_t run = 0;
+    for (int j = 0; j < per; ++j) {
+        const int i = t * per + j;
+        if (i < m) run += X[i];
+    }
+    uint64_t total;
+    const uint64_t incl = block_incl_scan(run, wsum, total);
+    uint64_t acc = incl - run;
+    for (int j = 0; j < per; ++j) {
+        const int i = t * per + j;
+        if (i < m) {
+            acc += X[i];
+            X[i] = acc;
+        }
+    }
+    __syncthreads();
+    const int b = base + t;
+    // S[b] = Q[b + r] - Q[b - r - 1], indices relative to lo
+    S0 = X[b + r - lo] - X[b - r - 1 - lo];
+    S1 = X[b + 1 + r - lo] - X[b - r - lo];
+}
+
+// ------------------------------------------------------------ launch 1
+__global__ void __launch_bounds__(kT)
+chunk_pass(const uint64_t* __restrict__ H, int rule, int param, uint32_t* __restrict__ scratch)
+{
+    __shared__ uint64_t X[kHalo];
+    __shared__ uint64_t wsum[kT / 64];
+    __shared__ uint64_t kbuf[kT];
+    __shared__ int ibuf[kT];
+    const int c = blockIdx.x, t = threadIdx.x, base = c * kT;
+    if (rule == VR_RULE_VALLEY) {
+        uint64_t S0, S1;
+        chunk_smoothed(H, base, param, X, wsum, S0, S1);
+        uint64_t m;
+        int a;
+        block_argmax<uint64_t>(S0, base + t, kbuf, ibuf, m, a);
+        if (t == 0) {
+            auto* rec = reinterpret_cast<ValleyChunk*>(scratch) + c;
+            rec->smax = m;
+            rec->arg = (uint32_t)a;
+        }
+    } else {
+        const int b = base + t;
+        const uint64_t h = coarse(H, b, param);
+        uint64_t tn, ts;
+        block_incl_scan(h, wsum, tn);
+        block_incl_scan((uint64_t)b * h, wsum, ts);
+        const int lo = block_min_i(h ? b : kB, ibuf);
+        const int hi = block_max_i(h ? b : -1, ibuf);
+        if (t == 0) {
+            auto* rec = reinterpret_cast<SumChunk*>(scratch) + c;
+            rec->n = tn;
+            rec->s = ts;
+            auto* rng = reinterpret_cast<ItsChunk*>(reinterpret_cast<char*>(scratch) + 2048) + c;
+            rng->lo = lo;
+            rng->hi = hi;
+        }
+    }
+}
+
+// ------------------------------------------------------------ launch 2
+__global__ void __launch_bounds__(kT)
+chunk_search(const uint64_t* __restrict__ H, int rule, int param, int n_chunks,
+             uint32_t* __restrict__ scratch)
+{
+    __shared__ uint64_t X[kHalo];
+    __shared__ uint64_t wsum[kT / 64];
+    __shared__ uint64_t kbuf[kT];
+    __shared__ int ibuf[kT];
+    __shared__ double dbuf[kT];
+    const int c = blockIdx.x, t = threadIdx.x, base = c * kT;
+    char* sc = reinterpret_cast<char*>(scratch);
+    if (rule == VR_RULE_VALLEY) {
+        // global peak p = first argmax over the chunk records
+        const auto* rec = reinterpret_cast<const ValleyChunk*>(sc);
+        uint64_t Sp;
+        int p;
+        block_argmax<uint64_t>(t < n_chunks ? rec[t].smax : 0, t < n_chunks ? (int)rec[t].arg : kB,
+                               kbuf, ibuf, Sp, p);
+        uint64_t S0, S1;
+        chunk_smoothed(H, base, param, X, wsum, S0, S1);
+        const int b = base + t;
+        const bool inr = b <= kB - 2;             // S[b + 1] exists
+        const bool qual = inr && b > p && 2 * S0 <= Sp && S1 > S0;
+        const bool chg = inr && b >= p && S1 != S0;
+        const int cand = block_min_i(qual ? b : kB, ibuf);
+        const int below = block_max_i(chg && b < cand ? b : -1, ibuf);
+        const int all = block_max_i(chg ? b : -1, ibuf);
+        if (t == 0) {
+            auto* out = reinterpret_cast<ValleyCand*>(sc + 1024) + c;
+            out->cand = cand;
+            out->chg_below = below;
+            out->chg_all = all;
+        }
+    } else {
+        // Otsu: T = b; class a = coarse bins [0, T), class b = [T, B-1]
+        const auto* rec = reinterpret_cast<const SumChunk*>(sc);
+        uint64_t n0 = 0, s0 = 0, N = 0, Stot = 0;
+        for (int k = 0; k < n_chunks; ++k) {
+            N += rec[k].n;
+            Stot += rec[k].s;
+            if (k < c) {
+                n0 += rec[k].n;
+                s0 += rec[k].s;
+            }
+        }
+        const int B = kB >> param;
+        const int T = base + t;
+        const uint64_t h = coarse(H, T, param);
+        uint64_t tn, ts;
+        const uint64_t in_n = block_incl_scan(h, wsum, tn);
+        const uint64_t in_s = block_incl_scan((uint64_t)T * h, wsum, ts);
+        const uint64_t na = n0 + in_n - h, sa = s0 + in_s - (uint64_t)T * h;   // exclusive at T
+        double sigma = 0.0;
         const uint64_t nb = N - na;
-        if (na != 0 && nb != 0) {
+        if (T < B && na != 0 && nb != 0) {
             const uint64_t sb = Stot - sa;
             const double w_a = __ddiv_rn((double)na, (double)N);
             const double w_b = __ddiv_rn((double)nb, (double)N);
             const double u_a = __ddiv_rn((double)sa, (double)na);
             const double u_b = __ddiv_rn((double)sb, (double)nb);
             const double d = __dsub_rn(u_a, u_b);
-            const double sigma = __dmul_rn(__dmul_rn(w_a, w_b), __dmul_rn(d, d));
-            if (sigma > best) { best = sigma; bestT = T; }
+            sigma = __dmul_rn(__dmul_rn(w_a, w_b), __dmul_rn(d, d));
         }
-        const uint64_t h = coarse(H, T, shift);
-        na += h;
-        sa += (uint64_t)T * h;
-    }
-    double bv;
-    int bT;
-    // a thread with no candidate reports (0, large index) so it never wins a tie
-    reduce_max_f64(red, best, best > 0.0 ? bestT : kB, bv, bT);
-    if (t == 0) {
-        out[0] = bv > 0.0 ? (uint32_t)(bT << shift) : 0u;
-        out[1] = 0;
-        out[2] = 0;
-        out[3] = 0;
-    }
-}
-
-// ---------------------------------------------------------------- ITS
-// Algorithm 2 as isodata: T starts at (b_min + b_max + 1) / 2 over non-empty
-// bins; mu_1 = s_1 / n_1 over [0, T), mu_2 = s_2 / n_2 over [T, B-1];
-// T <- floor((mu_1 + mu_2) * 0.5) until T repeats or a class is empty.
-__device__ void its(Red& red, const uint64_t* H, int shift, uint32_t* out)
-{
-    __shared__ uint64_t s_n1, s_s1;
-    __shared__ int s_T, s_done, s_it;
-    const int t = threadIdx.x;
-    const int B = kB >> shift;
-    const int per = (B + kT - 1) / kT;
-    const int b0 = t * per;
-    uint64_t n_loc = 0, s_loc = 0;
-    int lo = kB, hi = -1;
-    for (int j = 0; j < per && b0 + j < B; ++j) {
-        const uint64_t h = coarse(H, b0 + j, shift);
-        n_loc += h;
-        s_loc += (uint64_t)(b0 + j) * h;
-        if (h) {
-            if (b0 + j < lo) lo = b0 + j;
-            hi = b0 + j;
-        }
-    }
-    uint64_t nbase, sbase, N, Stot;
-    scan2(red, n_loc, s_loc, nbase, sbase, N, Stot);
-    const int bmin = reduce_min_i(red, lo);
-    const int bmax = -reduce_min_i(red, -hi);
-    if (bmax < 0) {
-        if (t == 0) { out[0] = 0; out[1] = 0; out[2] = 0; out[3] = 0; }
-        return;
-    }
-    if (t == 0) { s_T = (bmin + bmax + 1) / 2; s_done = 0; s_it = 0; }
-    __syncthreads();
-    for (int guard = 0; guard < 1000; ++guard) {
-        const int T = s_T;
-        // the owner of bin T supplies n_1, s_1 = sums over [0, T)
-        if (T >= b0 && T < b0 + per && T < B) {
-            uint64_t n1 = nbase, s1 = sbase;
-            for (int b = b0; b < T; ++b) {
-                const uint64_t h = coarse(H, b, shift);
-                n1 += h;
-                s1 += (uint64_t)b * h;
-            }
-            s_n1 = n1;
-            s_s1 = s1;
-        }
-        if (t == 0 && T >= B) { s_n1 = N; s_s1 = Stot; }
-        __syncthreads();
+        double best;
+        int bT;
+        block_argmax<double>(sigma, sigma > 0.0 ? T : kB, dbuf, ibuf, best, bT);
         if (t == 0) {
-            s_it += 1;
-            const uint64_t n1 = s_n1, s1 = s_s1, n2 = N - n1, s2 = Stot - s1;
-            if (n1 == 0 || n2 == 0) {
-                s_done = 1;
-            } else {
-                const double mu1 = __ddiv_rn((double)s1, (double)n1);
-                const double mu2 = __ddiv_rn((double)s2, (double)n2);
-                const int Tn = (int)floor(__dmul_rn(__dadd_rn(mu1, mu2), 0.5));
-                if (Tn == T) s_done = 1;
-                else s_T = Tn;
-            }
+            auto* out = reinterpret_cast<OtsuChunk*>(sc + 1024) + c;
+            out->sigma = best;
+            out->T = bT;
         }
-        __syncthreads();
-        if (s_done) break;
-    }
-    if (t == 0) {
-        out[0] = (uint32_t)(s_T << shift);
-        out[1] = (uint32_t)s_it;
-        out[2] = 0;
-        out[3] = 0;
     }
 }
 
+// ------------------------------------------------------------ launch 3
 __global__ void __launch_bounds__(kT)
-select_kernel(const uint64_t* __restrict__ H, const uint64_t* __restrict__ Htop, int rule, int param,
-              uint32_t* __restrict__ out, uint32_t* __restrict__ bits)
+finish(const uint64_t* __restrict__ H, const uint64_t* __restrict__ Htop, int rule, int param,
+       int n_chunks, uint32_t* __restrict__ result, uint32_t* __restrict__ bits)
 {
-    __shared__ Red red;
-    __shared__ uint32_t s_T;
-    if (rule == VR_RULE_VALLEY) valley(red, H, param, out);
-    else if (rule == VR_RULE_OTSU) otsu(red, H, param, out);
-    else if (rule == VR_RULE_ITS) its(red, H, param, out);
-    else if (threadIdx.x == 0) { out[0] = 0; out[1] = 0; out[2] = 0; out[3] = 0; }
-    __syncthreads();
-    // every thread of this block wrote `out` through thread 0 only; make it visible
-    __threadfence_block();
-    if (threadIdx.x == 0) s_T = out[0];
-    __syncthreads();
-    const uint32_t T = s_T;
-    for (int w = threadIdx.x; w < VR_KEEP_WORDS; w += kT) {
-        uint32_t m = 0;
-        for (int j = 0; j < 32; ++j) {
-            const uint32_t b = (uint32_t)w * 32u + (uint32_t)j;
-            const bool keep = b >= T && (Htop == nullptr || Htop[b] == 0);
-            m |= (keep ? 1u : 0u) << j;
+    __shared__ uint64_t wsum[kT / 64];
+    __shared__ int ibuf[kT];
+    __shared__ uint64_t kbuf[kT];
+    __shared__ double dbuf[kT];
+    __shared__ uint32_t s_res[4];
+    __shared__ int s_T, s_done, s_it;
+    __shared__ SumChunk sums[kMaxChunks];
+    const int t = threadIdx.x;
+    const char* sc = reinterpret_cast<const char*>(bits);
+    if (rule == VR_RULE_VALLEY) {
+        const auto* rec = reinterpret_cast<const ValleyChunk*>(sc);
+        const auto* cnd = reinterpret_cast<const ValleyCand*>(sc + 1024);
+        uint64_t Sp;
+        int p;
+        block_argmax<uint64_t>(t < n_chunks ? rec[t].smax : 0, t < n_chunks ? (int)rec[t].arg : kB,
+                               kbuf, ibuf, Sp, p);
+        const int bstar = block_min_i(t < n_chunks ? cnd[t].cand : kB, ibuf);
+        if (bstar >= kB) {
+            if (t == 0) { s_res[0] = kB - 1; s_res[1] = (uint32_t)p; s_res[2] = 0xFFFFFFFFu; s_res[3] = 0; }
+        } else {
+            const int cs = bstar / kT;
+            int v = -1;
+            if (t < cs) v = cnd[t].chg_all;
+            else if (t == cs) v = cnd[t].chg_below;
+            const int last = block_max_i(v, ibuf);
+            if (t == 0) { s_res[0] = (uint32_t)(last + 1); s_res[1] = (uint32_t)p; s_res[2] = (uint32_t)bstar; s_res[3] = 0; }
         }
-        bits[w] = m;
+    } else if (rule == VR_RULE_OTSU) {
+        const auto* oc = reinterpret_cast<const OtsuChunk*>(sc + 1024);
+        double best;
+        int bT;
+        block_argmax<double>(t < n_chunks ? oc[t].sigma : 0.0, t < n_chunks && oc[t].sigma > 0.0 ? oc[t].T : kB,
+                             dbuf, ibuf, best, bT);
+        if (t == 0) { s_res[0] = best > 0.0 ? (uint32_t)(bT << param) : 0u; s_res[1] = 0; s_res[2] = 0; s_res[3] = 0; }
+    } else if (rule == VR_RULE_ITS) {
+        // isodata from the middle of the occupied range, T <- floor((mu_1 + mu_2) * 0.5)
+        const auto* rec = reinterpret_cast<const SumChunk*>(sc);
+        const auto* rng = reinterpret_cast<const ItsChunk*>(sc + 2048);
+        if (t < n_chunks) sums[t] = rec[t];
+        const int bmin = block_min_i(t < n_chunks ? rng[t].lo : kB, ibuf);
+        const int bmax = block_max_i(t < n_chunks ? rng[t].hi : -1, ibuf);
+        uint64_t N = 0, Stot = 0;
+        for (int k = 0; k < n_chunks; ++k) { N += sums[k].n; Stot += sums[k].s; }
+        if (bmax < 0) {
+            if (t == 0) { s_res[0] = 0; s_res[1] = 0; s_res[2] = 0; s_res[3] = 0; }
+        } else {
+            if (t == 0) { s_T = (bmin + bmax + 1) / 2; s_done = 0; s_it = 0; }
+            __syncthreads();
+            for (int guard = 0; guard < 1000; ++guard) {
+                const int T = s_T;
+                // n_1, s_1 over coarse bins [0, T): whole chunks plus the part of chunk T / kT
+                const int c = T / kT;
+                const int b = c * kT + t;
+                const uint64_t h = b < T ? coarse(H, b, param) : 0;
+                uint64_t pn, ps;
+                block_incl_scan(h, wsum, pn);
+                block_incl_scan((uint64_t)b * h, wsum, ps);
+                if (t == 0) {
+                    uint64_t n1 = pn, s1 = ps;
+                    for (int k = 0; k < c; ++k) { n1 += sums[k].n; s1 += sums[k].s; }
+                    s_it += 1;
+                    const uint64_t n2 = N - n1, s2 = Stot - s1;
+                    if (n1 == 0 || n2 == 0) {
+                        s_done = 1;
+                    } else {
+                        const double mu1 = __ddiv_rn((double)s1, (double)n1);
+                        const double mu2 = __ddiv_rn((double)s2, (double)n2);
+                        const int Tn = (int)floor(__dmul_rn(__dadd_rn(mu1, mu2), 0.5));
+                        if (Tn == T) s_done = 1;
+                        else s_T = Tn;
+                    }
+                }
+                __syncthreads();
+                if (s_done) break;
+            }
+            if (t == 0) { s_res[0] = (uint32_t)(s_T << param); s_res[1] = (uint32_t)s_it; s_res[2] = 0; s_res[3] = 0; }
+        }
+    } else {
+        if (t == 0) { s_res[0] = 0; s_res[1] = 0; s_res[2] = 0; s_res[3] = 0; }
+    }
+    __syncthreads();          // every read of the scratch is done before the mask overwrites it
+    const uint32_t T = s_res[0];
+    if (t < 4) result[t] = s_res[t];
+    // mask: bin b = 1024 j + t; a wave's 64 consecutive bins become two words by ballot
+    const int lane = t & 63, w = t >> 6;
+    for (int j = 0; j < kB / kT; ++j) {
+        const uint32_t b = (uint32_t)(j * kT + t);
+        const bool keep = b >= T && (Htop == nullptr || Htop[b] == 0);
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) {
+            bits[32 * j + 2 * w] = (uint32_t)m;
+            bits[32 * j + 2 * w + 1] = (uint32_t)(m >> 32);
+        }
     }
 }
 
@@ -337,12 +395,24 @@ extern "C" int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_his
     VR_REQUIRE(rule >= VR_RULE_VALLEY && rule <= VR_RULE_NONE, VR_ERR_RANGE,
                "vr_select_threshold: unknown rule %d", rule);
     if (rule == VR_RULE_VALLEY)
-        VR_REQUIRE(param >= 1 && param <= 4096, VR_ERR_RANGE,
-                   "vr_select_threshold: smoothing radius %d outside [1, 4096]", param);
+        VR_REQUIRE(param >= 1 && param <= kMaxRadius, VR_ERR_RANGE,
+                   "vr_select_threshold: smoothing radius %d outside [1, %d]", param, kMaxRadius);
     if (rule == VR_RULE_OTSU || rule == VR_RULE_ITS)
         VR_REQUIRE(param >= 0 && param <= 12, VR_ERR_RANGE,
                    "vr_select_threshold: bin width shift %d outside [0, 12]", param);
-    select_kernel<<<1, kT, 0, vr::as_stream(stream)>>>(d_hist, d_hist_top, rule, param, d_result,
-                                                       d_keep_bits);
+    hipStream_t s = vr::as_stream(stream);
+    const int bins = rule == VR_RULE_VALLEY ? kB : (kB >> param);
+    const int n_chunks = (bins + kT - 1) / kT;
+    if (rule != VR_RULE_NONE) {
+        chunk_pass<<<n_chunks, kT, 0, s>>>(d_hist, rule, param, d_keep_bits);
+        int rc = vr::check_launch("vr_select_threshold: chunk pass");
+        if (rc) return rc;
+        if (rule != VR_RULE_ITS) {
+            chunk_search<<<n_chunks, kT, 0, s>>>(d_hist, rule, param, n_chunks, d_keep_bits);
+            rc = vr::check_launch("vr_select_threshold: chunk search");
+            if (rc) return rc;
+        }
+    }
+    finish<<<1, kT, 0, s>>>(d_hist, d_hist_top, rule, param, n_chunks, d_result, d_keep_bits);
     return vr::check_launch("vr_select_threshold");
 }

@@ -33,6 +33,8 @@ class PreviewConfig:
     fov_deg: float = 60.0
     ortho: bool = False
     ert_eps: float = 2.0 ** -14
+    bricked: bool = True            # render from the 4^3-brick layout
+    skip_empty: bool = True         # with the brick occupancy (exact)
 
 
 def atlas_tiles(nz: int):
@@ -68,6 +70,12 @@ class PreviewPipeline:
         self.frames = torch.empty((nv, cfg.height, cfg.width, 4), dtype=torch.float32, device=dev)
         self.tf = torch.from_numpy(synth.default_tf() if tf is None else tf).to(dev)
         self.samples = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.render_vol = None
+        if cfg.bricked:
+            nb = vr.vr_brick_count(rx, ry, rz)
+            occ = torch.empty(nb, dtype=torch.uint8, device=dev) if cfg.skip_empty else None
+            self.render_vol = vr.BrickedVolume(torch.empty(nb * 64, dtype=torch.uint16, device=dev),
+                                               (rz, ry, rx), occ)
 
     # the reduction half
     def reduce(self, vol, stream=None):
@@ -82,7 +90,11 @@ class PreviewPipeline:
 
     def render(self, stream=None, count=False):
         c = self.cfg
-        vr.vr_raycast(self.levels[c.render_level - 1], self.tf, self.cams, c.width, c.height, c.step,
+        src = self.levels[c.render_level - 1]
+        if self.render_vol is not None:
+            vr.vr_brick_volume(src, out=self.render_vol, stream=stream)
+            src = self.render_vol
+        vr.vr_raycast(src, self.tf, self.cams, c.width, c.height, c.step,
                       ert_eps=c.ert_eps, out=self.frames, samples=self.samples if count else None,
                       stream=stream)
 

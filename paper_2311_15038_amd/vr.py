@@ -22,6 +22,7 @@ MAX_LEVELS = 4
 MAX_VIEWS_PER_LAUNCH = 48
 RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
 U16_NORM, F32 = 0, 1
+LAYOUT_LINEAR, LAYOUT_BRICK4 = 0, 1
 ERRORS = {-1: "VR_ERR_NULL", -2: "VR_ERR_DIMS", -3: "VR_ERR_RANGE", -4: "VR_ERR_DTYPE",
           -5: "VR_ERR_HIP", -6: "VR_ERR_UNSUPPORTED", -7: "VR_ERR_WORKSPACE"}
 
@@ -33,9 +34,9 @@ class VrError(RuntimeError):
 
 
 class vr_volume(C.Structure):
-    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("layout", C.c_int32),
                 ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
-                ("spacing", C.c_double * 3)]
+                ("spacing", C.c_double * 3), ("occupancy", C.c_void_p)]
 
 
 class vr_camera(C.Structure):
@@ -68,10 +69,13 @@ def lib():
                                  C.POINTER(vr_render_opts), vp, vp, vp]
         L.vr_raycast_backward.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                           C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
+        L.vr_brick_volume.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
+        L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64)]
         L.vr_last_error.restype = C.c_char_p
         L.vr_version.restype = C.c_char_p
         for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
-                     "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward"):
+                     "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
+                     "vr_brick_count"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -177,17 +181,57 @@ def vr_pack_slicemap(level, tiles_x, tiles_y, out_bits=16, out=None, stream=None
 
 
 # ------------------------------------------------------------------ rendering
+def vr_brick_count(nx, ny, nz) -> int:
+    n = C.c_int64(0)
+    _check(lib().vr_brick_count(nx, ny, nz, C.byref(n)))
+    return int(n.value)
+
+
+class BrickedVolume:
+    """A volume in the 4^3-brick render layout, with its occupancy grid (or None)."""
+
+    def __init__(self, data, shape, occupancy=None):
+        self.data, self.shape, self.occupancy = data, tuple(shape), occupancy
+        self.dtype = data.dtype
+        self.device = data.device
+
+
+def vr_brick_volume(src, out=None, with_occupancy=True, stream=None) -> BrickedVolume:
+    """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy)."""
+    nz, ny, nx = src.shape
+    nb = vr_brick_count(nx, ny, nz)
+    dt = U16_NORM if src.dtype in _U16 else F32
+    if out is None:
+        data = torch.empty(nb * 64, dtype=src.dtype, device=src.device)
+        occ = torch.empty(nb, dtype=torch.uint8, device=src.device) if with_occupancy else None
+        out = BrickedVolume(data, (nz, ny, nx), occ)
+    occp = None if out.occupancy is None else _dev(out.occupancy, "occupancy", torch.uint8, nb)
+    _check(lib().vr_brick_volume(_dev(src, "src", (*_U16, torch.float32)), dt, nx, ny, nz,
+                                 _dev(out.data, "bricked", src.dtype, nb * 64), occp,
+                                 _stream(stream)))
+    return out
+
+
 def make_volume(data, spacing=(1.0, 1.0, 1.0)):
-    """vr_volume for a uint16 (normalised) or float32 tensor [nz][ny][nx]."""
-    if data.dtype in _U16:
+    """vr_volume for a uint16 (normalised) or float32 tensor [nz][ny][nx], or a BrickedVolume."""
+    if isinstance(data, BrickedVolume):
+        t, layout, shape = data.data, LAYOUT_BRICK4, data.shape
+        occ = None if data.occupancy is None else _dev(data.occupancy, "occupancy").value
+    else:
+        t, layout, shape, occ = data, LAYOUT_LINEAR, data.shape, None
+    if t.dtype in _U16:
         dt = U16_NORM
-    elif data.dtype == torch.float32:
+    elif t.dtype == torch.float32:
         dt = F32
     else:
-        raise TypeError(f"unsupported volume dtype {data.dtype}")
-    nz, ny, nx = data.shape
-    return vr_volume(_dev(data, "volume").value, dt, 0, nx, ny, nz,
-                     (C.c_double * 3)(*[float(s) for s in spacing]))
+        raise TypeError(f"unsupported volume dtype {t.dtype}")
+    nz, ny, nx = shape
+    return vr_volume(_dev(t, "volume").value, dt, layout, nx, ny, nz,
+                     (C.c_double * 3)(*[float(s) for s in spacing]), occ)
+
+
+def vol_shape(data):
+    return data.shape if isinstance(data, BrickedVolume) else tuple(data.shape)
 
 
 def make_cameras(cams):
@@ -233,6 +277,6 @@ def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba
     _check(lib().vr_raycast_backward(
         C.byref(vol), _dev(tf, "tf", torch.float32, 1024), ca, nv, C.byref(opts),
         _dev(rgba_fwd, "rgba_fwd", torch.float32, n), _dev(grad_rgba, "grad_rgba", torch.float32, n),
-        _dev(grad_density, "grad_density", torch.float32, data.numel()),
+        _dev(grad_density, "grad_density", torch.float32, int(np.prod(vol_shape(data)))),
         _dev(grad_tf, "grad_tf", torch.float32, 1024), _stream(stream)))
     return grad_density, grad_tf

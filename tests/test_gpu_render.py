@@ -125,3 +125,93 @@ def test_raycast_rejects_bad_args(level1):
         vr.vr_raycast(v, tf, bad, 8, 8, 0.5)
     with pytest.raises(vr.VrError):
         vr.vr_raycast(v, tf, cam, 0, 8, 0.5)
+
+
+# ------------------------------------------------------------ brick render layout
+def _brick_ref(a):
+    """The 4^3 brick layout and the dilated occupancy, written out with NumPy."""
+    nz, ny, nx = a.shape
+    nbz, nby, nbx = (nz + 3) // 4, (ny + 3) // 4, (nx + 3) // 4
+    pad = np.zeros((nbz * 4, nby * 4, nbx * 4), dtype=a.dtype)
+    pad[:nz, :ny, :nx] = a
+    br = pad.reshape(nbz, 4, nby, 4, nbx, 4).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
+    occ = np.zeros((nbz, nby, nbx), dtype=np.uint8)
+    for z, y, x in np.argwhere(a != 0):
+        for zz in (z - 1, z):
+            for yy in (y - 1, y):
+                for xx in (x - 1, x):
+                    if zz >= 0 and yy >= 0 and xx >= 0:
+                        occ[zz // 4, yy // 4, xx // 4] = 1
+    return br, occ.reshape(-1)
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37)])
+def test_brick_layout_and_occupancy(shape):
+    banner(f"brick layout {shape}")
+    rng = np.random.default_rng(31)
+    a = np.zeros(shape, dtype=np.uint16)
+    m = rng.random(shape) < 0.01
+    a[m] = rng.integers(1, 65536, size=int(m.sum()))
+    a[0, 0, 0] = 7
+    a[-1, -1, -1] = 9
+    bv = vr.vr_brick_volume(to_dev_u16(a))
+    br, occ = _brick_ref(a)
+    got = bv.data.cpu().view(torch.int16).numpy().view(np.uint16)
+    assert (got == br).all()
+    assert (bv.occupancy.cpu().numpy() == occ).all()
+    f = a.astype(np.float32) / 7.0
+    bf = vr.vr_brick_volume(torch.from_numpy(f).to(dev()))
+    assert (bf.data.cpu().numpy() == _brick_ref(f)[0]).all()
+    assert (bf.occupancy.cpu().numpy() == occ).all()
+
+
+def _sparse_volume(shape, seed):
+    """Blobs in empty space, some touching the faces: exercises brick skipping."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    idx = np.indices(shape).astype(np.float64)
+    a = np.zeros(shape)
+    for _ in range(6):
+        c = rng.uniform(0, 1, 3) * np.array(shape)
+        r = rng.uniform(2, 6)
+        d2 = ((idx - c[:, None, None, None]) ** 2).sum(axis=0)
+        a += 30000 * np.exp(-d2 / (2 * r * r)) * (d2 < 9 * r * r)
+    return np.clip(a, 0, 65535).astype(np.uint16)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (29, 23, 37), (40, 17, 50)])
+def test_brick_and_skip_bit_identical(level1, shape):
+    banner(f"bricked+skip == linear {shape}")
+    a = level1 if shape == (64, 64, 64) else _sparse_volume(shape, 5)
+    nz, ny, nx = a.shape
+    tf = _tf_dev(synth.default_tf(sigma_scale=3.0))
+    cams = np.concatenate([synth.turntable_cameras(nx, ny, nz, n_views=7),
+                           synth.front_ortho_camera(nx, ny, nz)])
+    v = to_dev_u16(a)
+    c0 = torch.zeros(1, dtype=torch.int64, device=dev())
+    c1 = torch.zeros(1, dtype=torch.int64, device=dev())
+    c2 = torch.zeros(1, dtype=torch.int64, device=dev())
+    lin = vr.vr_raycast(v, tf, cams, 45, 38, 0.5, samples=c0)
+    bv = vr.vr_brick_volume(v)
+    skip = vr.vr_raycast(bv, tf, cams, 45, 38, 0.5, samples=c1)
+    bv.occupancy = None
+    noskip = vr.vr_raycast(bv, tf, cams, 45, 38, 0.5, samples=c2)
+    assert torch.equal(lin, noskip) and torch.equal(lin, skip)
+    assert c0.item() == c1.item() == c2.item()
+    if shape != (64, 64, 64):
+        ref, n_ref = R.render(a, (1, 1, 1), synth.default_tf(sigma_scale=3.0).astype(np.float64),
+                              cams, 45, 38, 0.5)
+        assert np.abs(skip.cpu().numpy() - ref).max() <= TOL
+
+
+def test_skip_disabled_when_density_zero_is_not_empty(level1):
+    banner("no skipping when tf[0] has extinction")
+    tf = synth.default_tf()
+    tf[0, 3] = 0.01                                   # density 0 now attenuates
+    cams = synth.turntable_cameras(64, 64, 64, n_views=2)
+    v = to_dev_u16(level1)
+    lin = vr.vr_raycast(v, _tf_dev(tf), cams, 32, 32, 0.5)
+    br = vr.vr_raycast(vr.vr_brick_volume(v), _tf_dev(tf), cams, 32, 32, 0.5)
+    assert torch.equal(lin, br)
+    ref, _ = R.render(level1, (1, 1, 1), tf.astype(np.float64), cams, 32, 32, 0.5)
+    assert np.abs(br.cpu().numpy() - ref).max() <= TOL
