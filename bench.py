@@ -60,42 +60,35 @@ def run_gpu(steps, warmup):
     pipe.samples.zero_()
     pipe.step(vol, count=True)
     torch.cuda.synchronize()
-    samples = int(pipe.samples.item())
+    samples = int(pipe.samples[0].item())
+    evaluated = int(pipe.samples[1].item())
     for _ in range(warmup):
         pipe.step(vol)
     torch.cuda.synchronize()
     log(f"warmup done ({warmup} steps), {samples} samples per step")
 
+    calls = pipe.calls(vol)
     ev = _events(2)
-    k_ev = {name: _events(2 * steps) for name in ("hist", "hist_top", "select", "downsample", "pack", "raycast")}
-    from paper_2311_15038_amd import vr
-    c = pipe.cfg
+    k_ev = {name: _events(2 * steps) for name, _ in calls}
     torch.cuda.synchronize()
     ev[0].record()
-    for s in range(steps):
-        def rec(name, fn):
-            k_ev[name][2 * s].record()
+    for st in range(steps):
+        for name, fn in calls:
+            k_ev[name][2 * st].record()
             fn()
-            k_ev[name][2 * s + 1].record()
-        rec("hist", lambda: vr.vr_histogram(vol, 0, None, pipe.hist))
-        rec("hist_top", lambda: vr.vr_histogram(vol, 0, c.top_slices, pipe.hist_top))
-        rec("select", lambda: vr.vr_select_threshold(pipe.hist, pipe.hist_top, c.rule, c.rule_param,
-                                                     pipe.result, pipe.keep))
-        rec("downsample", lambda: vr.vr_threshold_downsample(vol, pipe.keep, c.n_levels, pipe.levels))
-        rec("pack", lambda: vr.vr_pack_slicemap(pipe.levels[c.atlas_level - 1], pipe.tiles[0],
-                                                pipe.tiles[1], 16, pipe.atlas))
-        rec("raycast", lambda: pipe.render())
+            k_ev[name][2 * st + 1].record()
     ev[1].record()
     torch.cuda.synchronize()
     total_ms = ev[0].elapsed_time(ev[1])
-    per = {k: sum(e[2 * s].elapsed_time(e[2 * s + 1]) for s in range(steps)) / steps
+    per = {k: sum(e[2 * st].elapsed_time(e[2 * st + 1]) for st in range(steps)) / steps
            for k, e in k_ev.items()}
     ms_step = total_ms / steps
-    red_ms = sum(per[k] for k in ("hist", "hist_top", "select", "downsample", "pack"))
+    red_ms = sum(per[k] for k in pipe.REDUCTION_CALLS)
     red_bytes = pipe.reduction_bytes()
     T = int(pipe.result[0].item())
     out = {
         "samples_per_step": samples,
+        "evaluated_per_step": evaluated,
         "ms_per_step": ms_step,
         "kernel_ms": per,
         "reduction_ms": red_ms,
@@ -105,8 +98,9 @@ def run_gpu(steps, warmup):
     nz, ny, nx = vol.shape
     vol_b = nx * ny * nz * 2
     lv_b = sum(l.numel() * 2 for l in pipe.levels)
-    out["kernel_bytes"] = {"hist": vol_b, "hist_top": nx * ny * 3 * 2, "downsample": vol_b + lv_b,
-                           "pack": 2 * pipe.atlas.numel() * 2}
+    out["kernel_bytes"] = {"histograms": vol_b + nx * ny * 3 * 2,
+                           "pyramid+atlas": vol_b + lv_b + pipe.atlas.numel() * 2,
+                           "bricks": 2 * pipe.levels[0].numel() * 2}
     return out, pipe, vol
 
 
@@ -147,7 +141,7 @@ def run_fwd_bwd(pipe, iters=5):
     torch.cuda.synchronize()
     it_ms = e[0].elapsed_time(e[1]) / iters
     with torch.no_grad():
-        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        cnt = torch.zeros(2, dtype=torch.int64, device=dev)
         fe = _events(2)
         fe[0].record()
         for _ in range(iters):
@@ -157,7 +151,7 @@ def run_fwd_bwd(pipe, iters=5):
         torch.cuda.synchronize()
         fwd_ms = fe[0].elapsed_time(fe[1]) / iters
     return {"ms_per_iter": it_ms, "fwd_ms": fwd_ms, "iter_over_fwd": it_ms / fwd_ms,
-            "samples_fwd": int(cnt.item()), "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
+            "samples_fwd": int(cnt[0].item()), "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
 
 
 def cpu_baseline(pipe, vol, budget_s=12.0):
@@ -226,7 +220,9 @@ def main():
     samples = res["samples_per_step"]
     value = samples / (ms * 1e-3) / 1e9
     rc_ms = res["kernel_ms"]["raycast"]
-    achieved = samples * FLOPS_PER_SAMPLE / (rc_ms * 1e-3) / 1e12
+    evaluated = res["evaluated_per_step"]
+    # ALU roofline over the samples the kernel evaluates (empty-brick samples are passed over)
+    achieved = evaluated * FLOPS_PER_SAMPLE / (rc_ms * 1e-3) / 1e12
     red_gbs = res["reduction_bytes"] / (res["reduction_ms"] * 1e-3) / 1e9
     line = {
         "metric": METRIC,
@@ -248,10 +244,13 @@ def main():
                    "volume": [1024, 1024, 1024], "levels": 4, "views": 36, "image": [512, 512]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "raycast_fwd<u16>", "flops_per_sample": FLOPS_PER_SAMPLE,
+                     "kernel": "raycast_fwd<u16,brick4>", "flops_per_sample": FLOPS_PER_SAMPLE,
+                     "samples": "evaluated",
                      "kernel_ms": rc_ms},
         "raycast_Gsamples_per_s": samples / (rc_ms * 1e-3) / 1e9,
+        "raycast_evaluated_Gsamples_per_s": evaluated / (rc_ms * 1e-3) / 1e9,
         "samples_per_step": samples,
+        "evaluated_per_step": evaluated,
         "reduction": {"ms": res["reduction_ms"], "bytes": res["reduction_bytes"],
                       "GB_per_s": red_gbs, "frac_hbm_peak": red_gbs / HBM_PEAK_GBS,
                       "threshold": res["threshold"]},

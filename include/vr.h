@@ -110,6 +110,23 @@ int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_hist_top, int 
                         uint32_t* d_result, uint32_t* d_keep_bits, void* stream);
 
 /*
+ * Both histograms Section III-D needs, in one launch: d_hist over the whole
+ * volume and d_hist_top over its first top_slices slices (1..nz); the same
+ * counts as two vr_histogram calls.  Both outputs are overwritten.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE, VR_ERR_HIP.
+ */
+int vr_histogram_with_top(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
+                          int64_t top_slices, uint64_t* d_hist, uint64_t* d_hist_top, void* stream);
+
+/* A slicemap atlas written as a side output of vr_threshold_downsample. */
+typedef struct {
+    int32_t level;             /* pyramid level (1..n_levels) packed into the atlas */
+    int32_t tiles_x, tiles_y;  /* tile grid; tiles_x * tiles_y >= that level's nz */
+    int32_t out_bits;          /* 16 or 8, as vr_pack_slicemap */
+    void* data;                /* device pointer, [tiles_y*ny_k][tiles_x*nx_k] */
+} vr_atlas_spec;
+
+/*
  * Thresholding fused with the multi-resolution pyramid (abstract and
  * Section II: a coarse resolution is delivered before the full data).
  * f = keep[v] ? v : 0 per voxel (d_keep_bits NULL keeps every voxel); level
@@ -121,11 +138,13 @@ int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_hist_top, int 
  *   h_levels: host array of n_levels device pointers, level k at
  *     h_levels[k-1], each [nz_k][ny_k][nx_k] u16, overwritten.
  *   n_levels: 1..VR_MAX_LEVELS.
- * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (n_levels), VR_ERR_HIP.
+ *   atlas: NULL, or a slicemap atlas of one of the levels to write in the
+ *     same pass (the layout and values of vr_pack_slicemap, overwritten).
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (n_levels, atlas), VR_ERR_HIP.
  */
 int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
                             const uint32_t* d_keep_bits, int n_levels,
-                            uint16_t* const* h_levels, void* stream);
+                            uint16_t* const* h_levels, const vr_atlas_spec* atlas, void* stream);
 
 /*
  * Slicemap atlas of a volume level (Section III, slicemaps of the cited
@@ -145,22 +164,25 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  * volume as 4 x 4 x 4-voxel bricks, brick (bx, by, bz) at element
  * ((bz*nby + by)*nbx + bx)*64 with nbx = ceil(nx / 4) (and so on), voxel (x, y, z) at
  * ((z&3)*16 + (y&3)*4 + (x&3)) inside it (voxels past the volume's end are 0).
- * Optional occupancy (one byte per brick): non-zero iff a non-zero voxel is
+ * Optional occupancy: one byte per brick, non-zero iff a non-zero voxel is
  * one of the 8 taps of a trilinear fetch whose base (floor, clamped) tap lies
- * in that brick.  The ray caster passes over samples of unoccupied bricks
+ * in that brick, followed by one byte per 4 x 4 x 4 bricks (16^3 voxels,
+ * [ceil(nbz/4)][ceil(nby/4)][ceil(nbx/4)]) that is non-zero iff any of its
+ * bricks is.  The ray caster passes over samples of unoccupied bricks
  * when the transfer function's first entry has zero extinction: such samples
  * have density 0 and change neither colour nor transmittance, so the result
  * is bit-identical.
  *   d_src: [nz][ny][nx] of u16 (dtype VR_U16_NORM) or f32 (VR_F32).
  *   d_bricked: vr_brick_count(...) * 64 elements, overwritten.
- *   d_occupancy: NULL or vr_brick_count(...) bytes, overwritten.
+ *   d_occupancy: NULL or the occupancy_bytes of vr_brick_count, overwritten.
  * Errors: VR_ERR_NULL, VR_ERR_DTYPE, VR_ERR_DIMS, VR_ERR_HIP.
  */
 int vr_brick_volume(const void* d_src, int dtype, int64_t nx, int64_t ny, int64_t nz,
                     void* d_bricked, uint8_t* d_occupancy, void* stream);
 
-/* Number of 4x4x4 bricks of an nx x ny x nz volume (host only). */
-int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks);
+/* Number of 4x4x4 bricks of an nx x ny x nz volume and the size of its
+ * occupancy (nullable) in bytes (host only). */
+int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_t* occupancy_bytes);
 
 /* A volume to render. dtype VR_U16_NORM (value / 65535) or VR_F32 (value). */
 typedef struct {
@@ -203,8 +225,10 @@ typedef struct {
  * back: alpha = 1 - exp(-sigma len), C += T alpha rgb, T *= exp(-sigma len);
  * output RGB = C + T bg_rgb, A = 1 - T (1 - bg_a).  Missing rays get bg.
  *   d_rgba: [n_views][height][width][4] f32, overwritten.
- *   d_samples: NULL or one uint64 to which the number of samples taken is
- *     added (the caller zeroes it).
+ *   d_samples: NULL or two uint64 counters the call adds to (the caller
+ *     zeroes them): [0] the samples of the definition above taken before
+ *     early termination, [1] the samples evaluated (those not passed over as
+ *     empty, see occupancy below).
  *   h_cams: n_views cameras (any n_views >= 1; views are launched in groups
  *     of VR_MAX_VIEWS_PER_LAUNCH).
  * All arithmetic is FP32; per-ray results do not depend on the launch shape,

@@ -7,7 +7,10 @@
 // occupancy[b] != 0 iff some non-zero voxel is one of the eight taps of a
 // trilinear fetch whose base tap (the floor corner, clamped to the volume)
 // lies in brick b; a voxel at (x, y, z) is a tap for base taps
-// (x - {0,1}, y - {0,1}, z - {0,1}), so it marks up to eight bricks.
+// (x - {0,1}, y - {0,1}, z - {0,1}), so it marks up to eight bricks.  A second
+// grid follows the first: one byte per 4 x 4 x 4 bricks (16^3 voxels), set
+// when any of its bricks is marked, so a ray can cross large empty regions in
+// long steps.
 #include "common.h"
 
 namespace {
@@ -32,7 +35,8 @@ __device__ __forceinline__ bool nonzero(T v) { return v != (T)0; }
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
-             T* __restrict__ dst, uint8_t* __restrict__ occ)
+             T* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx,
+             int nmy)
 {
     __shared__ __align__(16) T slab[16 * 64];
     __shared__ uint32_t marks[17 * 2 * 2];      // (bx - 1 .. bx + 15) x (by - 1, by) x (bz - 1, bz)
@@ -83,21 +87,26 @@ brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby
     if (occ != nullptr && t < 17 * 4) {
         const int xi = t % 17, yi = (t / 17) & 1, zi = t / 34;
         const int bx = bx0 + xi - 1, byy = by + yi - 1, bzz = bz + zi - 1;
-        if (marks[t] && bx >= 0 && bx < nbx && byy >= 0 && bzz >= 0)
+        if (marks[t] && bx >= 0 && bx < nbx && byy >= 0 && bzz >= 0) {
             occ[((int64_t)bzz * nby + byy) * nbx + bx] = 1;
+            macro[((int64_t)(bzz >> 2) * nmy + (byy >> 2)) * nmx + (bx >> 2)] = 1;
+        }
     }
 }
 
 }  // namespace
 
-extern "C" int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks)
+extern "C" int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks,
+                              int64_t* occupancy_bytes)
 {
     vr::clear_error();
     VR_REQUIRE(n_bricks != nullptr, VR_ERR_NULL, "vr_brick_count: n_bricks is NULL");
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
                VR_ERR_DIMS, "vr_brick_count: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
                (long long)nz);
-    *n_bricks = ((nx + 3) / 4) * ((ny + 3) / 4) * ((nz + 3) / 4);
+    const int64_t bx = (nx + 3) / 4, by = (ny + 3) / 4, bz = (nz + 3) / 4;
+    *n_bricks = bx * by * bz;
+    if (occupancy_bytes) *occupancy_bytes = bx * by * bz + ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 3) / 4);
     return VR_OK;
 }
 
@@ -112,15 +121,17 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int64_t nx, int64_t
                VR_ERR_DIMS, "vr_brick_volume: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
                (long long)nz);
     const int nbx = (int)((nx + 3) / 4), nby = (int)((ny + 3) / 4), nbz = (int)((nz + 3) / 4);
+    const int nmx = (nbx + 3) / 4, nmy = (nby + 3) / 4, nmz = (nbz + 3) / 4;
     const int64_t bricks = (int64_t)nbx * nby * nbz;
+    const int64_t occ_bytes = bricks + (int64_t)nmx * nmy * nmz;
     VR_REQUIRE(nby < 65536 && nbz < 65536, VR_ERR_DIMS, "vr_brick_volume: volume too large");
     VR_REQUIRE((reinterpret_cast<uintptr_t>(d_bricked) & 15u) == 0, VR_ERR_RANGE,
                "vr_brick_volume: d_bricked must be 16-byte aligned");
     hipStream_t s = vr::as_stream(stream);
     const int64_t cap = (int64_t)vr::num_cus() * 16;
     if (d_occupancy) {
-        const int64_t g = std::min<int64_t>(cap, vr::ceil_div<int64_t>(bricks, kThreads));
-        fill_u8<<<(unsigned)std::max<int64_t>(g, 1), kThreads, 0, s>>>(d_occupancy, bricks);
+        const int64_t g = std::min<int64_t>(cap, vr::ceil_div<int64_t>(occ_bytes, kThreads));
+        fill_u8<<<(unsigned)std::max<int64_t>(g, 1), kThreads, 0, s>>>(d_occupancy, occ_bytes);
         int rc = vr::check_launch("vr_brick_volume: fill");
         if (rc) return rc;
     }
@@ -128,10 +139,12 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int64_t nx, int64_t
     if (dtype == VR_U16_NORM)
         brick_kernel<uint16_t><<<grid, kThreads, 0, s>>>(
             static_cast<const uint16_t*>(d_src), (int)nx, (int)ny, (int)nz, nbx, nby,
-            static_cast<uint16_t*>(d_bricked), d_occupancy);
+            static_cast<uint16_t*>(d_bricked), d_occupancy,
+            d_occupancy ? d_occupancy + bricks : nullptr, nmx, nmy);
     else
         brick_kernel<float><<<grid, kThreads, 0, s>>>(
             static_cast<const float*>(d_src), (int)nx, (int)ny, (int)nz, nbx, nby,
-            static_cast<float*>(d_bricked), d_occupancy);
+            static_cast<float*>(d_bricked), d_occupancy,
+            d_occupancy ? d_occupancy + bricks : nullptr, nmx, nmy);
     return vr::check_launch("vr_brick_volume");
 }

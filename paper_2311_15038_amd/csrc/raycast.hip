@@ -37,6 +37,8 @@ struct Scene {
     const uint8_t* occ;     // brick occupancy or NULL
     int nx, ny, nz;
     int nbx, nby, nbz;      // 4^3 bricks per axis
+    int nmx, nmy, nmz;      // 16^3 groups of bricks per axis
+    uint32_t macro_off;     // byte offset of the group occupancy
     float inv_sp[3];
     float ext[3];
     int W, H;
@@ -215,23 +217,22 @@ __device__ __forceinline__ void pixel_of(const Scene& S, int nb, int& view, int&
     j = ty * kTile + (w >> 1) * 8 + (lane >> 3);
 }
 
-// Index of the first sample past the base-tap region of an empty brick: the
-// ray leaves brick (bx, by, bz) of the base tap where u = u0 + s g crosses a
-// multiple of 4 (the volume's first and last bricks extend to infinity, since
-// taps are clamped).  Samples with offset below the exit minus a margin are in
-// the brick; the sample at the returned index is checked again.
+// Index of the first sample past the base-tap region of an empty cell (a
+// brick, sh = 2, or a 16^3 group of bricks, sh = 4): the base tap stays in
+// cell (cx, cy, cz) while u = u0 + s g lies in [cell << sh, (cell + 1) << sh)
+// on every axis; the first and last cells of an axis extend to infinity,
+// since taps are clamped.  Samples whose offset is below the exit minus a
+// margin are in the cell; the sample at the returned index is checked again.
 __device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const float g[3],
-                                       const Cell& c, int k, int n)
+                                       const uint32_t cell[3], const int ncell[3], int sh, int k, int n)
 {
-    const uint32_t bi[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-    const int nb[3] = {S.nbx, S.nby, S.nbz};
     float s_exit = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (g[a] > 0.0f && (int)bi[a] < nb[a] - 1)
-            s_exit = fminf(s_exit, ((float)(4u * (bi[a] + 1u)) - u0[a]) / g[a]);
-        else if (g[a] < 0.0f && bi[a] > 0u)
-            s_exit = fminf(s_exit, ((float)(4u * bi[a]) - u0[a]) / g[a]);
+        if (g[a] > 0.0f && (int)cell[a] < ncell[a] - 1)
+            s_exit = fminf(s_exit, ((float)((cell[a] + 1u) << sh) - u0[a]) / g[a]);
+        else if (g[a] < 0.0f && cell[a] > 0u)
+            s_exit = fminf(s_exit, ((float)(cell[a] << sh) - u0[a]) / g[a]);
     }
     const float lim = (s_exit - S.step * (1.0f / 256.0f) - 0.5f * S.step) / S.step;
     int next = n;
@@ -253,7 +254,7 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
     int view, i, j;
     pixel_of(S, (int)gridDim.x, view, i, j);
     const T* vol = static_cast<const T*>(S.data);
-    unsigned long long cnt = 0;
+    unsigned long long cnt = 0, evals = 0;
     if (i < S.W && j < S.H) {
         const View& v = V.v[view];
         float p[3], d[3], L;
@@ -274,7 +275,18 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
                 const float off = fmaf(0.5f, len, (float)k * S.step);
                 const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
                 if (skip && S.occ[((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2)] == 0) {
-                    const int next = skip_to(S, u0, g, c, k, n);
+                    // empty brick: leave its 16^3 group if that is empty too, else the brick
+                    const uint32_t m[3] = {c.x0 >> 4, c.y0 >> 4, c.z0 >> 4};
+                    const bool coarse = S.occ[S.macro_off + (m[2] * (uint32_t)S.nmy + m[1]) * (uint32_t)S.nmx + m[0]] == 0;
+                    int next;
+                    if (coarse) {
+                        const int nm[3] = {S.nmx, S.nmy, S.nmz};
+                        next = skip_to(S, u0, g, m, nm, 4, k, n);
+                    } else {
+                        const uint32_t b[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
+                        const int nb[3] = {S.nbx, S.nby, S.nbz};
+                        next = skip_to(S, u0, g, b, nb, 2, k, n);
+                    }
                     cnt += (unsigned long long)(next - k);
                     k = next;
                     continue;
@@ -289,6 +301,7 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
                 cb = fmaf(ta, h.q.z, cb);
                 Tr = Tr * e;
                 ++cnt;
+                ++evals;
                 ++k;
                 if (Tr < S.eps) break;
             }
@@ -299,8 +312,12 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
     }
     if (samples) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        for (int off = 32; off > 0; off >>= 1) {
+            cnt += __shfl_xor(cnt, off);
+            evals += __shfl_xor(evals, off);
+        }
         if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(samples, cnt);
+        if ((threadIdx.x & 63) == 0 && evals) atomicAdd(samples + 1, evals);
     }
 }
 
@@ -445,6 +462,10 @@ int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams
     S.nbx = (int)nb[0];
     S.nby = (int)nb[1];
     S.nbz = (int)nb[2];
+    S.nmx = (S.nbx + 3) / 4;
+    S.nmy = (S.nby + 3) / 4;
+    S.nmz = (S.nbz + 3) / 4;
+    S.macro_off = (uint32_t)(nb[0] * nb[1] * nb[2]);
     S.nx = (int)vol->nx;
     S.ny = (int)vol->ny;
     S.nz = (int)vol->nz;

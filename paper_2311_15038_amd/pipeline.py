@@ -69,24 +69,24 @@ class PreviewPipeline:
         nv = len(self.cams)
         self.frames = torch.empty((nv, cfg.height, cfg.width, 4), dtype=torch.float32, device=dev)
         self.tf = torch.from_numpy(synth.default_tf() if tf is None else tf).to(dev)
-        self.samples = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.samples = torch.zeros(2, dtype=torch.int64, device=dev)
         self.render_vol = None
         if cfg.bricked:
-            nb = vr.vr_brick_count(rx, ry, rz)
-            occ = torch.empty(nb, dtype=torch.uint8, device=dev) if cfg.skip_empty else None
+            nb, nocc = vr.vr_brick_count(rx, ry, rz)
+            occ = torch.empty(nocc, dtype=torch.uint8, device=dev) if cfg.skip_empty else None
             self.render_vol = vr.BrickedVolume(torch.empty(nb * 64, dtype=torch.uint16, device=dev),
                                                (rz, ry, rx), occ)
 
-    # the reduction half
+    # the reduction half: three launches-worth of calls (histograms, selection,
+    # pyramid with its atlas written in the same pass)
     def reduce(self, vol, stream=None):
         c = self.cfg
-        vr.vr_histogram(vol, 0, None, self.hist, stream)
-        vr.vr_histogram(vol, 0, c.top_slices, self.hist_top, stream)
+        vr.vr_histogram_with_top(vol, c.top_slices, self.hist, self.hist_top, stream)
         vr.vr_select_threshold(self.hist, self.hist_top, c.rule, c.rule_param, self.result,
                                self.keep, stream)
-        vr.vr_threshold_downsample(vol, self.keep, c.n_levels, self.levels, stream)
-        vr.vr_pack_slicemap(self.levels[c.atlas_level - 1], self.tiles[0], self.tiles[1], 16,
-                            self.atlas, stream)
+        vr.vr_threshold_downsample(vol, self.keep, c.n_levels, self.levels,
+                                   (c.atlas_level, self.tiles[0], self.tiles[1], 16, self.atlas),
+                                   stream)
 
     def render(self, stream=None, count=False):
         c = self.cfg
@@ -102,8 +102,33 @@ class PreviewPipeline:
         self.reduce(vol, stream)
         self.render(stream, count)
 
+    def calls(self, vol, stream=None):
+        """The step as named library calls, in order (for per-call timing)."""
+        c = self.cfg
+        out = [
+            ("histograms", lambda: vr.vr_histogram_with_top(vol, c.top_slices, self.hist,
+                                                            self.hist_top, stream)),
+            ("select", lambda: vr.vr_select_threshold(self.hist, self.hist_top, c.rule,
+                                                      c.rule_param, self.result, self.keep, stream)),
+            ("pyramid+atlas", lambda: vr.vr_threshold_downsample(
+                vol, self.keep, c.n_levels, self.levels,
+                (c.atlas_level, self.tiles[0], self.tiles[1], 16, self.atlas), stream)),
+        ]
+        level = self.levels[c.render_level - 1]
+        src = level
+        if self.render_vol is not None:
+            out.append(("bricks", lambda: vr.vr_brick_volume(level, out=self.render_vol, stream=stream)))
+            src = self.render_vol
+        out.append(("raycast", lambda src=src: vr.vr_raycast(src, self.tf, self.cams, c.width, c.height,
+                                                             c.step, ert_eps=c.ert_eps, out=self.frames,
+                                                             stream=stream)))
+        return out
+
+    REDUCTION_CALLS = ("histograms", "select", "pyramid+atlas")
+
     def reduction_bytes(self) -> int:
-        """Algorithmic HBM bytes of the reduction half: every input read once, every output written once."""
+        """Algorithmic HBM bytes of the reduction steps (histograms, pyramid, atlas), each
+        input read once and each output written once, as for separate steps."""
         nz, ny, nx = self.shape
         vol = nx * ny * nz * 2
         top = nx * ny * min(self.cfg.top_slices, nz) * 2

@@ -44,6 +44,11 @@ class vr_camera(C.Structure):
                 ("fov_y_deg", C.c_double), ("ortho_half_h", C.c_double)]
 
 
+class vr_atlas_spec(C.Structure):
+    _fields_ = [("level", C.c_int32), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
+                ("out_bits", C.c_int32), ("data", C.c_void_p)]
+
+
 class vr_render_opts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("step", C.c_float),
                 ("ert_eps", C.c_float), ("bg", C.c_float * 4)]
@@ -63,19 +68,21 @@ def lib():
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
         L.vr_histogram.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp]
         L.vr_select_threshold.argtypes = [vp, vp, i32, i32, vp, vp, vp]
-        L.vr_threshold_downsample.argtypes = [vp, i64, i64, i64, vp, i32, C.POINTER(vp), vp]
+        L.vr_threshold_downsample.argtypes = [vp, i64, i64, i64, vp, i32, C.POINTER(vp),
+                                              C.POINTER(vr_atlas_spec), vp]
+        L.vr_histogram_with_top.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
         L.vr_pack_slicemap.argtypes = [vp, i64, i64, i64, i32, i32, i32, vp, vp]
         L.vr_raycast.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                  C.POINTER(vr_render_opts), vp, vp, vp]
         L.vr_raycast_backward.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                           C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
         L.vr_brick_volume.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
-        L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64)]
+        L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.vr_last_error.restype = C.c_char_p
         L.vr_version.restype = C.c_char_p
         for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
                      "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
-                     "vr_brick_count"):
+                     "vr_brick_count", "vr_histogram_with_top"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -126,6 +133,20 @@ def vr_histogram(vol, z0=0, nz_range=None, out=None, stream=None):
     return out
 
 
+def vr_histogram_with_top(vol, top_slices=3, hist=None, hist_top=None, stream=None):
+    """Histograms of the whole volume and of its first top_slices slices, one launch."""
+    nz, ny, nx = vol.shape
+    if hist is None:
+        hist = torch.empty(NBINS, dtype=torch.int64, device=vol.device)
+    if hist_top is None:
+        hist_top = torch.empty(NBINS, dtype=torch.int64, device=vol.device)
+    _check(lib().vr_histogram_with_top(_dev(vol, "vol", _U16), nx, ny, nz, int(top_slices),
+                                       _dev(hist, "hist", torch.int64, NBINS),
+                                       _dev(hist_top, "hist_top", torch.int64, NBINS),
+                                       _stream(stream)))
+    return hist, hist_top
+
+
 def vr_select_threshold(hist, hist_top=None, rule=RULE_VALLEY, param=32, result=None, keep_bits=None,
                         stream=None):
     """-> (result int32[4] = T, aux, b*, 0; keep_bits int32[2048] holding the uint32 mask)."""
@@ -147,8 +168,12 @@ def level_shape(shape, k):
     return tuple(-(-n // d) for n in shape)
 
 
-def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, stream=None):
-    """Filtered pyramid levels 1..n_levels (list of uint16 tensors)."""
+def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, stream=None):
+    """Filtered pyramid levels 1..n_levels (list of uint16 tensors).
+
+    atlas: None or (level, tiles_x, tiles_y, out_bits, tensor): the slicemap
+    atlas of that level, written in the same pass.
+    """
     nz, ny, nx = vol.shape
     if levels is None:
         levels = [torch.empty(level_shape((nz, ny, nx), k), dtype=torch.uint16, device=vol.device)
@@ -162,8 +187,15 @@ def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, stream=None):
             raise ValueError(f"level {k + 1} has shape {tuple(levels[k].shape)}, expected {want}")
         ptrs[k] = _dev(levels[k], f"levels[{k}]", _U16).value
     kb = None if keep_bits is None else _dev(keep_bits, "keep_bits", torch.int32, KEEP_WORDS)
+    spec = None
+    if atlas is not None:
+        lvl, tx, ty, bits, t = atlas
+        lz, ly, lx = level_shape((nz, ny, nx), lvl)
+        dt = (torch.uint16, torch.int16) if bits == 16 else torch.uint8
+        spec = C.byref(vr_atlas_spec(int(lvl), int(tx), int(ty), int(bits),
+                                     _dev(t, "atlas", dt, tx * ty * lx * ly).value))
     _check(lib().vr_threshold_downsample(_dev(vol, "vol", _U16), nx, ny, nz, kb, int(n_levels),
-                                         ptrs, _stream(stream)))
+                                         ptrs, spec, _stream(stream)))
     return levels
 
 
@@ -181,10 +213,11 @@ def vr_pack_slicemap(level, tiles_x, tiles_y, out_bits=16, out=None, stream=None
 
 
 # ------------------------------------------------------------------ rendering
-def vr_brick_count(nx, ny, nz) -> int:
-    n = C.c_int64(0)
-    _check(lib().vr_brick_count(nx, ny, nz, C.byref(n)))
-    return int(n.value)
+def vr_brick_count(nx, ny, nz):
+    """-> (number of 4^3 bricks, bytes of the occupancy grids)."""
+    n, o = C.c_int64(0), C.c_int64(0)
+    _check(lib().vr_brick_count(nx, ny, nz, C.byref(n), C.byref(o)))
+    return int(n.value), int(o.value)
 
 
 class BrickedVolume:
@@ -199,13 +232,13 @@ class BrickedVolume:
 def vr_brick_volume(src, out=None, with_occupancy=True, stream=None) -> BrickedVolume:
     """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy)."""
     nz, ny, nx = src.shape
-    nb = vr_brick_count(nx, ny, nz)
+    nb, nocc = vr_brick_count(nx, ny, nz)
     dt = U16_NORM if src.dtype in _U16 else F32
     if out is None:
         data = torch.empty(nb * 64, dtype=src.dtype, device=src.device)
-        occ = torch.empty(nb, dtype=torch.uint8, device=src.device) if with_occupancy else None
+        occ = torch.empty(nocc, dtype=torch.uint8, device=src.device) if with_occupancy else None
         out = BrickedVolume(data, (nz, ny, nx), occ)
-    occp = None if out.occupancy is None else _dev(out.occupancy, "occupancy", torch.uint8, nb)
+    occp = None if out.occupancy is None else _dev(out.occupancy, "occupancy", torch.uint8, nocc)
     _check(lib().vr_brick_volume(_dev(src, "src", (*_U16, torch.float32)), dt, nx, ny, nz,
                                  _dev(out.data, "bricked", src.dtype, nb * 64), occp,
                                  _stream(stream)))
@@ -253,13 +286,14 @@ def make_opts(width, height, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0)):
 
 def vr_raycast(data, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
                bg=(0.0, 0.0, 0.0, 0.0), out=None, samples=None, stream=None):
-    """RGBA frames [V][H][W][4] float32; `samples` (int64[1]) accumulates the sample count."""
+    """RGBA frames [V][H][W][4] float32; `samples` (int64[2]) accumulates the sample
+    counts: [0] samples taken before early termination, [1] samples evaluated."""
     vol = make_volume(data, spacing)
     ca, nv = make_cameras(cams)
     opts = make_opts(width, height, step, ert_eps, bg)
     if out is None:
         out = torch.empty((nv, height, width, 4), dtype=torch.float32, device=data.device)
-    sp = None if samples is None else _dev(samples, "samples", torch.int64, 1)
+    sp = None if samples is None else _dev(samples, "samples", torch.int64, 2)
     _check(lib().vr_raycast(C.byref(vol), _dev(tf, "tf", torch.float32, 1024), ca, nv,
                             C.byref(opts), _dev(out, "out", torch.float32, nv * height * width * 4),
                             sp, _stream(stream)))

@@ -52,8 +52,15 @@ def test_validation_happens_on_the_host(lib):
     assert lib.vr_select_threshold(C.c_void_p(16), None, 9, 0, C.c_void_p(16), C.c_void_p(16), None) == -3
     assert lib.vr_select_threshold(C.c_void_p(16), None, 0, 0, C.c_void_p(16), C.c_void_p(16), None) == -3
     ptrs = (C.c_void_p * 5)(*([16] * 5))
-    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 5, ptrs, None) == -3
-    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 0, ptrs, None) == -3
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 5, ptrs, None, None) == -3
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 0, ptrs, None, None) == -3
+    from paper_2311_15038_amd import vr
+    spec = vr.vr_atlas_spec(2, 1, 1, 16, 16)       # 1 x 1 tiles cannot hold the 2 slices of level 2
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 2, ptrs, C.byref(spec), None) == -3
+    spec = vr.vr_atlas_spec(3, 4, 4, 16, 16)       # level 3 is not produced
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 2, ptrs, C.byref(spec), None) == -3
+    assert lib.vr_histogram_with_top(C.c_void_p(16), 4, 4, 4, 5, C.c_void_p(16), C.c_void_p(16), None) == -3
+    assert lib.vr_histogram_with_top(C.c_void_p(16), 4, 4, 4, 3, None, C.c_void_p(16), None) == -1
     assert lib.vr_pack_slicemap(C.c_void_p(16), 4, 4, 10, 3, 3, 16, C.c_void_p(16), None) == -3
     assert lib.vr_pack_slicemap(C.c_void_p(16), 4, 4, 9, 3, 3, 12, C.c_void_p(16), None) == -3
 

@@ -61,6 +61,16 @@ def test_histogram_concentrated_bins_carry():
     assert (u64_np(vr.vr_histogram(to_dev_u16(b))) == O.histogram(b)).all()
 
 
+@pytest.mark.parametrize("shape,top", [((128, 128, 128), 3), ((7, 5, 3), 3), ((33, 66, 130), 1),
+                                       ((5, 9, 11), 5)])
+def test_histogram_with_top(shape, top):
+    banner(f"histogram with top {shape} top={top}")
+    a = _rand_vol(shape, 11, 0, 3000)
+    H, Ht = vr.vr_histogram_with_top(to_dev_u16(a), top)
+    assert (u64_np(H) == O.histogram(a)).all()
+    assert (u64_np(Ht) == O.histogram(a, 0, top)).all()
+
+
 def test_histogram_rejects_bad_args():
     v = to_dev_u16(_rand_vol((4, 4, 4), 2))
     with pytest.raises(vr.VrError) as e:
@@ -211,6 +221,24 @@ def test_slicemap(shape, tx, ty, bits):
     want = O.slicemap(L, tx, ty, bits)
     g = u16_np(got) if bits == 16 else got.cpu().numpy()
     assert g.shape == want.shape and (g == want).all()
+
+
+@pytest.mark.parametrize("shape,level,tx,ty,bits", [((64, 64, 64), 2, 4, 4, 16), ((34, 66, 130), 1, 5, 4, 16),
+                                                     ((37, 23, 19), 2, 3, 4, 8), ((128, 128, 128), 2, 8, 8, 16)])
+def test_pyramid_with_atlas(shape, level, tx, ty, bits):
+    banner(f"pyramid + atlas {shape} level {level}")
+    a = _rand_vol(shape, 12)
+    keep = np.random.default_rng(13).random(65536) < 0.8
+    bv = O.pack_bits(keep)
+    lz, ly, lx = vr.level_shape(shape, level)
+    dt = torch.uint16 if bits == 16 else torch.uint8
+    atl = torch.full((ty * ly, tx * lx), 77, dtype=torch.int32).to(dt).to(dev())   # stale contents
+    got = vr.vr_threshold_downsample(to_dev_u16(a), bits_to_dev(bv), 2, atlas=(level, tx, ty, bits, atl))
+    want = O.pyramid(a, bv, 2)
+    for k in range(2):
+        assert (u16_np(got[k]) == want[k]).all()
+    g = u16_np(atl) if bits == 16 else atl.cpu().numpy()
+    assert (g == O.slicemap(want[level - 1], tx, ty, bits)).all()
 
 
 def test_slicemap_rejects_too_few_tiles():

@@ -33,13 +33,14 @@ def test_small_config_front_view(level1):
     banner("raycast 64^3 ortho 256^2")
     tf = synth.default_tf()
     cam = synth.front_ortho_camera(64, 64, 64)
-    cnt = torch.zeros(1, dtype=torch.int64, device=dev())
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev())
     img = vr.vr_raycast(to_dev_u16(level1), _tf_dev(tf), cam, 256, 256, 0.5, samples=cnt)
     ref, n_ref = R.render(level1, (1, 1, 1), tf.astype(np.float64), cam, 256, 256, 0.5)
     err = np.abs(img.cpu().numpy() - ref).max()
     assert err <= TOL, err
     assert ref[..., 3].max() > 0.5                        # the view does show the specimen
-    n_gpu = int(cnt.item())
+    n_gpu = int(cnt[0].item())
+    assert int(cnt[1].item()) == n_gpu               # no occupancy: every sample evaluated
     assert abs(n_gpu - int(n_ref[0])) <= 1e-3 * int(n_ref[0]), (n_gpu, n_ref)
 
 
@@ -142,10 +143,14 @@ def _brick_ref(a):
                 for xx in (x - 1, x):
                     if zz >= 0 and yy >= 0 and xx >= 0:
                         occ[zz // 4, yy // 4, xx // 4] = 1
-    return br, occ.reshape(-1)
+    mz, my, mx = (nbz + 3) // 4, (nby + 3) // 4, (nbx + 3) // 4
+    pad = np.zeros((mz * 4, my * 4, mx * 4), dtype=np.uint8)
+    pad[:nbz, :nby, :nbx] = occ
+    macro = pad.reshape(mz, 4, my, 4, mx, 4).max(axis=(1, 3, 5))
+    return br, np.concatenate([occ.reshape(-1), macro.reshape(-1)])
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (70, 33, 81)])
 def test_brick_layout_and_occupancy(shape):
     banner(f"brick layout {shape}")
     rng = np.random.default_rng(31)
@@ -179,7 +184,7 @@ def _sparse_volume(shape, seed):
     return np.clip(a, 0, 65535).astype(np.uint16)
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (29, 23, 37), (40, 17, 50)])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (29, 23, 37), (40, 17, 50), (90, 70, 110)])
 def test_brick_and_skip_bit_identical(level1, shape):
     banner(f"bricked+skip == linear {shape}")
     a = level1 if shape == (64, 64, 64) else _sparse_volume(shape, 5)
@@ -188,16 +193,18 @@ def test_brick_and_skip_bit_identical(level1, shape):
     cams = np.concatenate([synth.turntable_cameras(nx, ny, nz, n_views=7),
                            synth.front_ortho_camera(nx, ny, nz)])
     v = to_dev_u16(a)
-    c0 = torch.zeros(1, dtype=torch.int64, device=dev())
-    c1 = torch.zeros(1, dtype=torch.int64, device=dev())
-    c2 = torch.zeros(1, dtype=torch.int64, device=dev())
+    c0 = torch.zeros(2, dtype=torch.int64, device=dev())
+    c1 = torch.zeros(2, dtype=torch.int64, device=dev())
+    c2 = torch.zeros(2, dtype=torch.int64, device=dev())
     lin = vr.vr_raycast(v, tf, cams, 45, 38, 0.5, samples=c0)
     bv = vr.vr_brick_volume(v)
     skip = vr.vr_raycast(bv, tf, cams, 45, 38, 0.5, samples=c1)
     bv.occupancy = None
     noskip = vr.vr_raycast(bv, tf, cams, 45, 38, 0.5, samples=c2)
     assert torch.equal(lin, noskip) and torch.equal(lin, skip)
-    assert c0.item() == c1.item() == c2.item()
+    assert c0[0].item() == c1[0].item() == c2[0].item()
+    assert c0[1].item() == c0[0].item() and c2[1].item() == c2[0].item()
+    assert c1[1].item() <= c1[0].item()               # skipped samples are counted, not evaluated
     if shape != (64, 64, 64):
         ref, n_ref = R.render(a, (1, 1, 1), synth.default_tf(sigma_scale=3.0).astype(np.float64),
                               cams, 45, 38, 0.5)
