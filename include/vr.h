@@ -266,6 +266,66 @@ int vr_raycast_backward(const vr_volume* vol, const float* d_tf, const vr_camera
                         const float* d_grad_rgba, float* d_grad_density, float* d_grad_tf,
                         void* stream);
 
+/*
+ * Batched previews in one persistent launch (beyond the paper: many scans
+ * processed together, as a preview service would).  For every item: both
+ * histograms (vr_histogram_with_top), threshold selection, the fused level-1
+ * pyramid step, the brick layout with occupancy of level 1, and n_views
+ * frames ray cast from level 1 (vr_raycast semantics; the cameras are in the
+ * level-1 volume's world frame, whose voxel size is `spacing`).  One launch
+ * of a persistent kernel (one workgroup per compute unit) runs a device task
+ * queue with per-item dependency counters; the launch can be captured into a
+ * HIP graph (vr_batch_capture) and replayed.  Results equal those of the
+ * single-volume calls (bit-identical reduction, and bit-identical frames for
+ * the same bricked level).
+ *
+ * The caller provides one workspace of vr_batch_workspace_size bytes holding
+ * every intermediate (histograms, masks, levels, bricks, occupancy, task
+ * table, counters); the plan keeps pointers into it.  The first call of the
+ * plan's lifetime initialises it (synchronously); launches never allocate.
+ * Items must not change between launches (their pointers are in the plan).
+ */
+typedef struct vr_batch_plan vr_batch_plan;
+
+typedef struct {
+    const uint16_t* d_vol;     /* [nz][ny][nx] u16 */
+    int64_t nx, ny, nz;
+    double spacing[3];         /* world units per level-1 voxel (> 0) */
+    int32_t n_views;           /* 1..VR_MAX_VIEWS_PER_LAUNCH */
+    const vr_camera* h_cams;   /* host, read during plan creation */
+    float* d_frames;           /* [n_views][height][width][4] f32 */
+} vr_batch_item;
+
+typedef struct {
+    int32_t width, height;     /* frame size of every view */
+    float step, ert_eps;       /* as vr_render_opts */
+    float bg[4];
+    int32_t rule, rule_param;  /* as vr_select_threshold */
+    int32_t top_slices;        /* slices of the top histogram (3 in the paper) */
+    int32_t wave_w, wave_h;    /* ray tile of one wave, wave_w * wave_h == 64 */
+    int32_t waves_x;           /* waves across a render task's tile (16 waves per task; divides 16) */
+    int64_t hist_task_voxels;  /* voxels per histogram task (>= 8192) */
+    int32_t down_tiles_per_task;   /* 64x16x16 tiles per pyramid task */
+    int32_t slabs_per_task;    /* 16-brick slabs per brick task */
+    int32_t render_tiles_per_task; /* must be 1 */
+} vr_batch_config;
+
+int vr_batch_workspace_size(const vr_batch_item* items, int n_items, const vr_batch_config* cfg,
+                            int64_t* bytes);
+int vr_batch_plan_create(const vr_batch_item* items, int n_items, const vr_batch_config* cfg,
+                         const float* d_tf, void* d_workspace, int64_t workspace_bytes,
+                         vr_batch_plan** plan);
+/* One persistent launch on `stream` (the captured graph once vr_batch_capture ran). */
+int vr_batch_launch(vr_batch_plan* plan, void* stream);
+/* Capture the launch into a HIP graph; later vr_batch_launch calls replay it. */
+int vr_batch_capture(vr_batch_plan* plan, void* stream);
+/* Synchronous: status != 0 if a task timed out waiting; samples [taken, evaluated] so far. */
+int vr_batch_status(vr_batch_plan* plan, uint32_t* h_status, uint64_t* h_samples);
+/* Device pointers of an item's level 1 and selection result, and the task count. */
+int vr_batch_item_outputs(const vr_batch_plan* plan, int item, uint16_t** d_level1,
+                          uint32_t** d_result, int64_t* n_tasks);
+int vr_batch_plan_destroy(vr_batch_plan* plan);
+
 /* Message for the last non-zero return on this host thread ("" if none). */
 const char* vr_last_error(void);
 

@@ -1,21 +1,9 @@
-// Render layout of a volume level: 4 x 4 x 4-voxel bricks (a 128-byte line
-// for u16) and an occupancy grid that tells the ray caster where every tap of
-// a trilinear fetch is zero.
-//
-// Brick (bx, by, bz) starts at element ((bz * nby + by) * nbx + bx) * 64 and
-// voxel (x, y, z) sits at ((z & 3) * 16 + (y & 3) * 4 + (x & 3)) inside it.
-// occupancy[b] != 0 iff some non-zero voxel is one of the eight taps of a
-// trilinear fetch whose base tap (the floor corner, clamped to the volume)
-// lies in brick b; a voxel at (x, y, z) is a tap for base taps
-// (x - {0,1}, y - {0,1}, z - {0,1}), so it marks up to eight bricks.  A second
-// grid follows the first: one byte per 4 x 4 x 4 bricks (16^3 voxels), set
-// when any of its bricks is marked, so a ray can cross large empty regions in
-// long steps.
-#include "common.h"
+// Render layout of a volume level (layout and occupancy described in brick_dev.h).
+#include "brick_dev.h"
 
 namespace {
 
-constexpr int kThreads = 256;
+using namespace vr::bk;
 
 __global__ void __launch_bounds__(kThreads) fill_u8(uint8_t* __restrict__ p, int64_t n)
 {
@@ -24,74 +12,14 @@ __global__ void __launch_bounds__(kThreads) fill_u8(uint8_t* __restrict__ p, int
 }
 
 template <typename T>
-__device__ __forceinline__ bool nonzero(T v) { return v != (T)0; }
-
-// A workgroup converts a 64 x 4 x 4-voxel slab (16 bricks along x) at brick
-// row (by, bz): thread t reads 4 voxels of volume row (t / 16) at x offset
-// 4 (t % 16), which is row t / 16 of brick t % 16.  The slab goes through LDS
-// in brick order so that stores are 16-byte pieces of whole bricks.  The
-// occupancy marks of the slab (its 16 bricks and the neighbours at -1 in x, y
-// and z) are gathered in LDS and written once per workgroup.
-template <typename T>
 __global__ void __launch_bounds__(kThreads)
 brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
              T* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx,
              int nmy)
 {
-    __shared__ __align__(16) T slab[16 * 64];
-    __shared__ uint32_t marks[17 * 2 * 2];      // (bx - 1 .. bx + 15) x (by - 1, by) x (bz - 1, bz)
-    const int t = threadIdx.x;
-    const int bx0 = blockIdx.x * 16, by = blockIdx.y, bz = blockIdx.z;
-    if (t < 17 * 4) marks[t] = 0;
-    __syncthreads();
-    const int r = t >> 4, lb = t & 15;          // row inside the brick, brick within the slab
-    const int y = by * 4 + (r & 3), z = bz * 4 + (r >> 2), x0 = (bx0 + lb) * 4;
-    T v[4];
-    const bool rowok = y < ny && z < nz;
-    const T* row = src + ((int64_t)z * ny + y) * nx;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = (rowok && x0 + e < nx) ? row[x0 + e] : (T)0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) slab[lb * 64 + r * 4 + e] = v[e];
-    if (occ != nullptr) {
-        bool any = false;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) any |= nonzero(v[e]);
-        if (any) {
-            // a voxel at x marks the base-tap bricks of x and x - 1 (and likewise in y, z)
-            const int xs[2] = {lb + 1, nonzero(v[0]) ? lb : -1};          // index into -1..15 (+1)
-            const int ys[2] = {1, (r & 3) == 0 ? 0 : -1};
-            const int zs[2] = {1, (r >> 2) == 0 ? 0 : -1};
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        if (xs[a] >= 0 && ys[b] >= 0 && zs[c] >= 0)
-                            marks[(zs[c] * 2 + ys[b]) * 17 + xs[a]] = 1u;
-        }
-    }
-    __syncthreads();
-    // whole bricks out: 16 bricks x 64 voxels, 16 bytes per store
-    constexpr int kPer = 16 / sizeof(T);
-    const int nb_here = min(16, nbx - bx0);
-    for (int q = t; q < 16 * 64 / kPer; q += kThreads) {
-        const int e = q * kPer;
-        if (e / 64 < nb_here) {
-            const int64_t brick = ((int64_t)bz * nby + by) * nbx + bx0 + e / 64;
-            *reinterpret_cast<uint4*>(dst + (brick << 6) + (e & 63)) =
-                *reinterpret_cast<const uint4*>(slab + e);
-        }
-    }
-    if (occ != nullptr && t < 17 * 4) {
-        const int xi = t % 17, yi = (t / 17) & 1, zi = t / 34;
-        const int bx = bx0 + xi - 1, byy = by + yi - 1, bzz = bz + zi - 1;
-        if (marks[t] && bx >= 0 && bx < nbx && byy >= 0 && bzz >= 0) {
-            occ[((int64_t)bzz * nby + byy) * nbx + bx] = 1;
-            macro[((int64_t)(bzz >> 2) * nmy + (byy >> 2)) * nmx + (bx >> 2)] = 1;
-        }
-    }
+    __shared__ SlabLds<T> G;
+    slab_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, blockIdx.x * 16, blockIdx.y,
+                 blockIdx.z, true, threadIdx.x, G);
 }
 
 }  // namespace

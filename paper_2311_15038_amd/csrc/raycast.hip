@@ -12,198 +12,13 @@
 // the adjoint replay bit-identical transmittances and stop at the same sample.
 #include <cmath>
 
-#include "common.h"
+#include "raycast_dev.h"
 
 namespace {
 
+using namespace vr::rc;
+
 constexpr int kThreads = 256;
-constexpr int kTile = 16;
-constexpr int kMaxViews = VR_MAX_VIEWS_PER_LAUNCH;
-
-struct View {
-    float eye[3];   // perspective origin, or centre of the orthographic view
-    float f[3];     // unit forward
-    float r[3];     // right, scaled by tan(fov/2) or by the orthographic half height
-    float u[3];     // up, scaled likewise
-    float persp;    // 1: perspective, 0: orthographic
-};
-
-struct Views {
-    View v[kMaxViews];
-};
-
-struct Scene {
-    const void* data;
-    const uint8_t* occ;     // brick occupancy or NULL
-    int nx, ny, nz;
-    int nbx, nby, nbz;      // 4^3 bricks per axis
-    int nmx, nmy, nmz;      // 16^3 groups of bricks per axis
-    uint32_t macro_off;     // byte offset of the group occupancy
-    float inv_sp[3];
-    float ext[3];
-    int W, H;
-    float aspect;
-    float step, eps;
-    float bg[4];
-    int view0;
-    int tiles_x, tiles_y;
-};
-
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + min(x, r) + i;
-}
-
-// Everything one sample needs: the eight tap offsets, the trilinear weights
-// and the interpolated (normalised) density.
-struct Sample {
-    uint32_t off[8];   // (x, y, z) taps in order x fastest: 000 100 010 110 001 101 011 111
-    float wx, wy, wz;
-    float s;
-};
-
-template <typename T>
-__device__ __forceinline__ float voxel(const T* p, uint32_t i);
-template <>
-__device__ __forceinline__ float voxel<uint16_t>(const uint16_t* p, uint32_t i) { return (float)p[i]; }
-template <>
-__device__ __forceinline__ float voxel<float>(const float* p, uint32_t i) { return p[i]; }
-
-__device__ __forceinline__ float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
-
-// Offsets of the eight taps (x fastest: 000 100 010 110 001 101 011 111) of
-// the clamped tap corners, in the linear or the 4^3-brick layout.
-template <int LAYOUT>
-__device__ __forceinline__ void tap_offsets(const Scene& S, uint32_t x0, uint32_t x1, uint32_t y0,
-                                            uint32_t y1, uint32_t z0, uint32_t z1, uint32_t off[8])
-{
-    uint32_t ax0, ax1, ay0, ay1, az0, az1;
-    if (LAYOUT == VR_LAYOUT_LINEAR) {
-        const uint32_t nx = (uint32_t)S.nx, nxy = (uint32_t)S.nx * (uint32_t)S.ny;
-        ax0 = x0; ax1 = x1;
-        ay0 = y0 * nx; ay1 = y1 * nx;
-        az0 = z0 * nxy; az1 = z1 * nxy;
-    } else {
-        const uint32_t row = (uint32_t)S.nbx << 6, slab = row * (uint32_t)S.nby;
-        ax0 = ((x0 >> 2) << 6) | (x0 & 3u); ax1 = ((x1 >> 2) << 6) | (x1 & 3u);
-        ay0 = (y0 >> 2) * row + ((y0 & 3u) << 2); ay1 = (y1 >> 2) * row + ((y1 & 3u) << 2);
-        az0 = (z0 >> 2) * slab + ((z0 & 3u) << 4); az1 = (z1 >> 2) * slab + ((z1 & 3u) << 4);
-    }
-    off[0] = az0 + ay0 + ax0; off[1] = az0 + ay0 + ax1;
-    off[2] = az0 + ay1 + ax0; off[3] = az0 + ay1 + ax1;
-    off[4] = az1 + ay0 + ax0; off[5] = az1 + ay0 + ax1;
-    off[6] = az1 + ay1 + ax0; off[7] = az1 + ay1 + ax1;
-}
-
-// Base tap corner (clamped) and trilinear weights of the point p.
-struct Cell {
-    uint32_t x0, x1, y0, y1, z0, z1;
-    float wx, wy, wz;
-};
-
-__device__ __forceinline__ Cell cell_at(const Scene& S, float px, float py, float pz)
-{
-    Cell c;
-    const float ux = fmaf(px, S.inv_sp[0], -0.5f);
-    const float uy = fmaf(py, S.inv_sp[1], -0.5f);
-    const float uz = fmaf(pz, S.inv_sp[2], -0.5f);
-    const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
-    c.wx = ux - fx;
-    c.wy = uy - fy;
-    c.wz = uz - fz;
-    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    c.x0 = (uint32_t)min(max(ix, 0), S.nx - 1); c.x1 = (uint32_t)min(max(ix + 1, 0), S.nx - 1);
-    c.y0 = (uint32_t)min(max(iy, 0), S.ny - 1); c.y1 = (uint32_t)min(max(iy + 1, 0), S.ny - 1);
-    c.z0 = (uint32_t)min(max(iz, 0), S.nz - 1); c.z1 = (uint32_t)min(max(iz + 1, 0), S.nz - 1);
-    return c;
-}
-
-template <typename T, int LAYOUT>
-__device__ __forceinline__ void sample(const Scene& S, const T* __restrict__ vol, const Cell& c,
-                                       Sample& sm)
-{
-    sm.wx = c.wx;
-    sm.wy = c.wy;
-    sm.wz = c.wz;
-    tap_offsets<LAYOUT>(S, c.x0, c.x1, c.y0, c.y1, c.z0, c.z1, sm.off);
-    float v[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = voxel<T>(vol, sm.off[t]);
-    const float c0 = lerpf(lerpf(v[0], v[1], sm.wx), lerpf(v[2], v[3], sm.wx), sm.wy);
-    const float c1 = lerpf(lerpf(v[4], v[5], sm.wx), lerpf(v[6], v[7], sm.wx), sm.wy);
-    const float s = lerpf(c0, c1, sm.wz);
-    sm.s = (sizeof(T) == 2) ? s * (1.0f / 65535.0f) : s;
-}
-
-struct TfHit {
-    int k;
-    float w;
-    float4 q;
-};
-
-__device__ __forceinline__ TfHit tf_lookup(const float4* tf, float s)
-{
-    TfHit h;
-    const float x = fminf(fmaxf(s, 0.0f), 1.0f) * 255.0f;
-    h.k = min((int)x, 254);
-    h.w = x - (float)h.k;
-    const float4 a = tf[h.k], b = tf[h.k + 1];
-    h.q = make_float4(lerpf(a.x, b.x, h.w), lerpf(a.y, b.y, h.w), lerpf(a.z, b.z, h.w),
-                      lerpf(a.w, b.w, h.w));
-    return h;
-}
-
-// Ray for pixel (i, j): entry point p, unit direction d, segment length L.
-__device__ __forceinline__ bool setup_ray(const View& v, const Scene& S, int i, int j, float p[3],
-                                          float d[3], float& L)
-{
-    const float ndc_x = ((2.0f * ((float)i + 0.5f)) / (float)S.W - 1.0f) * S.aspect;
-    const float ndc_y = 1.0f - (2.0f * ((float)j + 0.5f)) / (float)S.H;
-    float o[3];
-    if (v.persp != 0.0f) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            o[a] = v.eye[a];
-            d[a] = fmaf(ndc_y, v.u[a], fmaf(ndc_x, v.r[a], v.f[a]));
-        }
-        const float nrm = sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
-        d[0] /= nrm;
-        d[1] /= nrm;
-        d[2] /= nrm;
-    } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            o[a] = fmaf(ndc_y, v.u[a], fmaf(ndc_x, v.r[a], v.eye[a]));
-            d[a] = v.f[a];
-        }
-    }
-    float tin = -INFINITY, tout = INFINITY;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0f) {
-            if (o[a] < 0.0f || o[a] > S.ext[a]) return false;
-            continue;
-        }
-        const float ta = (0.0f - o[a]) / d[a];
-        const float tb = (S.ext[a] - o[a]) / d[a];
-        tin = fmaxf(tin, fminf(ta, tb));
-        tout = fminf(tout, fmaxf(ta, tb));
-    }
-    tin = fmaxf(tin, 0.0f);
-    if (!(tout > tin)) return false;
-    L = tout - tin;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) p[a] = fmaf(tin, d[a], o[a]);
-    return true;
-}
-
-// n = max(1, ceil(L/step - 2^-10)): a segment that is a whole number of steps
-// up to the rounding of its clipped length gets no extra sliver of a step.
-__device__ __forceinline__ int step_count(float L, float step)
-{
-    return max(1, (int)ceilf(L / step - (1.0f / 1024.0f)));
-}
 
 __device__ __forceinline__ void pixel_of(const Scene& S, int nb, int& view, int& i, int& j)
 {
@@ -217,29 +32,6 @@ __device__ __forceinline__ void pixel_of(const Scene& S, int nb, int& view, int&
     j = ty * kTile + (w >> 1) * 8 + (lane >> 3);
 }
 
-// Index of the first sample past the base-tap region of an empty cell (a
-// brick, sh = 2, or a 16^3 group of bricks, sh = 4): the base tap stays in
-// cell (cx, cy, cz) while u = u0 + s g lies in [cell << sh, (cell + 1) << sh)
-// on every axis; the first and last cells of an axis extend to infinity,
-// since taps are clamped.  Samples whose offset is below the exit minus a
-// margin are in the cell; the sample at the returned index is checked again.
-__device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const float g[3],
-                                       const uint32_t cell[3], const int ncell[3], int sh, int k, int n)
-{
-    float s_exit = INFINITY;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (g[a] > 0.0f && (int)cell[a] < ncell[a] - 1)
-            s_exit = fminf(s_exit, ((float)((cell[a] + 1u) << sh) - u0[a]) / g[a]);
-        else if (g[a] < 0.0f && cell[a] > 0u)
-            s_exit = fminf(s_exit, ((float)(cell[a] << sh) - u0[a]) / g[a]);
-    }
-    const float lim = (s_exit - S.step * (1.0f / 256.0f) - 0.5f * S.step) / S.step;
-    int next = n;
-    if (lim < (float)n) next = (int)ceilf(lim);
-    return min(max(next, k + 1), n);
-}
-
 template <typename T, int LAYOUT>
 __global__ void __launch_bounds__(kThreads)
 raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4* __restrict__ out,
@@ -248,66 +40,13 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
     __shared__ float4 tf_s[256];
     tf_s[threadIdx.x] = tf[threadIdx.x];
     __syncthreads();
-    // empty bricks may be passed over only if density 0 has zero extinction
-    const bool skip = S.occ != nullptr && tf_s[0].w == 0.0f && isfinite(tf_s[0].x) &&
-                      isfinite(tf_s[0].y) && isfinite(tf_s[0].z);
+    const bool skip = can_skip(S, tf_s);
     int view, i, j;
     pixel_of(S, (int)gridDim.x, view, i, j);
-    const T* vol = static_cast<const T*>(S.data);
     unsigned long long cnt = 0, evals = 0;
     if (i < S.W && j < S.H) {
-        const View& v = V.v[view];
-        float p[3], d[3], L;
-        float4 res = make_float4(S.bg[0], S.bg[1], S.bg[2], S.bg[3]);
-        if (setup_ray(v, S, i, j, p, d, L)) {
-            const int n = step_count(L, S.step);
-            const float last = L - (float)(n - 1) * S.step;
-            float u0[3], g[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                u0[a] = fmaf(p[a], S.inv_sp[a], -0.5f);
-                g[a] = d[a] * S.inv_sp[a];
-            }
-            float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-            int k = 0;
-            while (k < n) {
-                const float len = (k < n - 1) ? S.step : last;
-                const float off = fmaf(0.5f, len, (float)k * S.step);
-                const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
-                if (skip && S.occ[((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2)] == 0) {
-                    // empty brick: leave its 16^3 group if that is empty too, else the brick
-                    const uint32_t m[3] = {c.x0 >> 4, c.y0 >> 4, c.z0 >> 4};
-                    const bool coarse = S.occ[S.macro_off + (m[2] * (uint32_t)S.nmy + m[1]) * (uint32_t)S.nmx + m[0]] == 0;
-                    int next;
-                    if (coarse) {
-                        const int nm[3] = {S.nmx, S.nmy, S.nmz};
-                        next = skip_to(S, u0, g, m, nm, 4, k, n);
-                    } else {
-                        const uint32_t b[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                        const int nb[3] = {S.nbx, S.nby, S.nbz};
-                        next = skip_to(S, u0, g, b, nb, 2, k, n);
-                    }
-                    cnt += (unsigned long long)(next - k);
-                    k = next;
-                    continue;
-                }
-                Sample sm;
-                sample<T, LAYOUT>(S, vol, c, sm);
-                const TfHit h = tf_lookup(tf_s, sm.s);
-                const float e = __expf(-(h.q.w * len));
-                const float ta = Tr * (1.0f - e);
-                cr = fmaf(ta, h.q.x, cr);
-                cg = fmaf(ta, h.q.y, cg);
-                cb = fmaf(ta, h.q.z, cb);
-                Tr = Tr * e;
-                ++cnt;
-                ++evals;
-                ++k;
-                if (Tr < S.eps) break;
-            }
-            res = make_float4(fmaf(Tr, S.bg[0], cr), fmaf(Tr, S.bg[1], cg), fmaf(Tr, S.bg[2], cb),
-                              1.0f - Tr * (1.0f - S.bg[3]));
-        }
+        const float4 res = march<T, LAYOUT>(S, V.v[view], static_cast<const T*>(S.data), tf_s, skip, i, j,
+                                            cnt, evals);
         out[((int64_t)(S.view0 + view) * S.H + j) * S.W + i] = res;
     }
     if (samples) {
@@ -411,110 +150,6 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
         const float x = gtf_s[q];
         if (x != 0.0f) atomicAdd(gtf + q, x);
     }
-}
-
-int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams, int n_views,
-                const vr_render_opts* o, Scene& S)
-{
-    VR_REQUIRE(vol && d_tf && h_cams && o, VR_ERR_NULL, "raycast: NULL argument");
-    VR_REQUIRE(vol->data != nullptr, VR_ERR_NULL, "raycast: volume data is NULL");
-    VR_REQUIRE(vol->dtype == VR_U16_NORM || vol->dtype == VR_F32, VR_ERR_DTYPE,
-               "raycast: unknown dtype %d", vol->dtype);
-    VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4, VR_ERR_RANGE,
-               "raycast: unknown layout %d", vol->layout);
-    VR_REQUIRE(vol->nx >= 1 && vol->ny >= 1 && vol->nz >= 1 && vol->nx < (1 << 30) &&
-                   vol->ny < (1 << 30) && vol->nz < (1 << 30),
-               VR_ERR_DIMS, "raycast: volume dims %lld x %lld x %lld", (long long)vol->nx,
-               (long long)vol->ny, (long long)vol->nz);
-    const int64_t nb[3] = {(vol->nx + 3) / 4, (vol->ny + 3) / 4, (vol->nz + 3) / 4};
-    const int64_t elems = vol->layout == VR_LAYOUT_BRICK4 ? nb[0] * nb[1] * nb[2] * 64
-                                                          : vol->nx * vol->ny * vol->nz;
-    VR_REQUIRE(elems <= (int64_t)0xFFFFFFFFu, VR_ERR_DIMS,
-               "raycast: volume of %lld elements exceeds 32-bit offsets", (long long)elems);
-    for (int a = 0; a < 3; ++a)
-        VR_REQUIRE(std::isfinite(vol->spacing[a]) && vol->spacing[a] > 0.0, VR_ERR_RANGE,
-                   "raycast: spacing[%d] = %g", a, vol->spacing[a]);
-    VR_REQUIRE(n_views >= 1, VR_ERR_DIMS, "raycast: n_views %d", n_views);
-    VR_REQUIRE(o->width >= 1 && o->height >= 1 && o->width <= 32768 && o->height <= 32768,
-               VR_ERR_DIMS, "raycast: image %d x %d", o->width, o->height);
-    VR_REQUIRE(std::isfinite(o->step) && o->step > 0.0f, VR_ERR_RANGE, "raycast: step %g",
-               (double)o->step);
-    VR_REQUIRE(std::isfinite(o->ert_eps) && o->ert_eps >= 0.0f && o->ert_eps < 1.0f, VR_ERR_RANGE,
-               "raycast: ert_eps %g", (double)o->ert_eps);
-    {   // bound the samples per ray: the box diagonal over the step
-        double diag2 = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            const double e = (double)(a == 0 ? vol->nx : a == 1 ? vol->ny : vol->nz) * vol->spacing[a];
-            diag2 += e * e;
-        }
-        VR_REQUIRE(std::sqrt(diag2) / (double)o->step <= (double)(1 << 24), VR_ERR_RANGE,
-                   "raycast: step %g gives more than 2^24 samples per ray", (double)o->step);
-    }
-    for (int v = 0; v < n_views; ++v) {
-        const vr_camera& c = h_cams[v];
-        VR_REQUIRE(c.fov_y_deg == 0.0 ? (std::isfinite(c.ortho_half_h) && c.ortho_half_h > 0.0)
-                                      : (c.fov_y_deg > 0.0 && c.fov_y_deg < 180.0),
-                   VR_ERR_RANGE, "raycast: camera %d has fov %g / half height %g", v, c.fov_y_deg,
-                   c.ortho_half_h);
-    }
-    S.data = vol->data;
-    S.occ = vol->occupancy;
-    S.nbx = (int)nb[0];
-    S.nby = (int)nb[1];
-    S.nbz = (int)nb[2];
-    S.nmx = (S.nbx + 3) / 4;
-    S.nmy = (S.nby + 3) / 4;
-    S.nmz = (S.nbz + 3) / 4;
-    S.macro_off = (uint32_t)(nb[0] * nb[1] * nb[2]);
-    S.nx = (int)vol->nx;
-    S.ny = (int)vol->ny;
-    S.nz = (int)vol->nz;
-    const int64_t n[3] = {vol->nx, vol->ny, vol->nz};
-    for (int a = 0; a < 3; ++a) {
-        S.inv_sp[a] = (float)(1.0 / vol->spacing[a]);
-        S.ext[a] = (float)((double)n[a] * vol->spacing[a]);
-    }
-    S.W = o->width;
-    S.H = o->height;
-    S.aspect = (float)((double)o->width / (double)o->height);
-    S.step = o->step;
-    S.eps = o->ert_eps;
-    for (int c = 0; c < 4; ++c) S.bg[c] = o->bg[c];
-    S.tiles_x = (o->width + kTile - 1) / kTile;
-    S.tiles_y = (o->height + kTile - 1) / kTile;
-    return VR_OK;
-}
-
-int build_views(const vr_camera* cams, int count, Views& V)
-{
-    for (int k = 0; k < count; ++k) {
-        const vr_camera& c = cams[k];
-        double f[3], r[3], u[3];
-        for (int a = 0; a < 3; ++a) f[a] = c.target[a] - c.eye[a];
-        double lf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-        VR_REQUIRE(lf > 0.0 && std::isfinite(lf), VR_ERR_RANGE, "raycast: camera eye == target");
-        for (int a = 0; a < 3; ++a) f[a] /= lf;
-        r[0] = f[1] * c.up[2] - f[2] * c.up[1];
-        r[1] = f[2] * c.up[0] - f[0] * c.up[2];
-        r[2] = f[0] * c.up[1] - f[1] * c.up[0];
-        double lr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-        VR_REQUIRE(lr > 0.0 && std::isfinite(lr), VR_ERR_RANGE, "raycast: camera up is parallel to the view");
-        for (int a = 0; a < 3; ++a) r[a] /= lr;
-        u[0] = r[1] * f[2] - r[2] * f[1];
-        u[1] = r[2] * f[0] - r[0] * f[2];
-        u[2] = r[0] * f[1] - r[1] * f[0];
-        const bool persp = c.fov_y_deg > 0.0;
-        const double sc = persp ? std::tan(0.5 * c.fov_y_deg * M_PI / 180.0) : c.ortho_half_h;
-        View& v = V.v[k];
-        for (int a = 0; a < 3; ++a) {
-            v.eye[a] = (float)c.eye[a];
-            v.f[a] = (float)f[a];
-            v.r[a] = (float)(sc * r[a]);
-            v.u[a] = (float)(sc * u[a]);
-        }
-        v.persp = persp ? 1.0f : 0.0f;
-    }
-    return VR_OK;
 }
 
 }  // namespace

@@ -49,6 +49,21 @@ class vr_atlas_spec(C.Structure):
                 ("out_bits", C.c_int32), ("data", C.c_void_p)]
 
 
+class vr_batch_item(C.Structure):
+    _fields_ = [("d_vol", C.c_void_p), ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("spacing", C.c_double * 3), ("n_views", C.c_int32), ("h_cams", C.c_void_p),
+                ("d_frames", C.c_void_p)]
+
+
+class vr_batch_config(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("step", C.c_float),
+                ("ert_eps", C.c_float), ("bg", C.c_float * 4), ("rule", C.c_int32),
+                ("rule_param", C.c_int32), ("top_slices", C.c_int32), ("wave_w", C.c_int32),
+                ("wave_h", C.c_int32), ("waves_x", C.c_int32), ("hist_task_voxels", C.c_int64),
+                ("down_tiles_per_task", C.c_int32), ("slabs_per_task", C.c_int32),
+                ("render_tiles_per_task", C.c_int32)]
+
+
 class vr_render_opts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("step", C.c_float),
                 ("ert_eps", C.c_float), ("bg", C.c_float * 4)]
@@ -78,11 +93,22 @@ def lib():
                                           C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
         L.vr_brick_volume.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
         L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        PB = C.POINTER(vr_batch_item)
+        PC = C.POINTER(vr_batch_config)
+        L.vr_batch_workspace_size.argtypes = [PB, i32, PC, C.POINTER(C.c_int64)]
+        L.vr_batch_plan_create.argtypes = [PB, i32, PC, vp, vp, i64, C.POINTER(vp)]
+        L.vr_batch_launch.argtypes = [vp, vp]
+        L.vr_batch_capture.argtypes = [vp, vp]
+        L.vr_batch_status.argtypes = [vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]
+        L.vr_batch_item_outputs.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64)]
+        L.vr_batch_plan_destroy.argtypes = [vp]
         L.vr_last_error.restype = C.c_char_p
         L.vr_version.restype = C.c_char_p
         for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
                      "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
-                     "vr_brick_count", "vr_histogram_with_top"):
+                     "vr_brick_count", "vr_histogram_with_top", "vr_batch_workspace_size",
+                     "vr_batch_plan_create", "vr_batch_launch", "vr_batch_capture", "vr_batch_status",
+                     "vr_batch_item_outputs", "vr_batch_plan_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -314,3 +340,45 @@ def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba
         _dev(grad_density, "grad_density", torch.float32, int(np.prod(vol_shape(data)))),
         _dev(grad_tf, "grad_tf", torch.float32, 1024), _stream(stream)))
     return grad_density, grad_tf
+
+
+# ------------------------------------------------------------------ batching
+def vr_batch_workspace_size(items, cfg) -> int:
+    arr = (vr_batch_item * len(items))(*items)
+    n = C.c_int64(0)
+    _check(lib().vr_batch_workspace_size(arr, len(items), C.byref(cfg), C.byref(n)))
+    return int(n.value)
+
+
+def vr_batch_plan_create(items, cfg, tf, workspace):
+    arr = (vr_batch_item * len(items))(*items)
+    plan = C.c_void_p(None)
+    _check(lib().vr_batch_plan_create(arr, len(items), C.byref(cfg), _dev(tf, "tf", torch.float32, 1024),
+                                      _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                                      C.byref(plan)))
+    return plan
+
+
+def vr_batch_launch(plan, stream=None):
+    _check(lib().vr_batch_launch(plan, _stream(stream)))
+
+
+def vr_batch_capture(plan, stream=None):
+    _check(lib().vr_batch_capture(plan, _stream(stream)))
+
+
+def vr_batch_status(plan):
+    st = C.c_uint32(0)
+    sm = (C.c_uint64 * 2)()
+    _check(lib().vr_batch_status(plan, C.byref(st), sm))
+    return int(st.value), (int(sm[0]), int(sm[1]))
+
+
+def vr_batch_item_outputs(plan, item):
+    lv, res, nt = C.c_void_p(None), C.c_void_p(None), C.c_int64(0)
+    _check(lib().vr_batch_item_outputs(plan, item, C.byref(lv), C.byref(res), C.byref(nt)))
+    return lv.value, res.value, int(nt.value)
+
+
+def vr_batch_plan_destroy(plan):
+    _check(lib().vr_batch_plan_destroy(plan))
