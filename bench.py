@@ -1,6 +1,6 @@
 """Benchmark of the preview hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-extras] [--serve-seconds S]
 
 One step = one pass of the whole path over the 1024^3 u16 volume resident in
 HBM: histogram of the volume and of its first three slices, valley threshold
@@ -8,8 +8,9 @@ HBM: histogram of the volume and of its first three slices, valley threshold
 and 36 perspective turntable frames of 512^2 ray cast from the 512^3 level
 (step 0.5).  Prints one JSON line.  `value` is rendered samples per second of
 whole-step wall time (reduction included); the reduction's own bandwidth, the
-per-kernel times, the forward+backward fit iteration and the oracle's CPU
-rate are reported beside it.
+per-kernel times and the oracle's CPU rate are reported beside it, then the
+forward+backward fit iteration, the batched persistent launch of 64 uneven
+volumes and the serving loop, each against the plain single-volume path.
 """
 from __future__ import annotations
 
@@ -154,6 +155,119 @@ def run_fwd_bwd(pipe, iters=5):
             "samples_fwd": int(cnt[0].item()), "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
 
 
+def _median_ms(fn, reps=5):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ev = _events(2 * reps)
+    for r in range(reps):
+        ev[2 * r].record()
+        fn()
+        ev[2 * r + 1].record()
+    torch.cuda.synchronize()
+    return sorted(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(reps))[reps // 2]
+
+
+def run_batched(n_volumes=64, n_views=12, res=256):
+    """64 volumes of uneven shape (each axis uniform in 64..512), each with its
+    own threshold, 2x level and 12 turntable views at 256^2: one persistent
+    graph-replayed launch with the tuned launch shape, against the plain
+    single-volume pipeline run volume after volume on one stream."""
+    import torch
+
+    from paper_2311_15038_amd import batch as VB
+    from paper_2311_15038_amd import pipeline as P
+    from paper_2311_15038_amd import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    vols = [synth.make_volume(s, dev) for s in synth.batch_specs(n_volumes)]
+    torch.cuda.synchronize()
+    voxels = sum(v.numel() for v in vols)
+    log(f"batched: generated {n_volumes} volumes ({voxels} voxels) in {time.time() - t0:.1f} s")
+    best, timings = VB.tune(vols, n_views=n_views, width=res, height=res, use_cache=False)
+    log(f"batched: tuned over {len(timings)} launch shapes: {best}")
+    b = VB.BatchPreview(vols, n_views=n_views, width=res, height=res, tuning=best)
+    b.launch()
+    torch.cuda.synchronize()
+    st, (taken, evald) = b.status()
+    b.capture()
+    batched_ms = _median_ms(b.launch)
+    st2, _ = b.status()
+    b.close()
+    pipes = [P.PreviewPipeline(v.shape, P.PreviewConfig(n_levels=1, atlas_level=0, n_views=n_views,
+                                                         width=res, height=res), device=dev)
+             for v in vols]
+
+    def plain():
+        for v, p in zip(vols, pipes):
+            p.step(v)
+
+    plain_ms = _median_ms(plain)
+    del pipes, vols
+    torch.cuda.empty_cache()
+    return {"volumes": n_volumes, "voxels": voxels, "views_per_volume": n_views, "image": [res, res],
+            "batched_ms": batched_ms, "plain_ms": plain_ms, "speedup": plain_ms / batched_ms,
+            "samples": taken, "evaluated": evald,
+            "batched_Gsamples_per_s": taken / (batched_ms * 1e-3) / 1e9,
+            "plain_Gsamples_per_s": taken / (plain_ms * 1e-3) / 1e9,
+            "tuning": best, "status": max(st, st2)}
+
+
+def run_served(seconds=20.0, warmup_s=5.0, rate=50.0, slots=4, budget_gib=64.0, burst=200):
+    """Poisson preview requests (50/s; cubic volumes log-uniform 128^3..1024^3
+    from a pool of 64; 1..36 views at 256^2 or 512^2) served by the
+    continuous-batching loop with resident volumes, against the plain path
+    (one request at a time, every request loads and reduces its volume), on
+    the same arrival trace.  Then the capacity of each from a burst of
+    requests on resident volumes (all arriving at once)."""
+    import torch
+
+    from paper_2311_15038_amd import serve as S
+
+    trace, edges = S.make_trace(rate=rate, duration=warmup_s + seconds, pool=64, seed=5000)
+    t0 = time.time()
+    served_ex = S.GpuExecutor(edges, slots=slots)
+    for v in range(len(edges)):
+        served_ex.host_volume(v)
+        if v % 16 == 15:
+            log(f"served: {v + 1} of 64 volumes in the host store ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    store_bytes = sum(h.numel() * 2 for h in served_ex.store.values())
+    log(f"served: host store of 64 volumes ({store_bytes / 2**30:.1f} GiB pinned) in "
+        f"{time.time() - t0:.1f} s; {len(trace)} requests over {warmup_s + seconds:.0f} s")
+    budget = int(budget_gib * 2**30)
+    out = {"rate_per_s": rate, "seconds": seconds, "warmup_s": warmup_s, "slots": slots,
+           "budget_bytes": budget, "requests": len(trace), "pool": 64,
+           "edges": [int(e) for e in edges]}
+    srv = S.Server(served_ex, budget, slots=slots)
+    out["served"] = srv.run(trace, warmup=warmup_s).summary()
+    log(f"served: {out['served']}")
+    plain_ex = S.GpuExecutor(edges, slots=1, store=served_ex.store)
+    plain = S.Server(plain_ex, budget, slots=1, resident=False)
+    out["plain"] = plain.run(S.copy_trace(trace), warmup=warmup_s).summary()
+    log(f"plain: {out['plain']}")
+    # capacity on resident volumes: the served loop vs one request at a time
+    bt = S.copy_trace(trace[:burst], burst=True)
+    cap = S.Server(served_ex, budget, slots=slots)
+    cap.resident.update(srv.resident)             # the volumes the served run left resident
+    cap_s = cap.run(bt).summary()
+    one = S.Server(served_ex, budget, slots=1)
+    one.resident.update(srv.resident)
+    one_s = one.run(S.copy_trace(trace[:burst], burst=True)).summary()
+    out["capacity"] = {"requests": burst, "served_views_per_s": cap_s["views_per_s"],
+                       "one_slot_views_per_s": one_s["views_per_s"],
+                       "served_loads": cap_s["loads"], "one_slot_loads": one_s["loads"]}
+    log(f"capacity: {out['capacity']}")
+    out["views_per_s_vs_plain"] = out["served"]["views_per_s"] / max(out["plain"]["views_per_s"], 1e-9)
+    out["p99_vs_plain"] = out["served"]["p99_ms"] / max(out["plain"]["p99_ms"], 1e-9)
+    served_ex.vols.clear()
+    served_ex.store.clear()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(pipe, vol, budget_s=12.0):
     """The oracle, untuned, on a bounded sample of the same step."""
     import numpy as np
@@ -202,6 +316,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="measured window of the serving trace (after 5 s of warm-up)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
@@ -258,14 +374,26 @@ def main():
         "kernel_GB_per_s": {k: b / (res["kernel_ms"][k] * 1e-3) / 1e9
                             for k, b in res["kernel_bytes"].items()},
     }
-    if not args.no_extras:
-        try:
-            fb = run_fwd_bwd(pipe)
-            line["fwd_bwd"] = fb
-        except Exception as e:  # reported, not hidden
-            line["fwd_bwd"] = {"error": repr(e)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(pipe, vol)
+    if not args.no_extras:
+        try:
+            line["fwd_bwd"] = run_fwd_bwd(pipe)
+        except Exception as e:  # reported, not hidden
+            line["fwd_bwd"] = {"error": repr(e)}
+        log(f"fwd_bwd: {line['fwd_bwd']}")
+        del pipe, vol
+        import torch
+        torch.cuda.empty_cache()
+        try:
+            line["batched"] = run_batched()
+        except Exception as e:
+            line["batched"] = {"error": repr(e)}
+        log(f"batched: {line['batched']}")
+        try:
+            line["served"] = run_served(seconds=args.serve_seconds)
+        except Exception as e:
+            line["served"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)
 
 

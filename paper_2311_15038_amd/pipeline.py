@@ -21,7 +21,7 @@ from . import synth, vr
 @dataclass
 class PreviewConfig:
     n_levels: int = 4
-    atlas_level: int = 2            # level packed into the slicemap atlas
+    atlas_level: int = 2            # level packed into the slicemap atlas (0: none)
     render_level: int = 1           # level the frames are rendered from
     n_views: int = 36
     width: int = 512
@@ -56,10 +56,12 @@ class PreviewPipeline:
         self.keep = torch.empty(vr.KEEP_WORDS, dtype=torch.int32, device=dev)
         self.levels = [torch.empty(vr.level_shape(self.shape, k), dtype=torch.uint16, device=dev)
                        for k in range(1, cfg.n_levels + 1)]
-        az, ay, ax = self.levels[cfg.atlas_level - 1].shape
-        self.tiles = atlas_tiles(az)
-        self.atlas = torch.empty((self.tiles[1] * ay, self.tiles[0] * ax), dtype=torch.uint16,
-                                 device=dev)
+        self.tiles, self.atlas = None, None
+        if cfg.atlas_level > 0:
+            az, ay, ax = self.levels[cfg.atlas_level - 1].shape
+            self.tiles = atlas_tiles(az)
+            self.atlas = torch.empty((self.tiles[1] * ay, self.tiles[0] * ax), dtype=torch.uint16,
+                                     device=dev)
         rz, ry, rx = self.levels[cfg.render_level - 1].shape
         self.render_shape = (rz, ry, rx)
         if cfg.ortho:
@@ -77,6 +79,11 @@ class PreviewPipeline:
             self.render_vol = vr.BrickedVolume(torch.empty(nb * 64, dtype=torch.uint16, device=dev),
                                                (rz, ry, rx), occ)
 
+    def _atlas_arg(self):
+        if self.atlas is None:
+            return None
+        return (self.cfg.atlas_level, self.tiles[0], self.tiles[1], 16, self.atlas)
+
     # the reduction half: three launches-worth of calls (histograms, selection,
     # pyramid with its atlas written in the same pass)
     def reduce(self, vol, stream=None):
@@ -84,8 +91,7 @@ class PreviewPipeline:
         vr.vr_histogram_with_top(vol, c.top_slices, self.hist, self.hist_top, stream)
         vr.vr_select_threshold(self.hist, self.hist_top, c.rule, c.rule_param, self.result,
                                self.keep, stream)
-        vr.vr_threshold_downsample(vol, self.keep, c.n_levels, self.levels,
-                                   (c.atlas_level, self.tiles[0], self.tiles[1], 16, self.atlas),
+        vr.vr_threshold_downsample(vol, self.keep, c.n_levels, self.levels, self._atlas_arg(),
                                    stream)
 
     def render(self, stream=None, count=False):
@@ -111,8 +117,7 @@ class PreviewPipeline:
             ("select", lambda: vr.vr_select_threshold(self.hist, self.hist_top, c.rule,
                                                       c.rule_param, self.result, self.keep, stream)),
             ("pyramid+atlas", lambda: vr.vr_threshold_downsample(
-                vol, self.keep, c.n_levels, self.levels,
-                (c.atlas_level, self.tiles[0], self.tiles[1], 16, self.atlas), stream)),
+                vol, self.keep, c.n_levels, self.levels, self._atlas_arg(), stream)),
         ]
         level = self.levels[c.render_level - 1]
         src = level
@@ -133,6 +138,8 @@ class PreviewPipeline:
         vol = nx * ny * nz * 2
         top = nx * ny * min(self.cfg.top_slices, nz) * 2
         lv = sum(l.numel() * 2 for l in self.levels)
-        at_in = self.levels[self.cfg.atlas_level - 1].numel() * 2
-        at_out = self.atlas.numel() * 2
+        at_in = at_out = 0
+        if self.atlas is not None:
+            at_in = self.levels[self.cfg.atlas_level - 1].numel() * 2
+            at_out = self.atlas.numel() * 2
         return vol + top + vol + lv + at_in + at_out
