@@ -105,9 +105,12 @@ def run_gpu(steps, warmup):
     return out, pipe, vol
 
 
-def run_fwd_bwd(pipe, iters=5):
-    """One fit iteration: 16 turntable views at 256^2 of a 256^3 f32 grid
-    (spacing 2, step 1 = half its voxel) against renders of the 512^3 level."""
+def run_fwd_bwd(pipe, steps=200):
+    """The 200-step Adam fit: 16 turntable views at 256^2 of a 256^3 f32 grid
+    (spacing 2, step 1 = half its voxel, initialised from the 256^3 level)
+    against renders of the 512^3 level.  Reports the time per iteration
+    (forward, adjoint, Adam; after two untimed ones) beside the forward alone,
+    and the loss at the first and last step."""
     import torch
 
     from paper_2311_15038_amd import autograd as VA
@@ -122,37 +125,43 @@ def run_fwd_bwd(pipe, iters=5):
     dens = (pipe.levels[1].to(torch.float32) / 65535.0).contiguous().requires_grad_(True)
     tfp = tf.clone().requires_grad_(True)
     opt = torch.optim.Adam([dens, tfp], lr=1e-2)
+    losses = torch.zeros(steps, dtype=torch.float32, device=dev)
 
-    def it():
+    def it(i):
         opt.zero_grad(set_to_none=False)
         img = VA.render(dens, tfp, cams, 256, 256, 1.0, (2.0, 2.0, 2.0))
         loss = ((img - target) ** 2).mean()
         loss.backward()
         opt.step()
-        return loss
+        losses[i] = loss.detach()
 
-    for _ in range(2):
-        it()
+    for i in range(2):
+        it(i)
     torch.cuda.synchronize()
     e = _events(2)
     e[0].record()
-    for _ in range(iters):
-        it()
+    for i in range(2, steps):
+        it(i)
     e[1].record()
     torch.cuda.synchronize()
-    it_ms = e[0].elapsed_time(e[1]) / iters
+    it_ms = e[0].elapsed_time(e[1]) / (steps - 2)
+    lo = losses.cpu().tolist()
     with torch.no_grad():
         cnt = torch.zeros(2, dtype=torch.int64, device=dev)
         fe = _events(2)
         fe[0].record()
-        for _ in range(iters):
+        for _ in range(5):
             vr.vr_raycast(dens.detach(), tfp.detach(), cams, 256, 256, 1.0, (2.0, 2.0, 2.0))
         fe[1].record()
         vr.vr_raycast(dens.detach(), tfp.detach(), cams, 256, 256, 1.0, (2.0, 2.0, 2.0), samples=cnt)
         torch.cuda.synchronize()
-        fwd_ms = fe[0].elapsed_time(fe[1]) / iters
+        fwd_ms = fe[0].elapsed_time(fe[1]) / 5
+    n_fwd = int(cnt[0].item())
     return {"ms_per_iter": it_ms, "fwd_ms": fwd_ms, "iter_over_fwd": it_ms / fwd_ms,
-            "samples_fwd": int(cnt[0].item()), "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
+            "samples_fwd": n_fwd, "fwd_Gsamples_per_s": n_fwd / (fwd_ms * 1e-3) / 1e9,
+            "iter_Gsamples_per_s": n_fwd / (it_ms * 1e-3) / 1e9,
+            "steps": steps, "loss_first": lo[0], "loss_last": lo[-1],
+            "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
 
 
 def _median_ms(fn, reps=5):
@@ -309,6 +318,28 @@ def cpu_baseline(pipe, vol, budget_s=12.0):
             "reduction_GB_per_s": red_bytes / red_s / 1e9}
 
 
+def traffic_probe():
+    """One step of the path, then a plain copy of known size (1 GiB read, 1 GiB
+    written by one elementwise kernel) that scales the HBM counters."""
+    import torch
+
+    from paper_2311_15038_amd import pipeline as P
+    from paper_2311_15038_amd import synth
+
+    dev = torch.device("cuda:0")
+    vol = synth.make_volume(synth.FULL, dev)
+    pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=dev)
+    torch.cuda.synchronize()
+    pipe.step(vol)
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "traffic", "copy_bytes_read": src.numel() * 4,
+                      "copy_bytes_written": dst.numel() * 4}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +347,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one step plus a 1 GiB elementwise copy, for HBM counter runs")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured window of the serving trace (after 5 s of warm-up)")
     args = ap.parse_args()
@@ -331,6 +364,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
 
+    if args.traffic_probe:
+        traffic_probe()
+        return
     res, pipe, vol = run_gpu(args.steps, args.warmup)
     ms = res["ms_per_step"]
     samples = res["samples_per_step"]

@@ -128,3 +128,38 @@ def test_adjoint_rejects_u16():
     with pytest.raises(vr.VrError):
         vr.vr_raycast_backward(v, tf, cams, 4, 4, 0.5, out, out, torch.zeros(64, device=dev()),
                                torch.zeros(1024, device=dev()))
+
+
+def test_adam_fit_200_steps(small_volume):
+    """Fit a coarse f32 grid (32^3, spacing 2) and the TF to 16 turntable renders of
+    the 64^3 level with 200 Adam steps.  The trajectory depends on the order of the
+    density atomics, so this is a trend check (parity unpinned): the loss falls."""
+    from oracle import reduce as O
+    banner("backward: 200-step Adam fit")
+    H, Ht = O.histogram(small_volume), O.histogram(small_volume, 0, 3)
+    L1 = O.pyramid(small_volume, O.keep_bits(O.valley_threshold(H), Ht), 1)[0]
+    n = L1.shape[0]
+    tf = torch.from_numpy(synth.default_tf(sigma_scale=2.0)).to(dev())
+    cams = synth.turntable_cameras(n, n, n, n_views=16)
+    with torch.no_grad():
+        target = vr.vr_raycast(synth.from_numpy_u16(L1, dev()), tf, cams, 96, 96, 0.5)
+    rng = np.random.default_rng(5)
+    init = 0.1 + 0.05 * rng.random((n // 2,) * 3)
+    dens = torch.tensor(init, dtype=torch.float32, device=dev()).requires_grad_(True)
+    tfp = tf.clone().requires_grad_(True)
+    opt = torch.optim.Adam([dens, tfp], lr=1e-2)
+    losses = []
+    for _ in range(200):
+        opt.zero_grad(set_to_none=False)
+        img = VA.render(dens, tfp, cams, 96, 96, 1.0, (2.0, 2.0, 2.0))
+        loss = ((img - target) ** 2).mean()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            dens.clamp_(0.0, 1.0)
+            tfp.clamp_(min=0.0)
+        losses.append(float(loss.item()))
+    assert all(np.isfinite(losses))
+    first, last = np.mean(losses[:10]), np.mean(losses[-10:])
+    assert losses[-1] < losses[0]
+    assert last < 0.5 * first, (first, last)

@@ -1,0 +1,117 @@
+"""Full-size parity: the 1024^3 volume through the step the benchmark times
+(histograms, selection, fused 4-level pyramid with the 256^3 -> 4096^2 atlas,
+bricked 512^3 level, 36 x 512^2 turntable frames with empty-space skipping).
+
+Checked against the oracle: both histograms in full; the threshold and keep
+mask; every level on sampled 16-slice slabs (box sums never cross them) plus
+level 1 in full (built slab by slab); the atlas as the slicemap of level 2;
+and rendered RGBA on sampled pixels of all 36 views, computed one ray at a
+time by the FP64 oracle from the oracle's own level 1."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import reduce as O
+from oracle import render as R
+from paper_2311_15038_amd import pipeline as P
+from paper_2311_15038_amd import synth
+
+from gpu_util import banner, dev, u16_np, u32_np, u64_np
+
+pytestmark = pytest.mark.gpu
+
+SLAB = 16                       # 2^4 slices: a slab holds whole boxes of every level
+
+
+@pytest.fixture(scope="module")
+def full():
+    banner("fullsize: 1024^3 step")
+    vol = synth.make_volume(synth.FULL, dev())
+    pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=dev())
+    pipe.samples.zero_()
+    pipe.step(vol, count=True)
+    torch.cuda.synchronize()
+    a = u16_np(vol)
+    del vol
+    torch.cuda.empty_cache()
+    H, Ht = O.histogram(a), O.histogram(a, 0, 3)
+    T = O.valley_threshold(H)
+    return pipe, a, H, Ht, T, O.keep_bits(T, Ht)
+
+
+def test_histograms(full):
+    pipe, a, H, Ht, T, bits = full
+    banner("fullsize: histograms")
+    assert int(H.sum()) == a.size
+    assert np.array_equal(u64_np(pipe.hist), H)
+    assert np.array_equal(u64_np(pipe.hist_top), Ht)
+
+
+def test_threshold_and_mask(full):
+    pipe, a, H, Ht, T, bits = full
+    banner(f"fullsize: threshold {T}")
+    assert int(pipe.result[0].item()) == T
+    assert np.array_equal(u32_np(pipe.keep), bits)
+    # the threshold separates air from the outer shell of the generated scene
+    assert 1000 + 3 * 40 < T < 8000 - 3 * 300
+
+
+def test_levels_on_sampled_slabs(full):
+    pipe, a, H, Ht, T, bits = full
+    rng = np.random.default_rng(7)
+    n_slabs = a.shape[0] // SLAB
+    slabs = sorted(set(rng.choice(n_slabs, size=6, replace=False).tolist()) | {0, n_slabs - 1})
+    for s in slabs:
+        banner(f"fullsize: levels of slab {s}")
+        ref = O.pyramid(a[SLAB * s:SLAB * (s + 1)], bits, 4)
+        for k in range(1, 5):
+            z0, z1 = (SLAB * s) >> k, (SLAB * (s + 1)) >> k
+            got = u16_np(pipe.levels[k - 1][z0:z1].contiguous())
+            assert np.array_equal(got, ref[k - 1]), (s, k)
+
+
+def test_atlas_is_slicemap_of_level2(full):
+    pipe, *_ = full
+    banner("fullsize: atlas")
+    L2 = u16_np(pipe.levels[1])
+    tx, ty = pipe.tiles
+    assert np.array_equal(u16_np(pipe.atlas), O.slicemap(L2, tx, ty, 16))
+
+
+@pytest.fixture(scope="module")
+def level1(full):
+    pipe, a, H, Ht, T, bits = full
+    banner("fullsize: oracle level 1, slab by slab")
+    nz = a.shape[0]
+    out = np.empty(O.level_dims(a.shape[2], a.shape[1], nz, 1)[::-1], dtype=np.uint16)
+    for z in range(0, nz, SLAB):
+        out[z // 2:(z + SLAB) // 2] = O.pyramid(a[z:z + SLAB], bits, 1)[0]
+    return out
+
+
+def test_level1_in_full(full, level1):
+    pipe, *_ = full
+    banner("fullsize: level 1 in full")
+    assert np.array_equal(u16_np(pipe.levels[0]), level1)
+
+
+def test_frames_on_sampled_pixels(full, level1):
+    pipe, *_ = full
+    c = pipe.cfg
+    banner("fullsize: sampled pixels of 36 x 512^2")
+    rng = np.random.default_rng(11)
+    n = 1536
+    pix = np.stack([rng.integers(0, len(pipe.cams), n), rng.integers(0, c.height, n),
+                    rng.integers(0, c.width, n)], axis=1)
+    # plus the centre column of every view, where rays cross the whole specimen
+    ctr = np.array([[v, j, c.width // 2] for v in range(len(pipe.cams))
+                    for j in range(0, c.height, 32)])
+    pix = np.concatenate([pix, ctr])
+    ref, _ = R.render_pixels(level1, (1, 1, 1), pipe.tf.cpu().numpy().astype(np.float64),
+                             pipe.cams, c.width, c.height, c.step, pix, c.ert_eps)
+    fr = pipe.frames.cpu().numpy()
+    got = fr[pix[:, 0], pix[:, 1], pix[:, 2]]
+    err = np.abs(got - ref).max()
+    assert err <= 2e-4, err
+    assert ref[:, 3].max() > 0.5                          # the sample sees the specimen
+    assert int(pipe.samples[1].item()) <= int(pipe.samples[0].item())
