@@ -68,7 +68,8 @@ enum { VR_U16_NORM = 0, VR_F32 = 1 };
 /* volume layouts for rendering */
 enum {
     VR_LAYOUT_LINEAR = 0,      /* [nz][ny][nx], x fastest */
-    VR_LAYOUT_BRICK4 = 1       /* 4x4x4 bricks, see vr_brick_volume */
+    VR_LAYOUT_BRICK4 = 1,      /* 4x4x4 bricks, see vr_brick_volume */
+    VR_LAYOUT_BRICK4_PAIRS = 2 /* 4x4x4 bricks of x-tap pairs, see vr_brick_volume */
 };
 
 /*
@@ -172,12 +173,19 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  * when the transfer function's first entry has zero extinction: such samples
  * have density 0 and change neither colour nor transmittance, so the result
  * is bit-identical.
+ * Layout VR_LAYOUT_BRICK4_PAIRS orders elements the same way, but element
+ * (x, y, z) holds two voxels, (x, y, z) then (min(x + 1, nx - 1), y, z)
+ * (two u16 in one 32-bit word, low half first, or two f32): the two x taps
+ * of a trilinear fetch come in one load, at twice the memory.
  *   d_src: [nz][ny][nx] of u16 (dtype VR_U16_NORM) or f32 (VR_F32).
- *   d_bricked: vr_brick_count(...) * 64 elements, overwritten.
+ *   layout: VR_LAYOUT_BRICK4 or VR_LAYOUT_BRICK4_PAIRS.
+ *   d_bricked: vr_brick_count(...) * 64 elements (x2 voxels for pairs),
+ *     16-byte aligned, overwritten.
  *   d_occupancy: NULL or the occupancy_bytes of vr_brick_count, overwritten.
- * Errors: VR_ERR_NULL, VR_ERR_DTYPE, VR_ERR_DIMS, VR_ERR_HIP.
+ * Errors: VR_ERR_NULL, VR_ERR_DTYPE, VR_ERR_DIMS, VR_ERR_RANGE (layout,
+ * alignment), VR_ERR_HIP.
  */
-int vr_brick_volume(const void* d_src, int dtype, int64_t nx, int64_t ny, int64_t nz,
+int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t nx, int64_t ny, int64_t nz,
                     void* d_bricked, uint8_t* d_occupancy, void* stream);
 
 /* Number of 4x4x4 bricks of an nx x ny x nz volume and the size of its
@@ -188,10 +196,10 @@ int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_
 typedef struct {
     const void* data;          /* device pointer in `layout` */
     int32_t dtype;
-    int32_t layout;            /* VR_LAYOUT_LINEAR or VR_LAYOUT_BRICK4 */
+    int32_t layout;            /* VR_LAYOUT_LINEAR, VR_LAYOUT_BRICK4 or VR_LAYOUT_BRICK4_PAIRS */
     int64_t nx, ny, nz;
     double spacing[3];         /* world units per voxel along x, y, z (> 0) */
-    const uint8_t* occupancy;  /* NULL, or the brick occupancy (VR_LAYOUT_BRICK4 only) */
+    const uint8_t* occupancy;  /* NULL, or the brick occupancy (brick layouts only) */
 } vr_volume;
 
 /* A pinhole (fov_y_deg > 0) or orthographic (fov_y_deg == 0) camera. */

@@ -153,13 +153,12 @@ def tune(volumes, n_views=12, width=256, height=256, use_cache=True, log=None, *
             cache = {}
     if use_cache and key in cache:
         return cache[key], {}
-    timings = {}
-    best, best_ms = dict(DEFAULTS), float("inf")
+    timings = {}                  # configuration -> fastest time seen (ms), status-0 runs only
+    best = dict(DEFAULTS)
     ws = None
     # stage 1: render tile shape; stage 2: task sizes with the best tile
-    stages = [[dict(best, wave_w=a, wave_h=b, waves_x=c) for a, b, c in RENDER_TILES]]
     for stage in range(2):
-        cands = stages[0] if stage == 0 else [
+        cands = [dict(best, wave_w=a, wave_h=b, waves_x=c) for a, b, c in RENDER_TILES] if stage == 0 else [
             dict(best, hist_task_voxels=h, down_tiles_per_task=d, slabs_per_task=s)
             for h, d, s in TASK_SIZES]
         for t in cands:
@@ -169,11 +168,12 @@ def tune(volumes, n_views=12, width=256, height=256, use_cache=True, log=None, *
             st, _ = b.status()
             b.close()
             name = json.dumps(t, sort_keys=True)
-            timings[name] = ms
             if log:
                 log(f"tune {t}: {ms:.3f} ms status={st}")
-            if st == 0 and ms < best_ms:
-                best, best_ms = dict(t), ms
+            if st == 0:
+                timings[name] = min(ms, timings.get(name, float("inf")))
+        if timings:
+            best = json.loads(min(timings, key=timings.get))
     if use_cache:
         cache[key] = best
         try:

@@ -88,7 +88,7 @@ union BatchLds {
         uint32_t first, bad;
     } down;
     vr::bk::SlabLds<uint16_t> brick[kT / vr::bk::kThreads];
-    float4 tf[256];
+    vr::rc::TfLds tf;
 };
 
 __device__ inline void wait_ge(const BatchDev& B, const uint32_t* c, uint32_t need)
@@ -208,7 +208,7 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
     case T_RENDER: {
         // a = view, b = tile index
         wait_ge(B, cnt + C_BRICK, it.need[C_BRICK]);
-        if (tid < 256) L.tf[tid] = B.tf[tid];
+        vr::rc::stage_tf(L.tf, B.tf, tid, kT);
         __syncthreads();
         const vr::rc::Scene& S = it.S;
         const bool skip = vr::rc::can_skip(S, L.tf);
@@ -217,13 +217,14 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
         const int tx = (int)(t.b % B.tiles_per_row), ty = (int)(t.b / B.tiles_per_row);
         const int i = tx * tile_w + (w % B.waves_x) * B.wave_w + lane % B.wave_w;
         const int j = ty * tile_h + (w / B.waves_x) * B.wave_h + lane / B.wave_w;
-        unsigned long long c = 0, e = 0;
+        uint32_t cr = 0, er = 0;
         if (i < S.W && j < S.H) {
-            const float4 rgba = vr::rc::march<uint16_t, VR_LAYOUT_BRICK4>(
-                S, it.V.v[t.a], it.bricked, L.tf, skip, i, j, c, e);
+            const float4 rgba = vr::rc::march<uint16_t, VR_LAYOUT_BRICK4, true, false>(
+                S, it.V.v[t.a], it.bricked, L.tf, skip, i, j, cr, er);
             reinterpret_cast<float4*>(it.frames)[((int64_t)t.a * S.H + j) * S.W + i] = rgba;
         }
         if (B.samples) {
+            unsigned long long c = cr, e = er;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 c += __shfl_xor(c, off);
@@ -385,6 +386,8 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
         for (int c = 0; c < 4; ++c) o.bg[c] = cfg->bg[c];
         int rc = vr::rc::build_scene(&vol, reinterpret_cast<const float*>(16), in.h_cams, in.n_views, &o, it.S);
         if (rc) return rc;
+        VR_REQUIRE(!vr::rc::needs_wide(it.S), VR_ERR_DIMS,
+                   "vr_batch_plan_create: item %d has a level of more than 2^24 bricks", v);
         it.S.data = it.bricked;
         it.S.occ = it.occ;
         it.S.view0 = 0;

@@ -11,15 +11,24 @@ __global__ void __launch_bounds__(kThreads) fill_u8(uint8_t* __restrict__ p, int
         p[i] = 0;
 }
 
-template <typename T>
+template <typename T, bool PAIRS>
 __global__ void __launch_bounds__(kThreads)
 brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
-             T* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx,
-             int nmy)
+             typename ElemOf<T, PAIRS>::type* __restrict__ dst, uint8_t* __restrict__ occ,
+             uint8_t* __restrict__ macro, int nmx, int nmy)
 {
-    __shared__ SlabLds<T> G;
-    slab_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, blockIdx.x * 16, blockIdx.y,
-                 blockIdx.z, true, threadIdx.x, G);
+    __shared__ SlabLds<T, PAIRS> G;
+    slab_body<T, PAIRS>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, blockIdx.x * 16, blockIdx.y,
+                        blockIdx.z, true, threadIdx.x, G);
+}
+
+template <typename T, bool PAIRS>
+void launch_brick(dim3 grid, hipStream_t s, const void* src, int nx, int ny, int nz, int nbx, int nby,
+                  void* dst, uint8_t* occ, uint8_t* macro, int nmx, int nmy)
+{
+    brick_kernel<T, PAIRS><<<grid, kThreads, 0, s>>>(
+        static_cast<const T*>(src), nx, ny, nz, nbx, nby,
+        static_cast<typename ElemOf<T, PAIRS>::type*>(dst), occ, macro, nmx, nmy);
 }
 
 }  // namespace
@@ -38,13 +47,15 @@ extern "C" int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bri
     return VR_OK;
 }
 
-extern "C" int vr_brick_volume(const void* d_src, int dtype, int64_t nx, int64_t ny, int64_t nz,
-                               void* d_bricked, uint8_t* d_occupancy, void* stream)
+extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t nx, int64_t ny,
+                               int64_t nz, void* d_bricked, uint8_t* d_occupancy, void* stream)
 {
     vr::clear_error();
     VR_REQUIRE(d_src && d_bricked, VR_ERR_NULL, "vr_brick_volume: NULL pointer");
     VR_REQUIRE(dtype == VR_U16_NORM || dtype == VR_F32, VR_ERR_DTYPE, "vr_brick_volume: dtype %d",
                dtype);
+    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS, VR_ERR_RANGE,
+               "vr_brick_volume: layout %d is not a brick layout", layout);
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
                VR_ERR_DIMS, "vr_brick_volume: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
                (long long)nz);
@@ -64,15 +75,15 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int64_t nx, int64_t
         if (rc) return rc;
     }
     const dim3 grid((unsigned)vr::ceil_div(nbx, 16), (unsigned)nby, (unsigned)nbz);
-    if (dtype == VR_U16_NORM)
-        brick_kernel<uint16_t><<<grid, kThreads, 0, s>>>(
-            static_cast<const uint16_t*>(d_src), (int)nx, (int)ny, (int)nz, nbx, nby,
-            static_cast<uint16_t*>(d_bricked), d_occupancy,
-            d_occupancy ? d_occupancy + bricks : nullptr, nmx, nmy);
-    else
-        brick_kernel<float><<<grid, kThreads, 0, s>>>(
-            static_cast<const float*>(d_src), (int)nx, (int)ny, (int)nz, nbx, nby,
-            static_cast<float*>(d_bricked), d_occupancy,
-            d_occupancy ? d_occupancy + bricks : nullptr, nmx, nmy);
+    uint8_t* macro = d_occupancy ? d_occupancy + bricks : nullptr;
+    const bool pairs = layout == VR_LAYOUT_BRICK4_PAIRS;
+    const int inx = (int)nx, iny = (int)ny, inz = (int)nz;
+    if (dtype == VR_U16_NORM) {
+        if (pairs) launch_brick<uint16_t, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
+        else launch_brick<uint16_t, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
+    } else {
+        if (pairs) launch_brick<float, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
+        else launch_brick<float, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
+    }
     return vr::check_launch("vr_brick_volume");
 }

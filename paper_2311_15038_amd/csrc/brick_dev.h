@@ -12,6 +12,10 @@
 // grid follows the first: one byte per 4 x 4 x 4 bricks (16^3 voxels), set
 // when any of its bricks is marked, so a ray can cross large empty regions in
 // long steps.
+//
+// Pair variant: the same brick order, but element (x, y, z) holds the two x
+// taps (voxel x and voxel min(x + 1, nx - 1)), so a trilinear fetch reads
+// four elements instead of eight voxels.  Elements past the volume's end are 0.
 #pragma once
 
 #include "common.h"
@@ -24,10 +28,22 @@ constexpr int kThreads = 256;      // threads of one slab group
 template <typename T>
 __device__ __forceinline__ bool nonzero(T v) { return v != (T)0; }
 
+// Element of the pair layout: (voxel x, voxel x + 1) in one load.
+template <typename T> struct PairOf;
+template <> struct PairOf<uint16_t> { typedef uint32_t type; };
+template <> struct PairOf<float> { typedef float2 type; };
+
+__device__ __forceinline__ uint32_t make_pair(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+__device__ __forceinline__ float2 make_pair(float lo, float hi) { return make_float2(lo, hi); }
+
+// Element type of a layout: the voxel, or its x pair.
+template <typename T, bool PAIRS> struct ElemOf { typedef T type; };
+template <typename T> struct ElemOf<T, true> { typedef typename PairOf<T>::type type; };
+
 // LDS of one slab group.
-template <typename T>
+template <typename T, bool PAIRS = false>
 struct SlabLds {
-    __align__(16) T slab[16 * 64];
+    __align__(16) typename ElemOf<T, PAIRS>::type slab[16 * 64];
     uint32_t marks[17 * 2 * 2];      // (bx - 1 .. bx + 15) x (by - 1, by) x (bz - 1, bz)
 };
 
@@ -39,11 +55,13 @@ struct SlabLds {
 // bricks and the neighbours at -1 in x, y and z) are gathered in LDS and
 // written once per slab, to the brick grid and to the 16^3 group grid.
 // Inactive groups take the same barriers.
-template <typename T>
+template <typename T, bool PAIRS = false>
 __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
-                                 T* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro,
-                                 int nmx, int nmy, int bx0, int by, int bz, bool active, int t, SlabLds<T>& G)
+                                 typename ElemOf<T, PAIRS>::type* __restrict__ dst, uint8_t* __restrict__ occ,
+                                 uint8_t* __restrict__ macro, int nmx, int nmy, int bx0, int by, int bz,
+                                 bool active, int t, SlabLds<T, PAIRS>& G)
 {
+    typedef typename ElemOf<T, PAIRS>::type P;
     if (t < 17 * 4) G.marks[t] = 0;
     __syncthreads();
     const int r = t >> 4, lb = t & 15;          // row inside the brick, brick within the slab
@@ -54,8 +72,18 @@ __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int 
         const T* row = src + ((int64_t)z * ny + y) * nx;
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] = (rowok && x0 + e < nx) ? row[x0 + e] : (T)0;
+        if constexpr (PAIRS) {
+            // the voxel after the four (clamped to the row's last voxel)
+            const T nxt = (rowok && x0 + 4 < nx) ? row[x0 + 4] : v[3];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) G.slab[lb * 64 + r * 4 + e] = v[e];
+            for (int e = 0; e < 4; ++e) {
+                const T hi = (x0 + e + 1 < nx) ? (e < 3 ? v[e + 1] : nxt) : v[e];
+                G.slab[lb * 64 + r * 4 + e] = make_pair(v[e], hi);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) G.slab[lb * 64 + r * 4 + e] = v[e];
+        }
         if (occ != nullptr) {
             bool any = false;
 #pragma unroll
@@ -78,8 +106,8 @@ __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int 
     }
     __syncthreads();
     if (!active) return;
-    // whole bricks out: 16 bricks x 64 voxels, 16 bytes per store
-    constexpr int kPer = 16 / sizeof(T);
+    // whole bricks out: 16 bricks x 64 elements, 16 bytes per store
+    constexpr int kPer = 16 / sizeof(P);
     const int nb_here = min(16, nbx - bx0);
     for (int q = t; q < 16 * 64 / kPer; q += kThreads) {
         const int e = q * kPer;

@@ -32,31 +32,48 @@ __device__ __forceinline__ void pixel_of(const Scene& S, int nb, int& view, int&
     j = ty * kTile + (w >> 1) * 8 + (lane >> 3);
 }
 
-template <typename T, int LAYOUT>
+template <typename T, int LAYOUT, bool COUNT, bool WIDE>
 __global__ void __launch_bounds__(kThreads)
 raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4* __restrict__ out,
             unsigned long long* __restrict__ samples)
 {
-    __shared__ float4 tf_s[256];
-    tf_s[threadIdx.x] = tf[threadIdx.x];
+    __shared__ TfLds tf_s;
+    stage_tf(tf_s, tf, (int)threadIdx.x, kThreads);
     __syncthreads();
     const bool skip = can_skip(S, tf_s);
     int view, i, j;
     pixel_of(S, (int)gridDim.x, view, i, j);
-    unsigned long long cnt = 0, evals = 0;
+    uint32_t cnt = 0, evals = 0;
     if (i < S.W && j < S.H) {
-        const float4 res = march<T, LAYOUT>(S, V.v[view], static_cast<const T*>(S.data), tf_s, skip, i, j,
-                                            cnt, evals);
+        const float4 res = march<T, LAYOUT, COUNT, WIDE>(S, V.v[view], static_cast<const T*>(S.data), tf_s,
+                                                         skip, i, j, cnt, evals);
         out[((int64_t)(S.view0 + view) * S.H + j) * S.W + i] = res;
     }
-    if (samples) {
+    if (COUNT) {
+        unsigned long long c = cnt, e = evals;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            cnt += __shfl_xor(cnt, off);
-            evals += __shfl_xor(evals, off);
+            c += __shfl_xor(c, off);
+            e += __shfl_xor(e, off);
         }
-        if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(samples, cnt);
-        if ((threadIdx.x & 63) == 0 && evals) atomicAdd(samples + 1, evals);
+        if ((threadIdx.x & 63) == 0 && c) atomicAdd(samples, c);
+        if ((threadIdx.x & 63) == 0 && e) atomicAdd(samples + 1, e);
+    }
+}
+
+// One forward launch with the kernel variant for the volume's type, layout,
+// counting and addressing width.
+template <typename T, int LAYOUT>
+void launch_fwd(unsigned blocks, hipStream_t s, const Views& V, const Scene& S, const float4* tf, float4* out,
+                unsigned long long* cnt)
+{
+    const bool wide = needs_wide(S);
+    if (cnt) {
+        if (wide) raycast_fwd<T, LAYOUT, true, true><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+        else raycast_fwd<T, LAYOUT, true, false><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+    } else {
+        if (wide) raycast_fwd<T, LAYOUT, false, true><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+        else raycast_fwd<T, LAYOUT, false, false><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
     }
 }
 
@@ -175,13 +192,16 @@ extern "C" int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_came
         auto* out = reinterpret_cast<float4*>(d_rgba);
         auto* cnt = reinterpret_cast<unsigned long long*>(d_samples);
         const auto* tf = reinterpret_cast<const float4*>(d_tf);
-        const bool brick = vol->layout == VR_LAYOUT_BRICK4;
+        const unsigned nb = (unsigned)blocks;
+        const int L = vol->layout;
         if (vol->dtype == VR_U16_NORM) {
-            if (brick) raycast_fwd<uint16_t, VR_LAYOUT_BRICK4><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
-            else raycast_fwd<uint16_t, VR_LAYOUT_LINEAR><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+            if (L == VR_LAYOUT_BRICK4_PAIRS) launch_fwd<uint16_t, VR_LAYOUT_BRICK4_PAIRS>(nb, s, V, S, tf, out, cnt);
+            else if (L == VR_LAYOUT_BRICK4) launch_fwd<uint16_t, VR_LAYOUT_BRICK4>(nb, s, V, S, tf, out, cnt);
+            else launch_fwd<uint16_t, VR_LAYOUT_LINEAR>(nb, s, V, S, tf, out, cnt);
         } else {
-            if (brick) raycast_fwd<float, VR_LAYOUT_BRICK4><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
-            else raycast_fwd<float, VR_LAYOUT_LINEAR><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+            if (L == VR_LAYOUT_BRICK4_PAIRS) launch_fwd<float, VR_LAYOUT_BRICK4_PAIRS>(nb, s, V, S, tf, out, cnt);
+            else if (L == VR_LAYOUT_BRICK4) launch_fwd<float, VR_LAYOUT_BRICK4>(nb, s, V, S, tf, out, cnt);
+            else launch_fwd<float, VR_LAYOUT_LINEAR>(nb, s, V, S, tf, out, cnt);
         }
         rc = vr::check_launch("vr_raycast");
         if (rc) return rc;

@@ -8,6 +8,7 @@
 
 #include <cmath>
 
+#include "brick_dev.h"
 #include "common.h"
 
 namespace vr {
@@ -40,10 +41,36 @@ struct Scene {
     int W, H;
     float aspect;
     float step, eps;
+    float inv_step;         // 1 / step
+    float skip_c;           // sample-centre offset (plus the last step's excess) in skip_to
+    uint32_t row_e, slab_e; // element strides of a brick row and a brick slab (brick layouts)
+    int wide;               // offsets need 64-bit addressing and full multiplies
     float bg[4];
     int view0;
     int tiles_x, tiles_y;
 };
+
+// Margin, in voxel units, by which skip_to stops short of a cell boundary:
+// it covers the rounding of the sample positions (a few ulp of coordinates
+// below 2^13), so a sample whose computed base tap lies past the boundary is
+// never passed over.
+constexpr float kSkipMarginVox = 1.0f / 128.0f;
+
+// Transfer function staged in LDS: the knots and the difference to the next
+// knot, so a lookup is one fma per channel (the same value as lerpf).
+struct TfLds {
+    float4 a[256];
+    float4 d[256];
+};
+
+__device__ __forceinline__ void stage_tf(TfLds& t, const float4* __restrict__ tf, int tid, int nthreads)
+{
+    for (int q = tid; q < 256; q += nthreads) {
+        const float4 a = tf[q], b = tf[q < 255 ? q + 1 : 255];
+        t.a[q] = a;
+        t.d[q] = make_float4(b.x - a.x, b.y - a.y, b.z - a.z, b.w - a.w);
+    }
+}
 
 __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
@@ -150,6 +177,17 @@ __device__ __forceinline__ TfHit tf_lookup(const float4* tf, float s)
     return h;
 }
 
+__device__ __forceinline__ TfHit tf_lookup(const TfLds& t, float s)
+{
+    TfHit h;
+    const float x = fminf(fmaxf(s, 0.0f), 1.0f) * 255.0f;
+    h.k = min((int)x, 254);
+    h.w = x - (float)h.k;
+    const float4 a = t.a[h.k], d = t.d[h.k];
+    h.q = make_float4(fmaf(h.w, d.x, a.x), fmaf(h.w, d.y, a.y), fmaf(h.w, d.z, a.z), fmaf(h.w, d.w, a.w));
+    return h;
+}
+
 // Ray for pixel (i, j): entry point p, unit direction d, segment length L.
 __device__ __forceinline__ bool setup_ray(const View& v, const Scene& S, int i, int j, float p[3],
                                           float d[3], float& L)
@@ -201,95 +239,250 @@ __device__ __forceinline__ int step_count(float L, float step)
     return max(1, (int)ceilf(L / step - (1.0f / 1024.0f)));
 }
 
-// Index of the first sample past the base-tap region of an empty cell (a
-// brick, sh = 2, or a 16^3 group of bricks, sh = 4): the base tap stays in
-// cell (cx, cy, cz) while u = u0 + s g lies in [cell << sh, (cell + 1) << sh)
-// on every axis; the first and last cells of an axis extend to infinity,
-// since taps are clamped.  Samples whose offset is below the exit minus a
-// margin are in the cell; the sample at the returned index is checked again.
+// Index of the first sample that may leave an empty cell (a brick, sh = 2,
+// or a 16^3 group of bricks, sh = 4).  The base tap stays in cell (cx, cy,
+// cz) while u = u0 + s g lies in [cell << sh, (cell + 1) << sh) on every
+// axis; the first and last cells of an axis extend to infinity, since taps
+// are clamped.  Each bound is moved kSkipMarginVox into the cell, which
+// covers the rounding of the sample positions, and the sample-centre offset
+// is taken off in ray distance; ig holds 1/g (0 where g = 0).  Samples below
+// the returned index are in the cell; the sample at it is checked again.
 __device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const float g[3],
-                                       const uint32_t cell[3], const int ncell[3], int sh, int k, int n)
+                                       const float ig[3], const uint32_t cell[3], const int ncell[3],
+                                       int sh, int k, int n)
 {
     float s_exit = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (g[a] > 0.0f && (int)cell[a] < ncell[a] - 1)
-            s_exit = fminf(s_exit, ((float)((cell[a] + 1u) << sh) - u0[a]) / g[a]);
-        else if (g[a] < 0.0f && cell[a] > 0u)
-            s_exit = fminf(s_exit, ((float)(cell[a] << sh) - u0[a]) / g[a]);
+        const bool up = g[a] > 0.0f;
+        const bool open = up ? ((int)cell[a] < ncell[a] - 1) : (g[a] < 0.0f && cell[a] > 0u);
+        const float bound = up ? (float)((cell[a] + 1u) << sh) - kSkipMarginVox
+                               : (float)(cell[a] << sh) + kSkipMarginVox;
+        const float sa = (bound - u0[a]) * ig[a];
+        s_exit = open ? fminf(s_exit, sa) : s_exit;
     }
-    const float lim = (s_exit - S.step * (1.0f / 256.0f) - 0.5f * S.step) / S.step;
+    const float lim = (s_exit - S.skip_c) * S.inv_step;
     int next = n;
     if (lim < (float)n) next = (int)ceilf(lim);
     return min(max(next, k + 1), n);
 }
 
-// Whether samples of empty bricks may be passed over: an occupancy grid is
-// given and density 0 has zero extinction (finite colour), so such samples
-// leave colour and transmittance bit-for-bit unchanged.
-__device__ __forceinline__ bool can_skip(const Scene& S, const float4* tf_s)
+// Whether samples of empty bricks may be passed over: the volume is in the
+// brick layout with an occupancy grid and density 0 has zero extinction
+// (finite colour), so such samples leave colour and transmittance
+// bit-for-bit unchanged.
+__device__ __forceinline__ bool can_skip(const Scene& S, const TfLds& tf)
 {
-    return S.occ != nullptr && tf_s[0].w == 0.0f && isfinite(tf_s[0].x) && isfinite(tf_s[0].y) &&
-           isfinite(tf_s[0].z);
+    return S.occ != nullptr && tf.a[0].w == 0.0f && isfinite(tf.a[0].x) && isfinite(tf.a[0].y) &&
+           isfinite(tf.a[0].z);
 }
 
-// Front-to-back march of the ray through pixel (i, j): returns its RGBA and
-// adds to the counts of samples taken (cnt) and evaluated (evals).
-template <typename T, int LAYOUT>
+template <bool WIDE>
+__device__ __forceinline__ uint32_t mul_idx(uint32_t a, uint32_t b)
+{
+    return WIDE ? a * b : __umul24(a, b);
+}
+
+// Voxel at offset o: in bytes (32-bit, so the load takes a 32-bit offset from
+// the volume base), or in elements with 64-bit addressing when WIDE.
+template <typename T, bool WIDE>
+__device__ __forceinline__ float tap(const T* vol, uint32_t o)
+{
+    if (WIDE) return voxel<T>(vol, o);
+    return voxel<T>(reinterpret_cast<const T*>(reinterpret_cast<const char*>(vol) + o), 0u);
+}
+
+// The eight corner voxels of a cell of a volume in the 4^3-brick layout
+// whose base-tap brick is b, and the key that identifies them (the base
+// offset and which axes are clamped).  Tap offsets are the base offset plus
+// per-axis steps: one voxel inside a brick, or into the next brick when the
+// base tap is on a brick's last layer, or zero where the taps are clamped.
+struct Corners {
+    float v[8];   // x fastest: 000 100 010 110 001 101 011 111
+    uint32_t key_o, key_f;
+};
+
+template <bool WIDE, typename P>
+__device__ __forceinline__ uint32_t base_offset(const Cell& c, uint32_t b)
+{
+    constexpr uint32_t E = WIDE ? 1u : (uint32_t)sizeof(P);   // offsets in elements or bytes
+    const uint32_t in0 = ((c.z0 & 3u) << 4) | ((c.y0 & 3u) << 2) | (c.x0 & 3u);
+    return ((b << 6) | in0) * E;
+}
+
+// Element of a pair-layout volume at offset o (bytes, or elements when
+// WIDE): its two voxels as floats.
+template <bool WIDE>
+__device__ __forceinline__ void tap_pair(const uint16_t* vol, uint32_t o, float& lo, float& hi)
+{
+    const uint32_t w = WIDE ? reinterpret_cast<const uint32_t*>(vol)[o]
+                            : *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(vol) + o);
+    lo = (float)(w & 0xFFFFu);
+    hi = (float)(w >> 16);
+}
+
+template <bool WIDE>
+__device__ __forceinline__ void tap_pair(const float* vol, uint32_t o, float& lo, float& hi)
+{
+    const float2 w = WIDE ? reinterpret_cast<const float2*>(vol)[o]
+                          : *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(vol) + o);
+    lo = w.x;
+    hi = w.y;
+}
+
+// Corners of cell c from a pair-layout volume: four loads, each bringing both
+// x taps.  Where the x taps are clamped to one voxel (x1 == x0) the stored
+// pair may hold the next voxel, so the low voxel is used for both.
+template <typename T, bool WIDE>
+__device__ __forceinline__ void load_corners_pairs(const Scene& S, const T* __restrict__ vol, const Cell& c,
+                                                   uint32_t o0, Corners& k)
+{
+    constexpr uint32_t E = WIDE ? 1u : 2u * (uint32_t)sizeof(T);
+    const uint32_t dy = (c.y1 == c.y0) ? 0u : ((c.y0 & 3u) == 3u ? (S.row_e - 12u) * E : 4u * E);
+    const uint32_t dz = (c.z1 == c.z0) ? 0u : ((c.z0 & 3u) == 3u ? (S.slab_e - 48u) * E : 16u * E);
+    const uint32_t o2 = o0 + dy, o4 = o0 + dz, o6 = o4 + dy;
+    tap_pair<WIDE>(vol, o0, k.v[0], k.v[1]);
+    tap_pair<WIDE>(vol, o2, k.v[2], k.v[3]);
+    tap_pair<WIDE>(vol, o4, k.v[4], k.v[5]);
+    tap_pair<WIDE>(vol, o6, k.v[6], k.v[7]);
+    if (c.x1 == c.x0) {
+        k.v[1] = k.v[0];
+        k.v[3] = k.v[2];
+        k.v[5] = k.v[4];
+        k.v[7] = k.v[6];
+    }
+}
+
+__device__ __forceinline__ uint32_t clamp_flags(const Cell& c)
+{
+    return (c.x1 == c.x0 ? 1u : 0u) | (c.y1 == c.y0 ? 2u : 0u) | (c.z1 == c.z0 ? 4u : 0u);
+}
+
+template <typename T, bool WIDE>
+__device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict__ vol, const Cell& c,
+                                             uint32_t o0, Corners& k)
+{
+    constexpr uint32_t E = WIDE ? 1u : (uint32_t)sizeof(T);
+    const uint32_t dx = (c.x1 == c.x0) ? 0u : ((c.x0 & 3u) == 3u ? 61u * E : E);
+    const uint32_t dy = (c.y1 == c.y0) ? 0u : ((c.y0 & 3u) == 3u ? (S.row_e - 12u) * E : 4u * E);
+    const uint32_t dz = (c.z1 == c.z0) ? 0u : ((c.z0 & 3u) == 3u ? (S.slab_e - 48u) * E : 16u * E);
+    const uint32_t o2 = o0 + dy, o4 = o0 + dz, o6 = o4 + dy;
+    k.v[0] = tap<T, WIDE>(vol, o0);
+    k.v[1] = tap<T, WIDE>(vol, o0 + dx);
+    k.v[2] = tap<T, WIDE>(vol, o2);
+    k.v[3] = tap<T, WIDE>(vol, o2 + dx);
+    k.v[4] = tap<T, WIDE>(vol, o4);
+    k.v[5] = tap<T, WIDE>(vol, o4 + dx);
+    k.v[6] = tap<T, WIDE>(vol, o6);
+    k.v[7] = tap<T, WIDE>(vol, o6 + dx);
+}
+
+// Normalised trilinear density from the corners of cell c.
+template <typename T>
+__device__ __forceinline__ float interp_corners(const Corners& k, const Cell& c)
+{
+    const float c0 = lerpf(lerpf(k.v[0], k.v[1], c.wx), lerpf(k.v[2], k.v[3], c.wx), c.wy);
+    const float c1 = lerpf(lerpf(k.v[4], k.v[5], c.wx), lerpf(k.v[6], k.v[7], c.wx), c.wy);
+    const float sv = lerpf(c0, c1, c.wz);
+    return (sizeof(T) == 2) ? sv * (1.0f / 65535.0f) : sv;
+}
+
+// Front-to-back march of the ray through pixel (i, j): returns its RGBA and,
+// with COUNT, adds to the counts of samples taken (cnt) and evaluated
+// (evals).  WIDE selects 64-bit addressing and full multiplies for volumes
+// of more than 2^24 bricks.
+template <typename T, int LAYOUT, bool COUNT, bool WIDE>
 __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* __restrict__ vol,
-                                        const float4* tf_s, bool skip, int i, int j,
-                                        unsigned long long& cnt, unsigned long long& evals)
+                                        const TfLds& tf, bool skip, int i, int j, uint32_t& cnt,
+                                        uint32_t& evals)
 {
     float p[3], d[3], L;
     if (!setup_ray(v, S, i, j, p, d, L)) return make_float4(S.bg[0], S.bg[1], S.bg[2], S.bg[3]);
     const int n = step_count(L, S.step);
     const float last = L - (float)(n - 1) * S.step;
-    float u0[3], g[3];
+    float u0[3], g[3], ig[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         u0[a] = fmaf(p[a], S.inv_sp[a], -0.5f);
         g[a] = d[a] * S.inv_sp[a];
+        ig[a] = g[a] != 0.0f ? 1.0f / g[a] : 0.0f;
     }
+    const bool skipping = skip && (LAYOUT == VR_LAYOUT_BRICK4 || LAYOUT == VR_LAYOUT_BRICK4_PAIRS);
     float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+    uint32_t cur_b = 0xFFFFFFFFu;
+    bool cur_full = true;
+    Corners kc;                  // corners of the last sampled cell (consecutive samples share
+    kc.key_o = 0xFFFFFFFFu;      // a cell about half the time at half-voxel steps)
+    kc.key_f = 0xFFFFFFFFu;
     int k = 0;
     while (k < n) {
         const float len = (k < n - 1) ? S.step : last;
         const float off = fmaf(0.5f, len, (float)k * S.step);
         const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
-        if (skip && S.occ[((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2)] == 0) {
-            // empty brick: leave its 16^3 group if that is empty too, else the brick
-            const uint32_t m[3] = {c.x0 >> 4, c.y0 >> 4, c.z0 >> 4};
-            const bool coarse = S.occ[S.macro_off + (m[2] * (uint32_t)S.nmy + m[1]) * (uint32_t)S.nmx + m[0]] == 0;
-            int next;
-            if (coarse) {
-                const int nm[3] = {S.nmx, S.nmy, S.nmz};
-                next = skip_to(S, u0, g, m, nm, 4, k, n);
-            } else {
-                const uint32_t b[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                const int nb[3] = {S.nbx, S.nby, S.nbz};
-                next = skip_to(S, u0, g, b, nb, 2, k, n);
+        float sv;
+        if constexpr (LAYOUT == VR_LAYOUT_BRICK4 || LAYOUT == VR_LAYOUT_BRICK4_PAIRS) {
+            const uint32_t b = mul_idx<WIDE>(mul_idx<WIDE>(c.z0 >> 2, (uint32_t)S.nby) + (c.y0 >> 2),
+                                             (uint32_t)S.nbx) + (c.x0 >> 2);
+            if (skipping) {
+                if (b != cur_b) {
+                    cur_b = b;
+                    cur_full = S.occ[b] != 0;
+                }
+                if (!cur_full) {
+                    // empty brick: leave its 16^3 group if that is empty too, else the brick
+                    const uint32_t m[3] = {c.x0 >> 4, c.y0 >> 4, c.z0 >> 4};
+                    const uint32_t mi = mul_idx<WIDE>(mul_idx<WIDE>(m[2], (uint32_t)S.nmy) + m[1],
+                                                      (uint32_t)S.nmx) + m[0];
+                    int next;
+                    if (S.occ[S.macro_off + mi] == 0) {
+                        const int nm[3] = {S.nmx, S.nmy, S.nmz};
+                        next = skip_to(S, u0, g, ig, m, nm, 4, k, n);
+                    } else {
+                        const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
+                        const int nb[3] = {S.nbx, S.nby, S.nbz};
+                        next = skip_to(S, u0, g, ig, bb, nb, 2, k, n);
+                    }
+                    if (COUNT) cnt += (uint32_t)(next - k);
+                    k = next;
+                    continue;
+                }
             }
-            cnt += (unsigned long long)(next - k);
-            k = next;
-            continue;
+            constexpr bool PAIRS = LAYOUT == VR_LAYOUT_BRICK4_PAIRS;
+            const uint32_t o0 = PAIRS ? base_offset<WIDE, typename vr::bk::PairOf<T>::type>(c, b)
+                                      : base_offset<WIDE, T>(c, b);
+            const uint32_t f = clamp_flags(c);
+            if (o0 != kc.key_o || f != kc.key_f) {
+                if (PAIRS) load_corners_pairs<T, WIDE>(S, vol, c, o0, kc);
+                else load_corners<T, WIDE>(S, vol, c, o0, kc);
+                kc.key_o = o0;
+                kc.key_f = f;
+            }
+            sv = interp_corners<T>(kc, c);
+        } else {
+            Sample sm;
+            sample<T, LAYOUT>(S, vol, c, sm);
+            sv = sm.s;
         }
-        Sample sm;
-        sample<T, LAYOUT>(S, vol, c, sm);
-        const TfHit h = tf_lookup(tf_s, sm.s);
+        const TfHit h = tf_lookup(tf, sv);
         const float e = __expf(-(h.q.w * len));
         const float ta = Tr * (1.0f - e);
         cr = fmaf(ta, h.q.x, cr);
         cg = fmaf(ta, h.q.y, cg);
         cb = fmaf(ta, h.q.z, cb);
         Tr = Tr * e;
-        ++cnt;
-        ++evals;
+        if (COUNT) {
+            ++cnt;
+            ++evals;
+        }
         ++k;
         if (Tr < S.eps) break;
     }
     return make_float4(fmaf(Tr, S.bg[0], cr), fmaf(Tr, S.bg[1], cg), fmaf(Tr, S.bg[2], cb),
                        1.0f - Tr * (1.0f - S.bg[3]));
 }
+
+// Whether a volume needs 64-bit addressing and full multiplies in march.
+inline bool needs_wide(const Scene& S) { return S.wide != 0; }
 
 // ------------------------------------------------------------ host side
 
@@ -300,15 +493,16 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
     VR_REQUIRE(vol->data != nullptr, VR_ERR_NULL, "raycast: volume data is NULL");
     VR_REQUIRE(vol->dtype == VR_U16_NORM || vol->dtype == VR_F32, VR_ERR_DTYPE,
                "raycast: unknown dtype %d", vol->dtype);
-    VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4, VR_ERR_RANGE,
-               "raycast: unknown layout %d", vol->layout);
+    VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4 ||
+                   vol->layout == VR_LAYOUT_BRICK4_PAIRS,
+               VR_ERR_RANGE, "raycast: unknown layout %d", vol->layout);
     VR_REQUIRE(vol->nx >= 1 && vol->ny >= 1 && vol->nz >= 1 && vol->nx < (1 << 30) &&
                    vol->ny < (1 << 30) && vol->nz < (1 << 30),
                VR_ERR_DIMS, "raycast: volume dims %lld x %lld x %lld", (long long)vol->nx,
                (long long)vol->ny, (long long)vol->nz);
     const int64_t nb[3] = {(vol->nx + 3) / 4, (vol->ny + 3) / 4, (vol->nz + 3) / 4};
-    const int64_t elems = vol->layout == VR_LAYOUT_BRICK4 ? nb[0] * nb[1] * nb[2] * 64
-                                                          : vol->nx * vol->ny * vol->nz;
+    const bool bricked = vol->layout != VR_LAYOUT_LINEAR;
+    const int64_t elems = bricked ? nb[0] * nb[1] * nb[2] * 64 : vol->nx * vol->ny * vol->nz;
     VR_REQUIRE(elems <= (int64_t)0xFFFFFFFFu, VR_ERR_DIMS,
                "raycast: volume of %lld elements exceeds 32-bit offsets", (long long)elems);
     for (int a = 0; a < 3; ++a)
@@ -353,6 +547,16 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
     for (int a = 0; a < 3; ++a) {
         S.inv_sp[a] = (float)(1.0 / vol->spacing[a]);
         S.ext[a] = (float)((double)n[a] * vol->spacing[a]);
+    }
+    S.row_e = (uint32_t)(nb[0] * 64);
+    S.slab_e = (uint32_t)(nb[0] * nb[1] * 64);
+    S.inv_step = 1.0f / o->step;
+    S.skip_c = 0.5f * o->step + o->step * (1.0f / 512.0f);
+    if (!bricked) S.occ = nullptr;   // occupancy belongs to the brick layouts
+    {   // 32-bit byte offsets and 24-bit brick-index products, unless the volume is too large
+        const int64_t bricks = nb[0] * nb[1] * nb[2];
+        const int64_t elem_bytes = (vol->dtype == VR_U16_NORM ? 2 : 4) * (vol->layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
+        S.wide = (bricks > (int64_t(1) << 24) || bricks * 64 * elem_bytes > (int64_t(1) << 32)) ? 1 : 0;
     }
     S.W = o->width;
     S.H = o->height;

@@ -34,6 +34,7 @@ class PreviewConfig:
     ortho: bool = False
     ert_eps: float = 2.0 ** -14
     bricked: bool = True            # render from the 4^3-brick layout
+    pairs: bool = False             # ... of x-tap pairs (two voxels per load, twice the memory)
     skip_empty: bool = True         # with the brick occupancy (exact)
 
 
@@ -76,8 +77,10 @@ class PreviewPipeline:
         if cfg.bricked:
             nb, nocc = vr.vr_brick_count(rx, ry, rz)
             occ = torch.empty(nocc, dtype=torch.uint8, device=dev) if cfg.skip_empty else None
-            self.render_vol = vr.BrickedVolume(torch.empty(nb * 64, dtype=torch.uint16, device=dev),
-                                               (rz, ry, rx), occ)
+            per = 128 if cfg.pairs else 64
+            self.render_vol = vr.BrickedVolume(torch.empty(nb * per, dtype=torch.uint16, device=dev),
+                                               (rz, ry, rx), occ,
+                                               vr.LAYOUT_BRICK4_PAIRS if cfg.pairs else vr.LAYOUT_BRICK4)
 
     def _atlas_arg(self):
         if self.atlas is None:
@@ -98,7 +101,7 @@ class PreviewPipeline:
         c = self.cfg
         src = self.levels[c.render_level - 1]
         if self.render_vol is not None:
-            vr.vr_brick_volume(src, out=self.render_vol, stream=stream)
+            vr.vr_brick_volume(src, out=self.render_vol, stream=stream, pairs=self.cfg.pairs)
             src = self.render_vol
         vr.vr_raycast(src, self.tf, self.cams, c.width, c.height, c.step,
                       ert_eps=c.ert_eps, out=self.frames, samples=self.samples if count else None,
@@ -122,7 +125,8 @@ class PreviewPipeline:
         level = self.levels[c.render_level - 1]
         src = level
         if self.render_vol is not None:
-            out.append(("bricks", lambda: vr.vr_brick_volume(level, out=self.render_vol, stream=stream)))
+            out.append(("bricks", lambda: vr.vr_brick_volume(level, out=self.render_vol, stream=stream,
+                                                             pairs=c.pairs)))
             src = self.render_vol
         out.append(("raycast", lambda src=src: vr.vr_raycast(src, self.tf, self.cams, c.width, c.height,
                                                              c.step, ert_eps=c.ert_eps, out=self.frames,

@@ -22,7 +22,7 @@ MAX_LEVELS = 4
 MAX_VIEWS_PER_LAUNCH = 48
 RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
 U16_NORM, F32 = 0, 1
-LAYOUT_LINEAR, LAYOUT_BRICK4 = 0, 1
+LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_BRICK4_PAIRS = 0, 1, 2
 ERRORS = {-1: "VR_ERR_NULL", -2: "VR_ERR_DIMS", -3: "VR_ERR_RANGE", -4: "VR_ERR_DTYPE",
           -5: "VR_ERR_HIP", -6: "VR_ERR_UNSUPPORTED", -7: "VR_ERR_WORKSPACE"}
 
@@ -91,7 +91,7 @@ def lib():
                                  C.POINTER(vr_render_opts), vp, vp, vp]
         L.vr_raycast_backward.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                           C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
-        L.vr_brick_volume.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
+        L.vr_brick_volume.argtypes = [vp, i32, i32, i64, i64, i64, vp, vp, vp]
         L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         PB = C.POINTER(vr_batch_item)
         PC = C.POINTER(vr_batch_config)
@@ -247,26 +247,33 @@ def vr_brick_count(nx, ny, nz):
 
 
 class BrickedVolume:
-    """A volume in the 4^3-brick render layout, with its occupancy grid (or None)."""
+    """A volume in a brick render layout (4^3 bricks, or 4^3 bricks of x-tap
+    pairs), with its occupancy grid (or None)."""
 
-    def __init__(self, data, shape, occupancy=None):
+    def __init__(self, data, shape, occupancy=None, layout=None):
         self.data, self.shape, self.occupancy = data, tuple(shape), occupancy
+        self.layout = LAYOUT_BRICK4 if layout is None else layout
         self.dtype = data.dtype
         self.device = data.device
 
 
-def vr_brick_volume(src, out=None, with_occupancy=True, stream=None) -> BrickedVolume:
-    """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy)."""
+def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False) -> BrickedVolume:
+    """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy);
+    with pairs, into the layout of x-tap pairs (twice the memory)."""
     nz, ny, nx = src.shape
     nb, nocc = vr_brick_count(nx, ny, nz)
     dt = U16_NORM if src.dtype in _U16 else F32
+    layout = LAYOUT_BRICK4_PAIRS if pairs else LAYOUT_BRICK4
+    per = 128 if pairs else 64                      # voxels stored per brick
     if out is None:
-        data = torch.empty(nb * 64, dtype=src.dtype, device=src.device)
+        data = torch.empty(nb * per, dtype=src.dtype, device=src.device)
         occ = torch.empty(nocc, dtype=torch.uint8, device=src.device) if with_occupancy else None
-        out = BrickedVolume(data, (nz, ny, nx), occ)
+        out = BrickedVolume(data, (nz, ny, nx), occ, layout)
+    if out.layout != layout:
+        raise ValueError("out has a different brick layout")
     occp = None if out.occupancy is None else _dev(out.occupancy, "occupancy", torch.uint8, nocc)
-    _check(lib().vr_brick_volume(_dev(src, "src", (*_U16, torch.float32)), dt, nx, ny, nz,
-                                 _dev(out.data, "bricked", src.dtype, nb * 64), occp,
+    _check(lib().vr_brick_volume(_dev(src, "src", (*_U16, torch.float32)), dt, layout, nx, ny, nz,
+                                 _dev(out.data, "bricked", src.dtype, nb * per), occp,
                                  _stream(stream)))
     return out
 
@@ -274,7 +281,7 @@ def vr_brick_volume(src, out=None, with_occupancy=True, stream=None) -> BrickedV
 def make_volume(data, spacing=(1.0, 1.0, 1.0)):
     """vr_volume for a uint16 (normalised) or float32 tensor [nz][ny][nx], or a BrickedVolume."""
     if isinstance(data, BrickedVolume):
-        t, layout, shape = data.data, LAYOUT_BRICK4, data.shape
+        t, layout, shape = data.data, data.layout, data.shape
         occ = None if data.occupancy is None else _dev(data.occupancy, "occupancy").value
     else:
         t, layout, shape, occ = data, LAYOUT_LINEAR, data.shape, None

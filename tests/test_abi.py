@@ -84,3 +84,17 @@ def test_raycast_validation_on_the_host(lib):
     # the adjoint differentiates f32 grids only
     assert lib.vr_raycast_backward(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16),
                                    C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == -4
+
+
+def test_brick_validation_on_the_host(lib):
+    from paper_2311_15038_amd import vr
+    p = C.c_void_p(256)
+    assert lib.vr_brick_volume(None, vr.U16_NORM, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, None) == -1
+    assert lib.vr_brick_volume(p, 5, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, None) == -4
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_LINEAR, 8, 8, 8, p, None, None) == -3
+    assert lib.vr_brick_volume(p, vr.U16_NORM, 7, 8, 8, 8, p, None, None) == -3
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 0, 8, 8, p, None, None) == -2
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 8, 8, 8, C.c_void_p(258), None, None) == -3
+    n, o = C.c_int64(0), C.c_int64(0)
+    assert lib.vr_brick_count(9, 5, 4, C.byref(n), C.byref(o)) == 0
+    assert n.value == 3 * 2 * 1 and o.value == 6 + 1

@@ -170,6 +170,33 @@ def test_brick_layout_and_occupancy(shape):
     assert (bf.occupancy.cpu().numpy() == occ).all()
 
 
+def _pairs_ref(a):
+    """The layout of x-tap pairs: element (x, y, z) = (a[z, y, x], a[z, y, min(x + 1, nx - 1)]),
+    in brick order, as the interleaved low/high voxels."""
+    nz, ny, nx = a.shape
+    hi = np.concatenate([a[:, :, 1:], a[:, :, -1:]], axis=2)
+    nbz, nby, nbx = (nz + 3) // 4, (ny + 3) // 4, (nx + 3) // 4
+    pad = np.zeros((nbz * 4, nby * 4, nbx * 4, 2), dtype=a.dtype)
+    pad[:nz, :ny, :nx, 0] = a
+    pad[:nz, :ny, :nx, 1] = hi
+    return pad.reshape(nbz, 4, nby, 4, nbx, 4, 2).transpose(0, 2, 4, 1, 3, 5, 6).reshape(-1)
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (5, 3, 4)])
+def test_pair_layout(shape):
+    banner(f"pair layout {shape}")
+    rng = np.random.default_rng(32)
+    a = rng.integers(0, 65536, size=shape).astype(np.uint16)
+    a[rng.random(shape) < 0.7] = 0
+    bv = vr.vr_brick_volume(to_dev_u16(a), pairs=True)
+    got = bv.data.cpu().view(torch.int16).numpy().view(np.uint16)
+    assert (got == _pairs_ref(a)).all()
+    assert (bv.occupancy.cpu().numpy() == _brick_ref(a)[1]).all()
+    f = a.astype(np.float32) / 3.0
+    bf = vr.vr_brick_volume(torch.from_numpy(f).to(dev()), pairs=True)
+    assert (bf.data.cpu().numpy() == _pairs_ref(f)).all()
+
+
 def _sparse_volume(shape, seed):
     """Blobs in empty space, some touching the faces: exercises brick skipping."""
     rng = np.random.default_rng(seed)
@@ -202,6 +229,12 @@ def test_brick_and_skip_bit_identical(level1, shape):
     bv.occupancy = None
     noskip = vr.vr_raycast(bv, tf, cams, 45, 38, 0.5, samples=c2)
     assert torch.equal(lin, noskip) and torch.equal(lin, skip)
+    pv = vr.vr_brick_volume(v, pairs=True)
+    c3 = torch.zeros(2, dtype=torch.int64, device=dev())
+    assert torch.equal(lin, vr.vr_raycast(pv, tf, cams, 45, 38, 0.5, samples=c3))
+    assert c3[0].item() == c0[0].item() and c3[1].item() == c1[1].item()
+    pv.occupancy = None
+    assert torch.equal(lin, vr.vr_raycast(pv, tf, cams, 45, 38, 0.5))
     assert c0[0].item() == c1[0].item() == c2[0].item()
     assert c0[1].item() == c0[0].item() and c2[1].item() == c2[0].item()
     assert c1[1].item() <= c1[0].item()               # skipped samples are counted, not evaluated
@@ -209,6 +242,42 @@ def test_brick_and_skip_bit_identical(level1, shape):
         ref, n_ref = R.render(a, (1, 1, 1), synth.default_tf(sigma_scale=3.0).astype(np.float64),
                               cams, 45, 38, 0.5)
         assert np.abs(skip.cpu().numpy() - ref).max() <= TOL
+
+
+def _grazing_cameras(nx, ny, nz):
+    """Views whose rays run almost parallel to brick faces (tiny direction
+    components), and exactly along an axis through brick boundaries."""
+    c = np.array([nx, ny, nz], dtype=np.float64) / 2
+    cams = []
+    for tilt in (0.0, 1e-6, 3e-4, 2e-3):
+        for axis in range(3):
+            d = np.full(3, tilt)
+            d[axis] = 1.0
+            d /= np.linalg.norm(d)
+            cam = np.zeros(11)
+            cam[0:3] = c - 3.0 * max(nx, ny, nz) * d
+            cam[3:6] = c
+            cam[6:9] = (0.0, 0.0, 1.0) if axis != 2 else (0.0, 1.0, 0.0)
+            cam[10] = 0.5 * max(nx, ny, nz)           # orthographic: rays on a grid through boundaries
+            cams.append(cam)
+            p = cam.copy()
+            p[9], p[10] = 20.0, 0.0                   # and a narrow perspective view
+            cams.append(p)
+    return np.array(cams)
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 44), (33, 48, 29)])
+def test_skip_exact_on_grazing_rays(shape):
+    banner(f"grazing rays {shape}")
+    a = _sparse_volume(shape, 9)
+    nz, ny, nx = shape
+    tf = _tf_dev(synth.default_tf(sigma_scale=3.0))
+    cams = _grazing_cameras(nx, ny, nz)
+    v = to_dev_u16(a)
+    lin = vr.vr_raycast(v, tf, cams, 64, 64, 0.5)
+    assert torch.equal(lin, vr.vr_raycast(vr.vr_brick_volume(v), tf, cams, 64, 64, 0.5))
+    assert torch.equal(lin, vr.vr_raycast(vr.vr_brick_volume(v, pairs=True), tf, cams, 64, 64, 0.5))
+    assert lin[..., 3].max().item() > 0.1
 
 
 def test_skip_disabled_when_density_zero_is_not_empty(level1):
