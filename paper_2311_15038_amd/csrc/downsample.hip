@@ -2,10 +2,11 @@
 // III-D): one streaming pass over the u16 volume writes up to four box-mean
 // levels, each rounded from its own exact integer sum.
 //
-// A workgroup (256 threads) walks 64 x 16 x 16-voxel tiles.  Each thread owns
-// two 8-voxel x-runs of a 2 x 2 (y, z) pair of rows: it loads 4 x 16 bytes per
-// run (adjacent threads read adjacent 16-byte pieces of a 128-byte row), looks
-// every voxel up in the keep mask held in LDS, and forms four level-1 sums.
+// A workgroup (512 threads) walks 256 x 16 x 16-voxel tiles, two steps of
+// loads ahead of its sums.  Each lane owns
+// an 8-voxel x-run of a 2 x 2 (y, z) pair of rows: it loads 4 x 16 bytes
+// (the 32 lanes of a half-wave read a 512-byte piece of each row), looks every
+// voxel up in the keep mask held in LDS, and forms four level-1 sums.
 // Level-k sums for k > 1 are reduced from the level-1 sums in LDS.  When the
 // keep mask is one interval [T, 65535] (a plain threshold, or a top-slice
 // filter that removed nothing above T) a voxel is kept by a compare instead
@@ -32,23 +33,253 @@ zero_tiles(void* atlas, int bits, int64_t W, int tiles_x, int nxk, int nyk, int 
     }
 }
 
-__global__ void __launch_bounds__(kThreads)
-downsample_kernel(const uint16_t* __restrict__ vol, int nx, int ny, int nz, int aligned,
+// Wide tiles of the standalone pass: 256 x 16 x 16 voxels per four steps of
+// a 512-thread workgroup.  Half-wave h (32 lanes) streams 512-byte pieces of
+// rows, eight voxels per lane: at step it = 0..3 of a tile it reads the rows
+// of (y, z) pair (2 (h & 3) + (it & 1), 2 (h >> 2) + (it >> 1)), so over the
+// four steps a lane covers whole level-2 boxes and keeps their sums in
+// registers.  Levels 3 and 4 are reduced from the level-2 sums in LDS.
+constexpr int WX = 256, WT = 512;
+
+// How a voxel is kept: looked up in the mask, by the interval [T, 65535]
+// (T >= 1), or every voxel (T = 0).
+enum { KEEP_LOOKUP = 0, KEEP_INTERVAL = 1, KEEP_ALL = 2 };
+
+struct WideLds {
+    uint32_t s2[TZ / 4][TY / 4][WX / 4];
+    uint32_t s3[TZ / 8][TY / 8][WX / 8];
+};
+
+struct WideTile {
+    int X0, Y0, Z0;
+    bool interior;
+};
+
+__device__ __forceinline__ WideTile wide_tile(int tile, int tiles_x, int tiles_y, int nx, int ny, int nz, int aligned)
+{
+    WideTile t;
+    t.X0 = (tile % tiles_x) * WX;
+    t.Y0 = ((tile / tiles_x) % tiles_y) * TY;
+    t.Z0 = (tile / (tiles_x * tiles_y)) * TZ;
+    t.interior = aligned && t.X0 + WX <= nx && t.Y0 + TY <= ny && t.Z0 + TZ <= nz;
+    return t;
+}
+
+// (y, z) row pair of half-wave h at step it of a tile
+__device__ __forceinline__ int pair_y(int h, int it) { return 2 * (h & 3) + (it & 1); }
+__device__ __forceinline__ int pair_z(int h, int it) { return 2 * (h >> 2) + (it >> 1); }
+
+// The four rows (y pair yp, z pair zp) of the lane's 8-voxel x-run, zero past
+// the volume's end.
+__device__ __forceinline__ void load_rows(const uint16_t* __restrict__ vol, int nx, int ny, int nz,
+                                          const WideTile& t, int yp, int zp, int l, uint4 (&q)[4])
+{
+    const int x = t.X0 + 8 * l, y = t.Y0 + 2 * yp, z = t.Z0 + 2 * zp;
+    const int64_t nxy = (int64_t)nx * ny;
+    const uint16_t* p = vol + ((int64_t)z * ny + y) * nx + x;
+    if (t.interior) {
+        q[0] = load_stream(p);
+        q[1] = load_stream(p + nx);
+        q[2] = load_stream(p + nxy);
+        q[3] = load_stream(p + nxy + nx);
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const bool rowok = y + (r & 1) < ny && z + (r >> 1) < nz;
+        const uint16_t* row = p + (r & 1) * (int64_t)nx + (r >> 1) * nxy;
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t lo = (rowok && x + 2 * e < nx) ? (uint32_t)row[2 * e] : 0u;
+            const uint32_t hi = (rowok && x + 2 * e + 1 < nx) ? (uint32_t)row[2 * e + 1] : 0u;
+            w[e] = lo | (hi << 16);
+        }
+        q[r] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// 1 in each 16-bit half of w whose voxel is >= T, else 0; t2 = (T - 1) in both
+// halves: a saturating packed subtract leaves a non-zero half exactly for the
+// kept voxels, and a packed minimum with 1 turns it into the flag.
+__device__ __forceinline__ uint32_t kept_flags(uint32_t w, uint32_t t2)
+{
+    uint32_t d, m;
+    asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(d) : "v"(w), "v"(t2));
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(d), "v"(0x00010001u));
+    return m;
+}
+
+// acc + the kept voxels of the two halves of w: one packed dot product with
+// their 0/1 flags.
+template <int MODE>
+__device__ __forceinline__ uint32_t add_kept(uint32_t acc, uint32_t w, const uint32_t* bits, uint32_t T, uint32_t t2)
+{
+    if (MODE == KEEP_LOOKUP)
+        return acc + keepv<false>(bits, w & 0xFFFFu, T) + keepv<false>(bits, w >> 16, T);
+    const uint32_t m = MODE == KEEP_ALL ? 0x00010001u : kept_flags(w, t2);
+    return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, w), __builtin_bit_cast(u16x2, m), acc, false);
+}
+
+template <int MODE>
+__device__ __forceinline__ uint32_t sum_column(uint32_t a, uint32_t b, uint32_t c, uint32_t d, const uint32_t* bits,
+                                               uint32_t T, uint32_t t2)
+{
+    return add_kept<MODE>(add_kept<MODE>(add_kept<MODE>(add_kept<MODE>(0u, a, bits, T, t2), b, bits, T, t2), c, bits,
+                                         T, t2), d, bits, T, t2);
+}
+
+// Store of level k at (x, y, z) of the level, with the atlas copy when k is
+// the atlas level; arow is the atlas offset of the tile holding slice z.
+__device__ __forceinline__ void store_at(const LevelOut& L, int k, int x, int y, int z, uint32_t sum, int64_t arow)
+{
+    const int i = k - 1;
+    if (x >= L.nx[i] || y >= L.ny[i] || z >= L.nz[i]) return;
+    const uint16_t v = round_level(sum, k);
+    L.p[i][((int64_t)z * L.ny[i] + y) * L.nx[i] + x] = v;
+    if (k == L.atlas_level) {
+        const int64_t a = arow + (int64_t)y * ((int64_t)L.atlas_tiles_x * L.nx[i]) + x;
+        if (L.atlas_bits == 16) {
+            static_cast<uint16_t*>(L.atlas)[a] = v;
+        } else {
+            const uint32_t b = ((uint32_t)v + 128u) >> 8;
+            static_cast<uint8_t*>(L.atlas)[a] = (uint8_t)(b > 255u ? 255u : b);
+        }
+    }
+}
+
+// Atlas offset of the tile (z mod tiles_x, z div tiles_x) of slice z of level k
+// (0 unless k is the atlas level).
+__device__ __forceinline__ int64_t atlas_row(const LevelOut& L, int k, int z)
+{
+    if (k != L.atlas_level) return 0;
+    const int i = k - 1;
+    const uint32_t tx = (uint32_t)z % (uint32_t)L.atlas_tiles_x, ty = (uint32_t)z / (uint32_t)L.atlas_tiles_x;
+    return (int64_t)ty * L.ny[i] * ((int64_t)L.atlas_tiles_x * L.nx[i]) + (int64_t)tx * L.nx[i];
+}
+
+// Level 1 of one step (four x pairs of the lane's rows) and its addition to
+// the lane's two level-2 partial sums.
+template <int MODE>
+__device__ __forceinline__ void level1_step(const uint4 (&q)[4], const uint32_t* bits, uint32_t T, uint32_t t2,
+                                            const WideTile& t, int yp, int zp, int l, int aligned_out,
+                                            const LevelOut& L, uint32_t (&l2)[2])
+{
+    uint32_t s[4];
+    s[0] = sum_column<MODE>(q[0].x, q[1].x, q[2].x, q[3].x, bits, T, t2);
+    s[1] = sum_column<MODE>(q[0].y, q[1].y, q[2].y, q[3].y, bits, T, t2);
+    s[2] = sum_column<MODE>(q[0].z, q[1].z, q[2].z, q[3].z, bits, T, t2);
+    s[3] = sum_column<MODE>(q[0].w, q[1].w, q[2].w, q[3].w, bits, T, t2);
+    const int x1 = (t.X0 >> 1) + 4 * l, y1 = (t.Y0 >> 1) + yp, z1 = (t.Z0 >> 1) + zp;
+    if (t.interior && aligned_out) {
+        uint2 w;
+        w.x = (uint32_t)round_level(s[0], 1) | ((uint32_t)round_level(s[1], 1) << 16);
+        w.y = (uint32_t)round_level(s[2], 1) | ((uint32_t)round_level(s[3], 1) << 16);
+        *reinterpret_cast<uint2*>(L.p[0] + ((int64_t)z1 * L.ny[0] + y1) * L.nx[0] + x1) = w;
+    } else {
+        const int64_t arow = atlas_row(L, 1, z1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store_at(L, 1, x1 + k, y1, z1, s[k], arow);
+    }
+    l2[0] += s[0] + s[1];
+    l2[1] += s[2] + s[3];
+}
+
+// Level 2 of a tile from the lane's register sums; levels 3 and 4 from the
+// level-2 sums in LDS.
+__device__ __forceinline__ void coarse_levels(const WideTile& t, int n_levels, const LevelOut& L, WideLds& G, int tid,
+                                              const uint32_t (&l2)[2])
+{
+    const int h = tid >> 5, l = tid & 31;
+    const int x2 = 2 * l, y2 = h & 3, z2 = h >> 2;
+    const int64_t arow = atlas_row(L, 2, (t.Z0 >> 2) + z2);
+    store_at(L, 2, (t.X0 >> 2) + x2, (t.Y0 >> 2) + y2, (t.Z0 >> 2) + z2, l2[0], arow);
+    store_at(L, 2, (t.X0 >> 2) + x2 + 1, (t.Y0 >> 2) + y2, (t.Z0 >> 2) + z2, l2[1], arow);
+    if (n_levels < 3) return;
+    G.s2[z2][y2][x2] = l2[0];
+    G.s2[z2][y2][x2 + 1] = l2[1];
+    __syncthreads();
+    if (tid < (TZ / 8) * (TY / 8) * (WX / 8)) {
+        const int x = tid % (WX / 8), y = (tid / (WX / 8)) % (TY / 8), z = tid / ((WX / 8) * (TY / 8));
+        uint32_t acc = 0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) acc += G.s2[2 * z + (d >> 2)][2 * y + ((d >> 1) & 1)][2 * x + (d & 1)];
+        store_at(L, 3, (t.X0 >> 3) + x, (t.Y0 >> 3) + y, (t.Z0 >> 3) + z, acc, atlas_row(L, 3, (t.Z0 >> 3) + z));
+        G.s3[z][y][x] = acc;
+    }
+    if (n_levels > 3) {
+        __syncthreads();
+        if (tid < WX / 16) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) acc += G.s3[d >> 2][(d >> 1) & 1][2 * tid + (d & 1)];
+            store_at(L, 4, (t.X0 >> 4) + tid, t.Y0 >> 4, t.Z0 >> 4, acc, atlas_row(L, 4, t.Z0 >> 4));
+        }
+    }
+    __syncthreads();   // the next tile writes its level-2 sums over these
+}
+
+// A workgroup walks its tiles (blockIdx.x, + gridDim.x, ...) as a flat
+// sequence of steps (tile, it); the rows of the next two steps are in flight
+// while the current step is summed, and the coarse levels of a tile are
+// reduced while the first rows of the next tile arrive.
+template <int MODE>
+__device__ inline void wide_tiles(const uint16_t* __restrict__ vol, int nx, int ny, int nz, int aligned,
+                                  int aligned_out, const uint32_t* bits, uint32_t T, int n_levels,
+                                  const LevelOut& L, int tiles_x, int tiles_y, int n_tiles, WideLds& G)
+{
+    const int tid = threadIdx.x, h = tid >> 5, l = tid & 31;
+    const int my_tiles = n_tiles > (int)blockIdx.x ? (n_tiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
+    const int steps = 4 * my_tiles;
+    const uint32_t tm1 = T > 0u ? T - 1u : 0u, t2 = tm1 | (tm1 << 16);
+    auto tile_at = [&](int m) {
+        return wide_tile((int)blockIdx.x + m * (int)gridDim.x, tiles_x, tiles_y, nx, ny, nz, aligned);
+    };
+    // rows of steps k .. k + LA - 1 are in flight; tl is the tile of the last one loaded
+    constexpr int LA = 3;
+    WideTile t0 = tile_at(0), tl = t0;
+    uint4 q[LA][4];
+#pragma unroll
+    for (int a = 0; a < LA - 1; ++a)
+        if (a < steps) load_rows(vol, nx, ny, nz, t0, pair_y(h, a), pair_z(h, a), l, q[a]);
+    uint32_t l2[2] = {0u, 0u};
+    for (int k = 0; k < steps; ++k) {
+        if (k + LA - 1 < steps) {
+            const int kn = k + LA - 1, itn = kn & 3;
+            if (itn == 0) tl = tile_at(kn >> 2);
+            load_rows(vol, nx, ny, nz, tl, pair_y(h, itn), pair_z(h, itn), l, q[LA - 1]);
+        }
+        const int it = k & 3;
+        level1_step<MODE>(q[0], bits, T, t2, t0, pair_y(h, it), pair_z(h, it), l, aligned_out, L, l2);
+        if (it == 3) {
+            if (n_levels > 1) coarse_levels(t0, n_levels, L, G, tid, l2);
+            l2[0] = l2[1] = 0u;
+            t0 = tile_at((k + 1) >> 2);
+        }
+#pragma unroll
+        for (int a = 0; a < LA - 1; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) q[a][r] = q[a + 1][r];
+    }
+}
+
+__global__ void __launch_bounds__(WT)
+downsample_kernel(const uint16_t* __restrict__ vol, int nx, int ny, int nz, int aligned, int aligned_out,
                   const uint32_t* __restrict__ keep_bits, int n_levels, LevelOut L, int tiles_x,
                   int tiles_y, int n_tiles)
 {
     __shared__ uint32_t bits[VR_KEEP_WORDS];
-    __shared__ TileLds G;
+    __shared__ WideLds G;
     __shared__ uint32_t s_first, s_bad;
     const uint32_t T = keep_bits == nullptr ? 0u : load_mask(keep_bits, bits, s_first, s_bad);
-    const int tid = threadIdx.x;
-    if (T <= VR_NBINS) {
-        for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
-            tile_body<true>(vol, nx, ny, nz, aligned, bits, T, n_levels, L, tiles_x, tiles_y, tile, true, tid, G);
-    } else {
-        for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
-            tile_body<false>(vol, nx, ny, nz, aligned, bits, 0u, n_levels, L, tiles_x, tiles_y, tile, true, tid, G);
-    }
+    if (T == 0u)
+        wide_tiles<KEEP_ALL>(vol, nx, ny, nz, aligned, aligned_out, bits, T, n_levels, L, tiles_x, tiles_y, n_tiles, G);
+    else if (T <= VR_NBINS)
+        wide_tiles<KEEP_INTERVAL>(vol, nx, ny, nz, aligned, aligned_out, bits, T, n_levels, L, tiles_x, tiles_y, n_tiles, G);
+    else
+        wide_tiles<KEEP_LOOKUP>(vol, nx, ny, nz, aligned, aligned_out, bits, 0u, n_levels, L, tiles_x, tiles_y, n_tiles, G);
 }
 
 }  // namespace
@@ -108,15 +339,23 @@ extern "C" int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_
             if (rc) return rc;
         }
     }
-    const int aligned = (nx % 8 == 0) && ((reinterpret_cast<uintptr_t>(d_vol) & 15u) == 0) &&
-                        ((reinterpret_cast<uintptr_t>(L.p[0]) & 7u) == 0);
-    const int tiles_x = (int)((nx + TX - 1) / TX), tiles_y = (int)((ny + TY - 1) / TY);
+    // 16-byte row loads need 8-voxel rows on a 16-byte base; whole 4-value level-1 stores need
+    // a level-1 row of a multiple of 4 on an 8-byte base and no atlas of level 1
+    const int aligned = (nx % 8 == 0) && ((reinterpret_cast<uintptr_t>(d_vol) & 15u) == 0);
+    const int aligned_out = (L.nx[0] % 4 == 0) && ((reinterpret_cast<uintptr_t>(L.p[0]) & 7u) == 0) &&
+                            L.atlas_level != 1;
+    const int tiles_x = (int)((nx + WX - 1) / WX), tiles_y = (int)((ny + TY - 1) / TY);
     const int64_t tiles = (int64_t)tiles_x * tiles_y * ((nz + TZ - 1) / TZ);
     VR_REQUIRE(tiles < (int64_t(1) << 31), VR_ERR_DIMS, "vr_threshold_downsample: volume too large");
-    int64_t grid = (int64_t)vr::num_cus() * 8;
+    // one resident round of workgroups (as many per compute unit as registers and LDS allow)
+    static const int per_cu = [] {
+        int n = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, downsample_kernel, WT, 0) == hipSuccess && n > 0 ? n : 1;
+    }();
+    int64_t grid = (int64_t)vr::num_cus() * per_cu;
     if (grid > tiles) grid = tiles;
-    downsample_kernel<<<(unsigned)grid, kThreads, 0, s>>>(
-        d_vol, (int)nx, (int)ny, (int)nz, aligned, d_keep_bits, n_levels, L, tiles_x, tiles_y,
-        (int)tiles);
+    downsample_kernel<<<(unsigned)grid, WT, 0, s>>>(
+        d_vol, (int)nx, (int)ny, (int)nz, aligned, aligned_out, d_keep_bits, n_levels, L, tiles_x,
+        tiles_y, (int)tiles);
     return vr::check_launch("vr_threshold_downsample");
 }

@@ -17,10 +17,14 @@ namespace {
 
 using namespace vr::hg;
 
-__global__ void __launch_bounds__(256) fill_u64(uint64_t* __restrict__ p, int n)
+// zero one or two 65536-bin histograms
+__global__ void __launch_bounds__(256) fill_u64(uint64_t* __restrict__ p, uint64_t* __restrict__ q, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
+    if (i < n) {
+        p[i] = 0;
+        if (q) q[i] = 0;
+    }
 }
 
 // One contiguous run of voxels and the histogram it goes to.
@@ -31,16 +35,12 @@ struct Range {
     int blocks;          // workgroups given to this range
 };
 
-// Workgroups [0, a.blocks) count range a, the next b.blocks count range b
-// (b.blocks may be 0): one launch for the volume and its top slices.
-__global__ void __launch_bounds__(kThreads) hist_kernel(Range a, Range b)
+__global__ void __launch_bounds__(kThreads) hist_kernel(Range R)
 {
     __shared__ uint32_t lds[kWords];
     zero_lds(lds);
     __syncthreads();
-    const bool first = (int)blockIdx.x < a.blocks;
-    const Range& R = first ? a : b;
-    const int64_t gtid = (int64_t)(first ? blockIdx.x : blockIdx.x - a.blocks) * kThreads + threadIdx.x;
+    const int64_t gtid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     count_range(lds, R.hist, R.vol, R.n, gtid, (int64_t)R.blocks * kThreads);
     __syncthreads();
     flush_lds(lds, R.hist);
@@ -85,14 +85,13 @@ extern "C" int vr_histogram(const uint16_t* d_vol, int64_t nx, int64_t ny, int64
     VR_REQUIRE(nz_range == 0 || d_vol != nullptr, VR_ERR_NULL, "vr_histogram: d_vol is NULL");
     hipStream_t s = vr::as_stream(stream);
 
-    fill_u64<<<VR_NBINS / 256, 256, 0, s>>>(d_hist, VR_NBINS);
+    fill_u64<<<VR_NBINS / 256, 256, 0, s>>>(d_hist, nullptr, VR_NBINS);
     rc = vr::check_launch("vr_histogram: fill");
     if (rc || nz_range == 0) return rc;
 
     Range a = make_range(d_vol + z0 * nx * ny, nx * ny * nz_range, d_hist);
     a.blocks = blocks_for(a.n, vr::num_cus());
-    Range b{};
-    hist_kernel<<<(unsigned)a.blocks, kThreads, 0, s>>>(a, b);
+    hist_kernel<<<(unsigned)a.blocks, kThreads, 0, s>>>(a);
     return vr::check_launch("vr_histogram");
 }
 
@@ -107,17 +106,20 @@ extern "C" int vr_histogram_with_top(const uint16_t* d_vol, int64_t nx, int64_t 
     VR_REQUIRE(top_slices >= 1 && top_slices <= nz, VR_ERR_RANGE,
                "vr_histogram_with_top: %lld top slices of %lld", (long long)top_slices, (long long)nz);
     hipStream_t s = vr::as_stream(stream);
-    fill_u64<<<VR_NBINS / 256, 256, 0, s>>>(d_hist, VR_NBINS);
-    fill_u64<<<VR_NBINS / 256, 256, 0, s>>>(d_hist_top, VR_NBINS);
+    fill_u64<<<VR_NBINS / 256, 256, 0, s>>>(d_hist, d_hist_top, VR_NBINS);
     rc = vr::check_launch("vr_histogram_with_top: fill");
     if (rc) return rc;
+    // two launches in stream order: the top slices on as many workgroups as their
+    // size warrants, then the whole volume on every compute unit (one launch
+    // sharing the compute units between the two runs measured slower)
     const int cus = vr::num_cus();
-    Range a = make_range(d_vol, nx * ny * nz, d_hist);
     Range b = make_range(d_vol, nx * ny * top_slices, d_hist_top);
-    // the top slices get a share of the compute units in proportion to their
-    // voxels (at least one workgroup), the volume the rest, all co-resident
-    b.blocks = std::max(1, std::min(blocks_for(b.n, cus), (int)((int64_t)cus * b.n / a.n) + 1));
-    a.blocks = std::max(1, std::min(blocks_for(a.n, cus), cus - b.blocks));
-    hist_kernel<<<(unsigned)(a.blocks + b.blocks), kThreads, 0, s>>>(a, b);
+    b.blocks = blocks_for(b.n, cus);
+    hist_kernel<<<(unsigned)b.blocks, kThreads, 0, s>>>(b);
+    rc = vr::check_launch("vr_histogram_with_top: top slices");
+    if (rc) return rc;
+    Range a = make_range(d_vol, nx * ny * nz, d_hist);
+    a.blocks = blocks_for(a.n, cus);
+    hist_kernel<<<(unsigned)a.blocks, kThreads, 0, s>>>(a);
     return vr::check_launch("vr_histogram_with_top");
 }

@@ -11,7 +11,7 @@ namespace hg {
 
 constexpr int kThreads = 1024;          // threads of a histogram workgroup
 constexpr int kWords = VR_NBINS / 2;      // packed LDS words
-constexpr int kUnroll = 4;                // 16-byte loads per thread per batch (two batches in flight)
+constexpr int kUnroll = 8;                // 16-byte loads per thread per batch (two batches in flight)
 constexpr uint32_t kMark = 0x8000u;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -40,6 +40,17 @@ __device__ __forceinline__ void count_n(uint32_t* lds, uint64_t* gh, uint32_t v,
     }
 }
 
+// Adds 1 to bin v: the counter crosses the mark exactly when it held 0x7FFF.
+__device__ __forceinline__ void count_1(uint32_t* lds, uint64_t* gh, uint32_t v)
+{
+    const uint32_t sh = (v & 1u) << 4;
+    const uint32_t old = atomicAdd(lds + (v >> 1), 1u << sh);
+    if (((old >> sh) & 0xFFFFu) == kMark - 1u) {
+        atomicSub(lds + (v >> 1), kMark << sh);
+        add_global(gh, v, kMark);
+    }
+}
+
 __device__ __forceinline__ void count_chunk(uint32_t* lds, uint64_t* gh, uint4 c)
 {
     // wave-uniform chunk: every lane holds eight copies of the first lane's value
@@ -51,14 +62,14 @@ __device__ __forceinline__ void count_chunk(uint32_t* lds, uint64_t* gh, uint4 c
         if (__lane_id() == (uint32_t)__builtin_ctzll(act)) count_n(lds, gh, w0, 8u * (uint32_t)__popcll(act));
         return;
     }
-    count_n(lds, gh, c.x & 0xFFFFu, 1u);
-    count_n(lds, gh, c.x >> 16, 1u);
-    count_n(lds, gh, c.y & 0xFFFFu, 1u);
-    count_n(lds, gh, c.y >> 16, 1u);
-    count_n(lds, gh, c.z & 0xFFFFu, 1u);
-    count_n(lds, gh, c.z >> 16, 1u);
-    count_n(lds, gh, c.w & 0xFFFFu, 1u);
-    count_n(lds, gh, c.w >> 16, 1u);
+    count_1(lds, gh, c.x & 0xFFFFu);
+    count_1(lds, gh, c.x >> 16);
+    count_1(lds, gh, c.y & 0xFFFFu);
+    count_1(lds, gh, c.y >> 16);
+    count_1(lds, gh, c.z & 0xFFFFu);
+    count_1(lds, gh, c.z >> 16);
+    count_1(lds, gh, c.w & 0xFFFFu);
+    count_1(lds, gh, c.w >> 16);
 }
 
 // The block's share of a contiguous run of n voxels starting at vol: block

@@ -1,14 +1,15 @@
 // Threshold selection and keep mask on the device (Sections III-A and III-D).
 //
-// Three launches on the caller's stream.  The histogram is cut into chunks of
+// Four launches on the caller's stream.  The histogram is cut into chunks of
 // 1024 bins; a chunk workgroup (one bin per thread) loads its bins plus a halo
 // with coalesced reads and works from a block scan in LDS.
 //   1. per chunk: the chunk's maximum of the smoothed histogram (valley), or
 //      its count and grey-value sum (Otsu, ITS);
 //   2. per chunk: valley candidates against the global peak, or the chunk's
 //      best Otsu threshold;
-//   3. one workgroup: combines the chunks (runs the ITS iteration), writes the
-//      result and the keep mask.
+//   3. one workgroup: combines the chunks (runs the ITS iteration) and writes
+//      the result;
+//   4. one workgroup per 1024 bins: the keep mask from the threshold.
 // The caller's keep-mask buffer (8 KiB) carries the per-chunk records between
 // the launches and is overwritten with the mask at the end, so nothing is
 // allocated.  Floating point that decides a threshold uses IEEE FP64
@@ -39,7 +40,14 @@ finish_kernel(const uint64_t* __restrict__ H, const uint64_t* __restrict__ Htop,
               int n_chunks, uint32_t* __restrict__ result, uint32_t* __restrict__ bits)
 {
     __shared__ SelLds Ls;
-    finish(Ls, H, Htop, rule, param, n_chunks, result, bits);
+    finish(Ls, H, Htop, rule, param, n_chunks, result, bits, false);
+}
+
+// row blockIdx.x of the keep mask, from the threshold the finish launch wrote
+__global__ void __launch_bounds__(kT)
+mask_kernel(const uint64_t* __restrict__ Htop, const uint32_t* __restrict__ result, uint32_t* __restrict__ bits)
+{
+    mask_row(Htop, result[0], (int)blockIdx.x, bits);
 }
 
 }  // namespace
@@ -72,5 +80,8 @@ extern "C" int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_his
         }
     }
     finish_kernel<<<1, kT, 0, s>>>(d_hist, d_hist_top, rule, param, n_chunks, d_result, d_keep_bits);
+    int rc = vr::check_launch("vr_select_threshold: finish");
+    if (rc) return rc;
+    mask_kernel<<<kB / kT, kT, 0, s>>>(d_hist_top, d_result, d_keep_bits);
     return vr::check_launch("vr_select_threshold");
 }

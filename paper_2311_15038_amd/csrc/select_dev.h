@@ -1,7 +1,7 @@
 // Device-side pieces of threshold selection shared by the single-volume
 // launches and the batched persistent kernel: block primitives over one
-// 1024-thread workgroup, the smoothed-histogram chunk, and the three stages
-// (per-chunk pass, per-chunk search, finish with the keep mask).
+// 1024-thread workgroup, the smoothed-histogram chunk, the stages (per-chunk
+// pass, per-chunk search, finish) and one row of the keep mask.
 #pragma once
 
 #include "common.h"
@@ -287,9 +287,26 @@ __device__ inline void chunk_search(SelLds& Ls, int c, const uint64_t* __restric
 }
 
 // ------------------------------------------------------------ launch 3
+// One 1024-bin row j of the keep mask: keep[b] = b >= T and no top-slice
+// count at b; a wave's 64 consecutive bins become two words by ballot.
+__device__ __forceinline__ void mask_row(const uint64_t* __restrict__ Htop, uint32_t T, int j,
+                                         uint32_t* __restrict__ bits)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t b = (uint32_t)(j * kT + t);
+    const uint64_t m = __ballot(b >= T && (Htop == nullptr || Htop[b] == 0));
+    if (lane == 0) {
+        bits[32 * j + 2 * w] = (uint32_t)m;
+        bits[32 * j + 2 * w + 1] = (uint32_t)(m >> 32);
+    }
+}
+
+// Combines the chunk records into the threshold and writes the result; with
+// write_mask the same workgroup then writes the whole keep mask (otherwise a
+// separate launch of mask_row workgroups does, after this one).
 __device__ inline void finish(SelLds& Ls, const uint64_t* __restrict__ H, const uint64_t* __restrict__ Htop,
                               int rule, int param, int n_chunks, uint32_t* __restrict__ result,
-                              uint32_t* __restrict__ bits)
+                              uint32_t* __restrict__ bits, bool write_mask = true)
 {
     uint64_t* wsum = Ls.wsum;
     int* ibuf = Ls.ibuf;
@@ -376,17 +393,8 @@ __device__ inline void finish(SelLds& Ls, const uint64_t* __restrict__ H, const 
     __syncthreads();          // every read of the scratch is done before the mask overwrites it
     const uint32_t T = s_res[0];
     if (t < 4) result[t] = s_res[t];
-    // mask: bin b = 1024 j + t; a wave's 64 consecutive bins become two words by ballot
-    const int lane = t & 63, w = t >> 6;
-    for (int j = 0; j < kB / kT; ++j) {
-        const uint32_t b = (uint32_t)(j * kT + t);
-        const bool keep = b >= T && (Htop == nullptr || Htop[b] == 0);
-        const uint64_t m = __ballot(keep);
-        if (lane == 0) {
-            bits[32 * j + 2 * w] = (uint32_t)m;
-            bits[32 * j + 2 * w + 1] = (uint32_t)(m >> 32);
-        }
-    }
+    if (write_mask)
+        for (int j = 0; j < kB / kT; ++j) mask_row(Htop, T, j, bits);
 }
 
 }  // namespace sel
