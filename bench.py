@@ -33,6 +33,26 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32, published
 FLOPS_PER_SAMPLE = 62
 METRIC = "Gsamples/s ray casting + GB/s reduction vs HBM peak; fwd+bwd, batched vs plain"
 
+# HBM bytes of one launch of the dominant kernel (raycast_fwd on this step),
+# FETCH_SIZE + WRITE_SIZE from two rocprofv3 --pmc runs of --traffic-probe,
+# scaled by the same counters on a 1 GiB copy (factor 1.000); valid only for
+# the kernel sources they were taken on (fingerprint below).
+RAYCAST_TRAFFIC = {"bytes": (1692699 + 147456) * 1024, "fetch_kib": 1692699, "write_kib": 147456,
+                   "scale": 1.000, "sources_sha256_16": "cb58d150cdb591e8"}
+RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "brick_dev.h", "common.h")
+
+
+def raycast_traffic():
+    """The counted traffic of the ray caster, or None once its sources changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in RAYCAST_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_15038_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != RAYCAST_TRAFFIC["sources_sha256_16"]:
+        return None
+    return RAYCAST_TRAFFIC["bytes"]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -99,6 +119,10 @@ def run_gpu(steps, warmup):
     nz, ny, nx = vol.shape
     vol_b = nx * ny * nz * 2
     lv_b = sum(l.numel() * 2 for l in pipe.levels)
+    rv = pipe.render_vol
+    out["raycast_alg_bytes"] = (rv.data.numel() * rv.data.element_size()
+                                + (rv.occupancy.numel() if rv.occupancy is not None else 0)
+                                + pipe.frames.numel() * 4)
     out["kernel_bytes"] = {"histograms": vol_b + nx * ny * 3 * 2,
                            "pyramid+atlas": vol_b + lv_b + pipe.atlas.numel() * 2,
                            "bricks": 2 * pipe.levels[0].numel() * 2}
@@ -395,7 +419,9 @@ def main():
                                 "step 0.5, ERT 2^-14"),
                    "volume": [1024, 1024, 1024], "levels": 4, "views": 36, "image": [512, 512]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": raycast_traffic(),
+                     "traffic_unit": "B per launch (HBM read + write, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "algorithmic_bytes": res["raycast_alg_bytes"],
                      "kernel": "raycast_fwd<u16,brick4>", "flops_per_sample": FLOPS_PER_SAMPLE,
                      "samples": "evaluated",
                      "kernel_ms": rc_ms},
