@@ -5,9 +5,10 @@
 One step = one pass of the whole path over the 1024^3 u16 volume resident in
 HBM: histogram of the volume and of its first three slices, valley threshold
 + top-slice filter, fused 4-level pyramid, 256^3 -> 4096^2 slicemap atlas,
-and 36 perspective turntable frames of 512^2 ray cast from the 512^3 level
-(step 0.5).  Prints one JSON line.  `value` is rendered samples per second of
-whole-step wall time (reduction included); the reduction's own bandwidth, the
+36 perspective turntable frames of 512^2 ray cast from the 512^3 level
+(step 0.5), and the best view among them by frame entropy.  Prints one JSON
+line.  `value` is rendered samples per second of whole-step wall time
+(reduction included); the reduction's own bandwidth, the
 per-kernel times and the oracle's CPU rate are reported beside it, then the
 forward+backward fit iteration, the batched persistent launch of 64 uneven
 volumes and the serving loop, each against the plain single-volume path.
@@ -107,6 +108,8 @@ def run_gpu(steps, warmup):
     red_ms = sum(per[k] for k in pipe.REDUCTION_CALLS)
     red_bytes = pipe.reduction_bytes()
     T = int(pipe.result[0].item())
+    best_view = int(pipe.best_view.item())
+    best_entropy = float(pipe.view_entropy[best_view].item())
     out = {
         "samples_per_step": samples,
         "evaluated_per_step": evaluated,
@@ -115,6 +118,7 @@ def run_gpu(steps, warmup):
         "reduction_ms": red_ms,
         "reduction_bytes": red_bytes,
         "threshold": T,
+        "best_view": {"view": best_view, "entropy_bits": best_entropy},
     }
     nz, ny, nx = vol.shape
     vol_b = nx * ny * nz * 2
@@ -186,6 +190,32 @@ def run_fwd_bwd(pipe, steps=200):
             "iter_Gsamples_per_s": n_fwd / (it_ms * 1e-3) / 1e9,
             "steps": steps, "loss_first": lo[0], "loss_last": lo[-1],
             "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
+
+
+def run_thresholds(pipe, reps=20):
+    """The threshold rules on the full volume's histogram, in the manner of the
+    Otsu / ITS comparison of Fig. 5: device time per rule (median of `reps`
+    calls, each call all of its launches), the threshold, and the ITS
+    iteration count, on 256 bins (8-bit, the paper's case) and 65536 bins."""
+    import torch
+
+    from paper_2311_15038_amd import vr
+
+    H, Ht = pipe.hist, pipe.hist_top
+    out = {}
+    for name, rule, param, top in [("valley_r32", vr.RULE_VALLEY, 32, Ht), ("otsu_8bit", vr.RULE_OTSU, 8, None),
+                                   ("its_8bit", vr.RULE_ITS, 8, None), ("otsu_16bit", vr.RULE_OTSU, 0, None),
+                                   ("its_16bit", vr.RULE_ITS, 0, None)]:
+        res = torch.empty(4, dtype=torch.int32, device=H.device)
+        bits = torch.empty(vr.KEEP_WORDS, dtype=torch.int32, device=H.device)
+        ms = _median_ms(lambda: vr.vr_select_threshold(H, top, rule, param, res, bits), reps)
+        r = res.cpu().tolist()
+        out[name] = {"us": ms * 1e3, "T": r[0]}
+        if rule == vr.RULE_ITS:
+            out[name]["iterations"] = r[1]
+        if rule == vr.RULE_OTSU:
+            out[name]["thresholds_scanned"] = 65536 >> param
+    return out
 
 
 def _median_ms(fn, reps=5):
@@ -326,6 +356,15 @@ def cpu_baseline(pipe, vol, budget_s=12.0):
         samples += cnt
         n_pix *= 2
     render_rate = samples / spent / 1e9
+    # threshold rules of the oracle on the full histogram (Fig. 5 compares Otsu and ITS on a CPU)
+    Hfull = O.histogram(synth.to_numpy_u16(vol))
+    rules = {}
+    for name, shift, fn in [("otsu_8bit", 8, O.otsu_threshold), ("its_8bit", 8, O.its_threshold),
+                            ("otsu_16bit", 0, O.otsu_threshold), ("its_16bit", 0, O.its_threshold)]:
+        Hc = Hfull.reshape(-1, 1 << shift).sum(axis=1)
+        t0 = time.time()
+        fn(Hc)
+        rules[name] = {"ms": (time.time() - t0) * 1e3}
     # reduction oracle on a z-slab of the volume
     slab = synth.to_numpy_u16(vol[:64])
     t0 = time.time()
@@ -339,7 +378,8 @@ def cpu_baseline(pipe, vol, budget_s=12.0):
                        f"pixels of the 36 turntable views ({spent:.1f} s); reduction oracle "
                        f"(NumPy, 1 thread) on 64 of the 1024 slices: "
                        f"{red_bytes / red_s / 1e9:.3f} GB/s"),
-            "reduction_GB_per_s": red_bytes / red_s / 1e9}
+            "reduction_GB_per_s": red_bytes / red_s / 1e9,
+            "threshold_rules_ms": rules}
 
 
 def traffic_probe():
@@ -432,10 +472,12 @@ def main():
         "reduction": {"ms": res["reduction_ms"], "bytes": res["reduction_bytes"],
                       "GB_per_s": red_gbs, "frac_hbm_peak": red_gbs / HBM_PEAK_GBS,
                       "threshold": res["threshold"]},
+        "best_view": res["best_view"],
         "kernel_ms": res["kernel_ms"],
         "kernel_GB_per_s": {k: b / (res["kernel_ms"][k] * 1e-3) / 1e9
                             for k, b in res["kernel_bytes"].items()},
     }
+    line["threshold_rules"] = run_thresholds(pipe)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(pipe, vol)
     if not args.no_extras:

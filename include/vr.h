@@ -104,8 +104,9 @@ int vr_histogram(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
  *   VR_RULE_NONE: T = 0.
  *   d_result: 4 uint32 written: [0] = T (16-bit grey value), [1] = the air
  *     peak p (valley) or the iteration count (ITS), [2] = b* (valley), [3] = 0.
+ *   d_hist: 16-byte aligned (read in 16-byte pieces).
  *   d_keep_bits: 2048 uint32, overwritten (also used as scratch by the call).
- * Errors: VR_ERR_NULL, VR_ERR_RANGE (rule or param), VR_ERR_HIP.
+ * Errors: VR_ERR_NULL, VR_ERR_RANGE (rule, param or alignment), VR_ERR_HIP.
  */
 int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_hist_top, int rule, int param,
                         uint32_t* d_result, uint32_t* d_keep_bits, void* stream);
@@ -214,6 +215,9 @@ typedef struct {
     float step;                /* sample spacing along the ray, world units (> 0) */
     float ert_eps;             /* stop a ray once its transmittance < ert_eps; 0 = never */
     float bg[4];               /* background RGBA behind the volume */
+    uint32_t* view_hist;       /* NULL, or [n_views][256] device counts, overwritten by
+                                  vr_raycast with the grey-value histogram of each frame
+                                  as vr_frame_entropy defines it (for vr_entropy_from_counts) */
 } vr_render_opts;
 
 /*
@@ -248,6 +252,29 @@ typedef struct {
  */
 int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams, int n_views,
                const vr_render_opts* opts, float* d_rgba, uint64_t* d_samples, void* stream);
+
+/*
+ * Best-view snapshot (Section III-C, Eq. 2).  For each of n_views RGBA frames
+ * (f32 [n_views][height][width][4], background already composited, alpha
+ * ignored) the 256-bin histogram of the pixels' grey values, each RGB channel
+ * coded as q = floor(255 clamp(c, 0, 1) + 1/2) in FP32 (product, then sum)
+ * and grey = (77 q_r + 150 q_g + 29 q_b + 128) >> 8; its Shannon entropy
+ * H = -sum_i p_i log2 p_i over the non-empty bins (p_i = count_i / pixels,
+ * FP64); and the first view of maximal entropy.
+ *   d_hist: [n_views][256] uint32, overwritten (the counts).
+ *   d_entropy: [n_views] double, overwritten (bits).
+ *   d_best: one int32, overwritten (the view index).
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS (empty or more than 2^32 - 1 pixels per
+ * frame, more than 65535 views), VR_ERR_HIP.
+ */
+int vr_frame_entropy(const float* d_rgba, int n_views, int width, int height, uint32_t* d_hist,
+                     double* d_entropy, int32_t* d_best, void* stream);
+
+/* The entropies and the best view of vr_frame_entropy from grey-value counts
+ * already taken (vr_raycast with opts->view_hist set), pixels per frame.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_HIP. */
+int vr_entropy_from_counts(const uint32_t* d_hist, int n_views, int64_t pixels, double* d_entropy,
+                           int32_t* d_best, void* stream);
 
 /*
  * Adjoint of vr_raycast for an f32 density grid: given dLoss/dRGBA, adds

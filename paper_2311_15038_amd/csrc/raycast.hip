@@ -20,6 +20,12 @@ using namespace vr::rc;
 
 constexpr int kThreads = 256;
 
+__global__ void __launch_bounds__(kThreads) zero_u32(uint32_t* __restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 __device__ __forceinline__ void pixel_of(const Scene& S, int nb, int& view, int& i, int& j)
 {
     const int b = xcd_remap((int)blockIdx.x, nb);
@@ -38,16 +44,27 @@ raycast_fwd(const Views V, const Scene S, const float4* __restrict__ tf, float4*
             unsigned long long* __restrict__ samples)
 {
     __shared__ TfLds tf_s;
+    __shared__ uint32_t grey[256];
     stage_tf(tf_s, tf, (int)threadIdx.x, kThreads);
+    if (S.view_hist) grey[threadIdx.x] = 0u;
     __syncthreads();
     const bool skip = can_skip(S, tf_s);
     int view, i, j;
     pixel_of(S, (int)gridDim.x, view, i, j);
     uint32_t cnt = 0, evals = 0;
-    if (i < S.W && j < S.H) {
-        const float4 res = march<T, LAYOUT, COUNT, WIDE>(S, V.v[view], static_cast<const T*>(S.data), tf_s,
-                                                         skip, i, j, cnt, evals);
+    const bool in = i < S.W && j < S.H;
+    float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (in) {
+        res = march<T, LAYOUT, COUNT, WIDE>(S, V.v[view], static_cast<const T*>(S.data), tf_s, skip, i, j, cnt,
+                                            evals);
         out[((int64_t)(S.view0 + view) * S.H + j) * S.W + i] = res;
+    }
+    if (S.view_hist) {
+        // grey-value counts of the tile for the best-view snapshot (one view per workgroup)
+        vr::ent::count_grey(grey, in, vr::ent::grey_code(res));
+        __syncthreads();
+        const uint32_t c = grey[threadIdx.x];
+        if (c) atomicAdd(S.view_hist + (int64_t)(S.view0 + view) * 256 + threadIdx.x, c);
     }
     if (COUNT) {
         unsigned long long c = cnt, e = evals;
@@ -181,6 +198,12 @@ extern "C" int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_came
     if (rc) return rc;
     VR_REQUIRE(d_rgba != nullptr, VR_ERR_NULL, "vr_raycast: d_rgba is NULL");
     hipStream_t s = vr::as_stream(stream);
+    if (S.view_hist) {
+        const int64_t n = (int64_t)n_views * 256;
+        zero_u32<<<(unsigned)vr::ceil_div<int64_t>(n, kThreads), kThreads, 0, s>>>(S.view_hist, n);
+        rc = vr::check_launch("vr_raycast: view counts");
+        if (rc) return rc;
+    }
     for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
         const int nv = std::min(kMaxViews, n_views - v0);
         Views V{};

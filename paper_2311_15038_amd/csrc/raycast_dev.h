@@ -10,6 +10,7 @@
 
 #include "brick_dev.h"
 #include "common.h"
+#include "entropy_dev.h"
 
 namespace vr {
 namespace rc {
@@ -48,6 +49,7 @@ struct Scene {
     float bg[4];
     int view0;
     int tiles_x, tiles_y;
+    uint32_t* view_hist;    // [views][256] grey-value counts of the frames, or NULL
 };
 
 // Margin, in voxel units, by which skip_to stops short of a cell boundary:
@@ -558,6 +560,7 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
         const int64_t elem_bytes = (vol->dtype == VR_U16_NORM ? 2 : 4) * (vol->layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
         S.wide = (bricks > (int64_t(1) << 24) || bricks * 64 * elem_bytes > (int64_t(1) << 32)) ? 1 : 0;
     }
+    S.view_hist = o->view_hist;
     S.W = o->width;
     S.H = o->height;
     S.aspect = (float)((double)o->width / (double)o->height);

@@ -58,6 +58,8 @@ extern "C" int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_his
 {
     vr::clear_error();
     VR_REQUIRE(d_hist && d_result && d_keep_bits, VR_ERR_NULL, "vr_select_threshold: NULL pointer");
+    VR_REQUIRE((reinterpret_cast<uintptr_t>(d_hist) & 15u) == 0, VR_ERR_RANGE,
+               "vr_select_threshold: d_hist must be 16-byte aligned");
     VR_REQUIRE(rule >= VR_RULE_VALLEY && rule <= VR_RULE_NONE, VR_ERR_RANGE,
                "vr_select_threshold: unknown rule %d", rule);
     if (rule == VR_RULE_VALLEY)

@@ -47,6 +47,7 @@ static_assert(sizeof(OtsuChunk) * kMaxChunks <= 1024, "scratch");
 // LDS of a selection workgroup (shared by the three stages).
 struct SelLds {
     uint64_t X[kHalo];
+    uint64_t cb[kT];          // coarse bins of a chunk (Otsu, ITS with bin width > 1)
     uint64_t wsum[kT / 64];
     uint64_t kbuf[kT];
     int ibuf[kT];
@@ -58,14 +59,57 @@ struct SelLds {
 
 __device__ __forceinline__ uint64_t hv(const uint64_t* H, int b) { return (b >= 0 && b < kB) ? H[b] : 0; }
 
-// coarse bin b of width 2^shift, 0 outside [0, B)
-__device__ __forceinline__ uint64_t coarse(const uint64_t* H, int b, int shift)
+// sum of the 2^k (k >= 1) fine bins from f (even), in 16-byte loads issued together
+template <int N>
+__device__ __forceinline__ uint64_t sum_run(const uint64_t* __restrict__ H, int64_t f)
 {
-    if (b < 0 || b >= (kB >> shift)) return 0;
+    const uint4* p = reinterpret_cast<const uint4*>(H + f);
+    uint4 q[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) q[i] = p[i];
     uint64_t s = 0;
-    const int w = 1 << shift;
-    for (int k = 0; k < w; ++k) s += H[(b << shift) + k];
+#pragma unroll
+    for (int i = 0; i < N; ++i) s += ((uint64_t)q[i].y << 32 | q[i].x) + ((uint64_t)q[i].w << 32 | q[i].z);
     return s;
+}
+
+__device__ __forceinline__ uint64_t sum_fine(const uint64_t* __restrict__ H, int64_t f, int n)
+{
+    switch (n) {
+    case 2: return sum_run<1>(H, f);
+    case 4: return sum_run<2>(H, f);
+    case 8: return sum_run<4>(H, f);
+    case 16: return sum_run<8>(H, f);
+    case 32: return sum_run<16>(H, f);
+    default: return sum_run<32>(H, f);   // 64
+    }
+}
+
+// Coarse bin c * kT + t (width 2^shift, 0 past the last one) for thread t of
+// the workgroup.  Up to 32 fine bins per coarse bin, each thread sums its own;
+// from 64 up, each thread sums a run of 64 fine bins and adds it to its coarse
+// bin in LDS (cb) with one atomic, and with `fresh` false the sums of the
+// previous call on the same chunk are reused.  Every thread must call it.
+__device__ inline uint64_t chunk_coarse(const uint64_t* __restrict__ H, int c, int shift, uint64_t* cb,
+                                        bool fresh = true)
+{
+    const int t = threadIdx.x, b = c * kT + t;
+    if (shift == 0) return hv(H, b);
+    const int nb = kB >> shift;
+    if (shift < 6) return b < nb ? sum_fine(H, (int64_t)b << shift, 1 << shift) : 0;
+    if (fresh) {
+        cb[t] = 0;
+        __syncthreads();
+        const int64_t f0 = ((int64_t)c * kT) << shift;
+        const int64_t f = f0 + (int64_t)t * 64;
+        if (f < kB) {
+            const uint64_t v = sum_fine(H, f, 64);
+            if (v) atomicAdd(reinterpret_cast<unsigned long long*>(cb + ((f >> shift) - (int64_t)c * kT)),
+                             (unsigned long long)v);
+        }
+        __syncthreads();
+    }
+    return b < nb ? cb[t] : 0;
 }
 
 // ------------------------------------------------------------ block primitives
@@ -195,7 +239,7 @@ __device__ inline void chunk_pass(SelLds& Ls, int c, const uint64_t* __restrict_
         }
     } else {
         const int b = base + t;
-        const uint64_t h = coarse(H, b, param);
+        const uint64_t h = chunk_coarse(H, c, param, Ls.cb);
         uint64_t tn, ts;
         block_incl_scan(h, wsum, tn);
         block_incl_scan((uint64_t)b * h, wsum, ts);
@@ -259,7 +303,7 @@ __device__ inline void chunk_search(SelLds& Ls, int c, const uint64_t* __restric
         }
         const int B = kB >> param;
         const int T = base + t;
-        const uint64_t h = coarse(H, T, param);
+        const uint64_t h = chunk_coarse(H, c, param, Ls.cb);
         uint64_t tn, ts;
         const uint64_t in_n = block_incl_scan(h, wsum, tn);
         const uint64_t in_s = block_incl_scan((uint64_t)T * h, wsum, ts);
@@ -358,12 +402,15 @@ __device__ inline void finish(SelLds& Ls, const uint64_t* __restrict__ H, const 
         } else {
             if (t == 0) { s_T = (bmin + bmax + 1) / 2; s_done = 0; s_it = 0; }
             __syncthreads();
+            int c_prev = -1;
             for (int guard = 0; guard < 1000; ++guard) {
                 const int T = s_T;
                 // n_1, s_1 over coarse bins [0, T): whole chunks plus the part of chunk T / kT
                 const int c = T / kT;
                 const int b = c * kT + t;
-                const uint64_t h = b < T ? coarse(H, b, param) : 0;
+                const uint64_t hb = chunk_coarse(H, c, param, Ls.cb, c != c_prev);
+                c_prev = c;
+                const uint64_t h = b < T ? hb : 0;
                 uint64_t pn, ps;
                 block_incl_scan(h, wsum, pn);
                 block_incl_scan((uint64_t)b * h, wsum, ps);

@@ -5,7 +5,8 @@ One step, all on one stream with no host synchronisation:
   threshold selection and keep mask on the device (Sections III-A, III-D),
   thresholding fused with the box-filtered pyramid (Section II),
   slicemap atlas of one level (Section III),
-  turntable frames ray cast from one level (Section III-C).
+  turntable frames ray cast from one level (Section III-C),
+  the best view among them by frame entropy (Section III-C, Eq. 2).
 """
 from __future__ import annotations
 
@@ -73,6 +74,10 @@ class PreviewPipeline:
         self.frames = torch.empty((nv, cfg.height, cfg.width, 4), dtype=torch.float32, device=dev)
         self.tf = torch.from_numpy(synth.default_tf() if tf is None else tf).to(dev)
         self.samples = torch.zeros(2, dtype=torch.int64, device=dev)
+        # best-view snapshot of the frames (Section III-C, Eq. 2)
+        self.view_hist = torch.empty((nv, 256), dtype=torch.int32, device=dev)
+        self.view_entropy = torch.empty(nv, dtype=torch.float64, device=dev)
+        self.best_view = torch.empty(1, dtype=torch.int32, device=dev)
         self.render_vol = None
         if cfg.bricked:
             nb, nocc = vr.vr_brick_count(rx, ry, rz)
@@ -105,11 +110,17 @@ class PreviewPipeline:
             src = self.render_vol
         vr.vr_raycast(src, self.tf, self.cams, c.width, c.height, c.step,
                       ert_eps=c.ert_eps, out=self.frames, samples=self.samples if count else None,
-                      stream=stream)
+                      stream=stream, view_hist=self.view_hist)
+
+    def snapshot(self, stream=None):
+        # the ray caster took the frames' grey-value counts; entropies and the best view from them
+        vr.vr_entropy_from_counts(self.view_hist, self.cfg.width * self.cfg.height, self.view_entropy,
+                                  self.best_view, stream)
 
     def step(self, vol, stream=None, count=False):
         self.reduce(vol, stream)
         self.render(stream, count)
+        self.snapshot(stream)
 
     def calls(self, vol, stream=None):
         """The step as named library calls, in order (for per-call timing)."""
@@ -130,7 +141,8 @@ class PreviewPipeline:
             src = self.render_vol
         out.append(("raycast", lambda src=src: vr.vr_raycast(src, self.tf, self.cams, c.width, c.height,
                                                              c.step, ert_eps=c.ert_eps, out=self.frames,
-                                                             stream=stream)))
+                                                             stream=stream, view_hist=self.view_hist)))
+        out.append(("best_view", lambda: self.snapshot(stream)))
         return out
 
     REDUCTION_CALLS = ("histograms", "select", "pyramid+atlas")

@@ -66,7 +66,7 @@ class vr_batch_config(C.Structure):
 
 class vr_render_opts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("step", C.c_float),
-                ("ert_eps", C.c_float), ("bg", C.c_float * 4)]
+                ("ert_eps", C.c_float), ("bg", C.c_float * 4), ("view_hist", C.c_void_p)]
 
 
 _lib = None
@@ -92,6 +92,8 @@ def lib():
         L.vr_raycast_backward.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                           C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
         L.vr_brick_volume.argtypes = [vp, i32, i32, i64, i64, i64, vp, vp, vp]
+        L.vr_frame_entropy.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+        L.vr_entropy_from_counts.argtypes = [vp, i32, i64, vp, vp, vp]
         L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         PB = C.POINTER(vr_batch_item)
         PC = C.POINTER(vr_batch_config)
@@ -106,6 +108,7 @@ def lib():
         L.vr_version.restype = C.c_char_p
         for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
                      "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
+                     "vr_frame_entropy", "vr_entropy_from_counts",
                      "vr_brick_count", "vr_histogram_with_top", "vr_batch_workspace_size",
                      "vr_batch_plan_create", "vr_batch_launch", "vr_batch_capture", "vr_batch_status",
                      "vr_batch_item_outputs", "vr_batch_plan_destroy"):
@@ -312,18 +315,20 @@ def make_cameras(cams):
     return arr, len(cams)
 
 
-def make_opts(width, height, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0)):
+def make_opts(width, height, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0), view_hist=None):
     return vr_render_opts(int(width), int(height), float(step), float(ert_eps),
-                          (C.c_float * 4)(*[float(b) for b in bg]))
+                          (C.c_float * 4)(*[float(b) for b in bg]), view_hist)
 
 
 def vr_raycast(data, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
-               bg=(0.0, 0.0, 0.0, 0.0), out=None, samples=None, stream=None):
+               bg=(0.0, 0.0, 0.0, 0.0), out=None, samples=None, stream=None, view_hist=None):
     """RGBA frames [V][H][W][4] float32; `samples` (int64[2]) accumulates the sample
-    counts: [0] samples taken before early termination, [1] samples evaluated."""
+    counts: [0] samples taken before early termination, [1] samples evaluated;
+    `view_hist` (int32 [V][256]) receives the grey-value counts of the frames."""
     vol = make_volume(data, spacing)
     ca, nv = make_cameras(cams)
-    opts = make_opts(width, height, step, ert_eps, bg)
+    vh = None if view_hist is None else _dev(view_hist, "view_hist", torch.int32, nv * 256).value
+    opts = make_opts(width, height, step, ert_eps, bg, vh)
     if out is None:
         out = torch.empty((nv, height, width, 4), dtype=torch.float32, device=data.device)
     sp = None if samples is None else _dev(samples, "samples", torch.int64, 2)
@@ -331,6 +336,38 @@ def vr_raycast(data, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0), ert
                             C.byref(opts), _dev(out, "out", torch.float32, nv * height * width * 4),
                             sp, _stream(stream)))
     return out
+
+
+def vr_frame_entropy(frames, hist=None, entropy=None, best=None, stream=None):
+    """Best view of RGBA frames [V][H][W][4] f32 by the entropy of their grey-value
+    histograms: -> (best view int32[1], entropies f64[V], counts int32[V][256])."""
+    nv, h, w, four = frames.shape
+    if four != 4:
+        raise ValueError("frames must be [V][H][W][4]")
+    if hist is None:
+        hist = torch.empty((nv, 256), dtype=torch.int32, device=frames.device)
+    if entropy is None:
+        entropy = torch.empty(nv, dtype=torch.float64, device=frames.device)
+    if best is None:
+        best = torch.empty(1, dtype=torch.int32, device=frames.device)
+    _check(lib().vr_frame_entropy(_dev(frames, "frames", torch.float32, nv * h * w * 4), nv, w, h,
+                                  _dev(hist, "hist", torch.int32, nv * 256),
+                                  _dev(entropy, "entropy", torch.float64, nv),
+                                  _dev(best, "best", torch.int32, 1), _stream(stream)))
+    return best, entropy, hist
+
+
+def vr_entropy_from_counts(hist, pixels, entropy=None, best=None, stream=None):
+    """Entropies and best view from grey-value counts [V][256] of frames of `pixels` pixels."""
+    nv = hist.shape[0]
+    if entropy is None:
+        entropy = torch.empty(nv, dtype=torch.float64, device=hist.device)
+    if best is None:
+        best = torch.empty(1, dtype=torch.int32, device=hist.device)
+    _check(lib().vr_entropy_from_counts(_dev(hist, "hist", torch.int32, nv * 256), nv, int(pixels),
+                                        _dev(entropy, "entropy", torch.float64, nv),
+                                        _dev(best, "best", torch.int32, 1), _stream(stream)))
+    return best, entropy
 
 
 def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba, grad_density,

@@ -115,3 +115,17 @@ def test_frames_on_sampled_pixels(full, level1):
     assert err <= 2e-4, err
     assert ref[:, 3].max() > 0.5                          # the sample sees the specimen
     assert int(pipe.samples[1].item()) <= int(pipe.samples[0].item())
+
+
+@pytest.mark.parametrize("shift", [8, 0])
+def test_otsu_and_its_full_histogram(full, shift):
+    """Algorithms 1 and 2 on the full volume's histogram, on 256 (8-bit) and 65536 bins."""
+    from paper_2311_15038_amd import vr
+    pipe, a, H, Ht, T, bits = full
+    banner(f"fullsize: otsu / its shift {shift}")
+    Hc = H.reshape(-1, 1 << shift).sum(axis=1)
+    res, _ = vr.vr_select_threshold(pipe.hist, None, vr.RULE_OTSU, shift)
+    assert int(res[0].item()) == O.otsu_threshold(Hc) << shift
+    res, _ = vr.vr_select_threshold(pipe.hist, None, vr.RULE_ITS, shift)
+    Ti, it = O.its_threshold(Hc)
+    assert int(res[0].item()) == Ti << shift and int(res[1].item()) == it
