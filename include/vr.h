@@ -120,6 +120,62 @@ int vr_select_threshold(const uint64_t* d_hist, const uint64_t* d_hist_top, int 
 int vr_histogram_with_top(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
                           int64_t top_slices, uint64_t* d_hist, uint64_t* d_hist_top, void* stream);
 
+/*
+ * Container removal (Section III-B).  The sample container is a cylinder
+ * about the z axis; its circle is found in one slice (the top slice, slice 0
+ * of the stack) with the Hough transform of Ioannou et al., and every voxel
+ * outside it is discarded in every slice.  The circle record is 8 int32:
+ *   [0] found (1/0), [1] cx, [2] cy (pixel of the centre), [3] r (detected
+ *   radius of the wall's inner boundary), [4] R = max(r - margin, 0) (kept
+ *   radius), [5] centre votes (box sum, saturated to 2^31 - 1), [6] count of
+ *   the radius, [7] edge pixels.
+ * The kept disc holds the pixels with (x - cx)^2 + (y - cy)^2 <= R^2; a record
+ * with found = 0 keeps every pixel.
+ */
+#define VR_CIRCLE_INTS 8
+
+/* Workspace bytes vr_find_container needs for an nx x ny slice and r_max.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (as vr_find_container). */
+int vr_container_workspace_size(int64_t nx, int64_t ny, int r_max, int64_t* bytes);
+
+/*
+ * The container's circle in the u16 slice d_slice [ny][nx] (3..8192 pixels a
+ * side), all on the device:
+ *   edges: the integer 3 x 3 Sobel gradient g of the interior pixels; a pixel
+ *     is an edge when |g|^2 > 0 and |g|^2 * 2^edge_shift >= the slice's
+ *     largest |g|^2 (edge_shift 0..16, 4 typical);
+ *   votes: each edge pixel votes once for every cell of the digital line from
+ *     it against its gradient (one cell per step along the gradient's major
+ *     axis, the minor offset rounded half up) whose distance from it along the
+ *     line lies in [r_min, r_max] (1 <= r_min <= r_max <= 4096);
+ *   centre: the first maximum, in row-major order, of the votes summed over
+ *     (2w+1)^2 boxes, w = max(1, r_max / 16);
+ *   radius: the first maximum (smallest radius) of round(|p - c|) over the
+ *     edge pixels p whose gradient points away from the centre, in
+ *     [r_min, r_max]; kept radius R = max(r - margin, 0), margin >= 0.
+ * All decisions are integer arithmetic.
+ *   d_work: >= vr_container_workspace_size bytes, 256-byte aligned, scratch.
+ *   d_circle: VR_CIRCLE_INTS int32, overwritten.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (radii, shift, margin or
+ * workspace alignment), VR_ERR_WORKSPACE, VR_ERR_HIP.
+ */
+int vr_find_container(const uint16_t* d_slice, int64_t nx, int64_t ny, int r_min, int r_max,
+                      int edge_shift, int margin, void* d_work, int64_t work_bytes,
+                      int32_t* d_circle, void* stream);
+
+/* Sets every voxel outside the kept disc of d_circle to 0, in every slice of
+ * d_vol [nz][ny][nx], in place (nothing changes when the circle was not
+ * found).  Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_HIP. */
+int vr_remove_container(uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz, const int32_t* d_circle,
+                        void* stream);
+
+/* vr_histogram_with_top restricted to the voxels inside the kept disc of
+ * d_circle: voxels outside it take no part in either histogram.  d_hist_top
+ * may be NULL (top_slices is then ignored).  Both outputs are overwritten.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE, VR_ERR_HIP. */
+int vr_histogram_in_disc(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz, int64_t top_slices,
+                         const int32_t* d_circle, uint64_t* d_hist, uint64_t* d_hist_top, void* stream);
+
 /* A slicemap atlas written as a side output of vr_threshold_downsample. */
 typedef struct {
     int32_t level;             /* pyramid level (1..n_levels) packed into the atlas */
@@ -147,6 +203,15 @@ typedef struct {
 int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
                             const uint32_t* d_keep_bits, int n_levels,
                             uint16_t* const* h_levels, const vr_atlas_spec* atlas, void* stream);
+
+/* vr_threshold_downsample with every voxel outside the kept disc of d_circle
+ * (see vr_find_container) counted as removed, so the levels equal those of
+ * the volume after vr_remove_container; d_vol is not modified.  Slices of at
+ * most 8192 x 8192.  Errors: as vr_threshold_downsample, and VR_ERR_NULL for
+ * d_circle. */
+int vr_threshold_downsample_in_disc(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
+                                    const uint32_t* d_keep_bits, const int32_t* d_circle, int n_levels,
+                                    uint16_t* const* h_levels, const vr_atlas_spec* atlas, void* stream);
 
 /*
  * Slicemap atlas of a volume level (Section III, slicemaps of the cited

@@ -11,6 +11,12 @@
 // keep mask is one interval [T, 65535] (a plain threshold, or a top-slice
 // filter that removed nothing above T) a voxel is kept by a compare instead
 // of the LDS lookup; each workgroup detects that once from the mask.
+//
+// With container removal (Section III-B) a voxel outside the kept disc of
+// its slice counts as removed: each workgroup tabulates the kept column run
+// of every image row in LDS once, loads only the 16-byte pieces that touch
+// the disc and zeroes the voxels of a piece that fall outside it.
+#include "disc_dev.h"
 #include "downsample_dev.h"
 
 namespace {
@@ -69,33 +75,65 @@ __device__ __forceinline__ WideTile wide_tile(int tile, int tiles_x, int tiles_y
 __device__ __forceinline__ int pair_y(int h, int it) { return 2 * (h & 3) + (it & 1); }
 __device__ __forceinline__ int pair_z(int h, int it) { return 2 * (h >> 2) + (it >> 1); }
 
+constexpr int kMaxDiscSide = 8192;          // rows tabulated by the disc variant
+
+// Bits e (0..7) of the voxels x + e of a row inside its kept run, from the
+// packed run x0 | x1 << 16 (an empty run has x0 > x1).
+__device__ __forceinline__ uint32_t run_bits(uint32_t sp, int x)
+{
+    const int lo = max((int)(sp & 0xFFFFu) - x, 0), hi = min((int)(sp >> 16) - x, 7);
+    return lo > hi ? 0u : (0xFFu >> (7 - hi)) & (0xFFu << lo);
+}
+
+// Zero the voxels of an 8-voxel piece whose bit in k is clear.
+__device__ __forceinline__ uint4 mask_piece(uint4 q, uint32_t k)
+{
+    auto m = [k](int i) {
+        return (((k >> (2 * i)) & 1u) ? 0x0000FFFFu : 0u) | (((k >> (2 * i + 1)) & 1u) ? 0xFFFF0000u : 0u);
+    };
+    return make_uint4(q.x & m(0), q.y & m(1), q.z & m(2), q.w & m(3));
+}
+
 // The four rows (y pair yp, z pair zp) of the lane's 8-voxel x-run, zero past
-// the volume's end.
+// the volume's end (and, with DISC, outside the kept disc of the rows).
+template <bool DISC>
 __device__ __forceinline__ void load_rows(const uint16_t* __restrict__ vol, int nx, int ny, int nz,
-                                          const WideTile& t, int yp, int zp, int l, uint4 (&q)[4])
+                                          const WideTile& t, int yp, int zp, int l, const uint32_t* spans,
+                                          uint4 (&q)[4])
 {
     const int x = t.X0 + 8 * l, y = t.Y0 + 2 * yp, z = t.Z0 + 2 * zp;
     const int64_t nxy = (int64_t)nx * ny;
     const uint16_t* p = vol + ((int64_t)z * ny + y) * nx + x;
-    if (t.interior) {
-        q[0] = load_stream(p);
-        q[1] = load_stream(p + nx);
-        q[2] = load_stream(p + nxy);
-        q[3] = load_stream(p + nxy + nx);
-        return;
+    uint32_t kb[2] = {0xFFu, 0xFFu};
+    if (DISC) {
+        kb[0] = y < ny ? run_bits(spans[y], x) : 0u;
+        kb[1] = y + 1 < ny ? run_bits(spans[y + 1], x) : 0u;
     }
+    if (t.interior) {
+        const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+        q[0] = !DISC || kb[0] ? load_stream(p) : zero;
+        q[1] = !DISC || kb[1] ? load_stream(p + nx) : zero;
+        q[2] = !DISC || kb[0] ? load_stream(p + nxy) : zero;
+        q[3] = !DISC || kb[1] ? load_stream(p + nxy + nx) : zero;
+    } else {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const bool rowok = y + (r & 1) < ny && z + (r >> 1) < nz;
-        const uint16_t* row = p + (r & 1) * (int64_t)nx + (r >> 1) * nxy;
-        uint32_t w[4];
+        for (int r = 0; r < 4; ++r) {
+            const bool rowok = y + (r & 1) < ny && z + (r >> 1) < nz && (!DISC || kb[r & 1]);
+            const uint16_t* row = p + (r & 1) * (int64_t)nx + (r >> 1) * nxy;
+            uint32_t w[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint32_t lo = (rowok && x + 2 * e < nx) ? (uint32_t)row[2 * e] : 0u;
-            const uint32_t hi = (rowok && x + 2 * e + 1 < nx) ? (uint32_t)row[2 * e + 1] : 0u;
-            w[e] = lo | (hi << 16);
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t lo = (rowok && x + 2 * e < nx) ? (uint32_t)row[2 * e] : 0u;
+                const uint32_t hi = (rowok && x + 2 * e + 1 < nx) ? (uint32_t)row[2 * e + 1] : 0u;
+                w[e] = lo | (hi << 16);
+            }
+            q[r] = make_uint4(w[0], w[1], w[2], w[3]);
         }
-        q[r] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    if (DISC) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (kb[r & 1] != 0xFFu) q[r] = mask_piece(q[r], kb[r & 1]);
     }
 }
 
@@ -225,10 +263,11 @@ __device__ __forceinline__ void coarse_levels(const WideTile& t, int n_levels, c
 // sequence of steps (tile, it); the rows of the next two steps are in flight
 // while the current step is summed, and the coarse levels of a tile are
 // reduced while the first rows of the next tile arrive.
-template <int MODE>
+template <int MODE, bool DISC>
 __device__ inline void wide_tiles(const uint16_t* __restrict__ vol, int nx, int ny, int nz, int aligned,
                                   int aligned_out, const uint32_t* bits, uint32_t T, int n_levels,
-                                  const LevelOut& L, int tiles_x, int tiles_y, int n_tiles, WideLds& G)
+                                  const LevelOut& L, int tiles_x, int tiles_y, int n_tiles, WideLds& G,
+                                  const uint32_t* spans)
 {
     const int tid = threadIdx.x, h = tid >> 5, l = tid & 31;
     const int my_tiles = n_tiles > (int)blockIdx.x ? (n_tiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
@@ -243,13 +282,13 @@ __device__ inline void wide_tiles(const uint16_t* __restrict__ vol, int nx, int 
     uint4 q[LA][4];
 #pragma unroll
     for (int a = 0; a < LA - 1; ++a)
-        if (a < steps) load_rows(vol, nx, ny, nz, t0, pair_y(h, a), pair_z(h, a), l, q[a]);
+        if (a < steps) load_rows<DISC>(vol, nx, ny, nz, t0, pair_y(h, a), pair_z(h, a), l, spans, q[a]);
     uint32_t l2[2] = {0u, 0u};
     for (int k = 0; k < steps; ++k) {
         if (k + LA - 1 < steps) {
             const int kn = k + LA - 1, itn = kn & 3;
             if (itn == 0) tl = tile_at(kn >> 2);
-            load_rows(vol, nx, ny, nz, tl, pair_y(h, itn), pair_z(h, itn), l, q[LA - 1]);
+            load_rows<DISC>(vol, nx, ny, nz, tl, pair_y(h, itn), pair_z(h, itn), l, spans, q[LA - 1]);
         }
         const int it = k & 3;
         level1_step<MODE>(q[0], bits, T, t2, t0, pair_y(h, it), pair_z(h, it), l, aligned_out, L, l2);
@@ -265,31 +304,54 @@ __device__ inline void wide_tiles(const uint16_t* __restrict__ vol, int nx, int 
     }
 }
 
+template <bool DISC>
 __global__ void __launch_bounds__(WT)
 downsample_kernel(const uint16_t* __restrict__ vol, int nx, int ny, int nz, int aligned, int aligned_out,
                   const uint32_t* __restrict__ keep_bits, int n_levels, LevelOut L, int tiles_x,
-                  int tiles_y, int n_tiles)
+                  int tiles_y, int n_tiles, const int32_t* __restrict__ circle)
 {
     __shared__ uint32_t bits[VR_KEEP_WORDS];
     __shared__ WideLds G;
     __shared__ uint32_t s_first, s_bad;
+    __shared__ uint32_t spans[DISC ? kMaxDiscSide : 1];
+    if (DISC) {
+        const vr::disc::Disc d = vr::disc::load_disc(circle);
+        for (int y = threadIdx.x; y < ny; y += WT) {
+            int64_t x0, x1;
+            vr::disc::row_span(d, y, nx, x0, x1);
+            spans[y] = x0 > x1 ? 0x0000FFFFu : (uint32_t)x0 | ((uint32_t)x1 << 16);
+        }
+        __syncthreads();
+    }
     const uint32_t T = keep_bits == nullptr ? 0u : load_mask(keep_bits, bits, s_first, s_bad);
     if (T == 0u)
-        wide_tiles<KEEP_ALL>(vol, nx, ny, nz, aligned, aligned_out, bits, T, n_levels, L, tiles_x, tiles_y, n_tiles, G);
+        wide_tiles<KEEP_ALL, DISC>(vol, nx, ny, nz, aligned, aligned_out, bits, T, n_levels, L, tiles_x, tiles_y,
+                                   n_tiles, G, spans);
     else if (T <= VR_NBINS)
-        wide_tiles<KEEP_INTERVAL>(vol, nx, ny, nz, aligned, aligned_out, bits, T, n_levels, L, tiles_x, tiles_y, n_tiles, G);
+        wide_tiles<KEEP_INTERVAL, DISC>(vol, nx, ny, nz, aligned, aligned_out, bits, T, n_levels, L, tiles_x,
+                                        tiles_y, n_tiles, G, spans);
     else
-        wide_tiles<KEEP_LOOKUP>(vol, nx, ny, nz, aligned, aligned_out, bits, 0u, n_levels, L, tiles_x, tiles_y, n_tiles, G);
+        wide_tiles<KEEP_LOOKUP, DISC>(vol, nx, ny, nz, aligned, aligned_out, bits, 0u, n_levels, L, tiles_x,
+                                      tiles_y, n_tiles, G, spans);
+}
+
+template <bool DISC>
+int occupancy()
+{
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, downsample_kernel<DISC>, WT, 0) == hipSuccess && n > 0
+               ? n
+               : 1;
 }
 
 }  // namespace
 
-extern "C" int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
-                                       const uint32_t* d_keep_bits, int n_levels,
-                                       uint16_t* const* h_levels, const vr_atlas_spec* atlas,
-                                       void* stream)
+namespace {
+
+int downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz, const uint32_t* d_keep_bits,
+               const int32_t* d_circle, int n_levels, uint16_t* const* h_levels, const vr_atlas_spec* atlas,
+               void* stream)
 {
-    vr::clear_error();
     VR_REQUIRE(d_vol && h_levels, VR_ERR_NULL, "vr_threshold_downsample: NULL pointer");
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
                VR_ERR_DIMS, "vr_threshold_downsample: dims %lld x %lld x %lld", (long long)nx,
@@ -348,14 +410,41 @@ extern "C" int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_
     const int64_t tiles = (int64_t)tiles_x * tiles_y * ((nz + TZ - 1) / TZ);
     VR_REQUIRE(tiles < (int64_t(1) << 31), VR_ERR_DIMS, "vr_threshold_downsample: volume too large");
     // one resident round of workgroups (as many per compute unit as registers and LDS allow)
-    static const int per_cu = [] {
-        int n = 0;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, downsample_kernel, WT, 0) == hipSuccess && n > 0 ? n : 1;
-    }();
-    int64_t grid = (int64_t)vr::num_cus() * per_cu;
+    static const int per_cu_plain = occupancy<false>();
+    static const int per_cu_disc = occupancy<true>();
+    int64_t grid = (int64_t)vr::num_cus() * (d_circle ? per_cu_disc : per_cu_plain);
     if (grid > tiles) grid = tiles;
-    downsample_kernel<<<(unsigned)grid, WT, 0, s>>>(
-        d_vol, (int)nx, (int)ny, (int)nz, aligned, aligned_out, d_keep_bits, n_levels, L, tiles_x,
-        tiles_y, (int)tiles);
+    if (d_circle)
+        downsample_kernel<true><<<(unsigned)grid, WT, 0, s>>>(d_vol, (int)nx, (int)ny, (int)nz, aligned, aligned_out,
+                                                              d_keep_bits, n_levels, L, tiles_x, tiles_y, (int)tiles,
+                                                              d_circle);
+    else
+        downsample_kernel<false><<<(unsigned)grid, WT, 0, s>>>(d_vol, (int)nx, (int)ny, (int)nz, aligned,
+                                                               aligned_out, d_keep_bits, n_levels, L, tiles_x,
+                                                               tiles_y, (int)tiles, nullptr);
     return vr::check_launch("vr_threshold_downsample");
+}
+
+}  // namespace
+
+extern "C" int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
+                                       const uint32_t* d_keep_bits, int n_levels,
+                                       uint16_t* const* h_levels, const vr_atlas_spec* atlas,
+                                       void* stream)
+{
+    vr::clear_error();
+    return downsample(d_vol, nx, ny, nz, d_keep_bits, nullptr, n_levels, h_levels, atlas, stream);
+}
+
+extern "C" int vr_threshold_downsample_in_disc(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
+                                               const uint32_t* d_keep_bits, const int32_t* d_circle,
+                                               int n_levels, uint16_t* const* h_levels,
+                                               const vr_atlas_spec* atlas, void* stream)
+{
+    vr::clear_error();
+    VR_REQUIRE(d_circle != nullptr, VR_ERR_NULL, "vr_threshold_downsample_in_disc: d_circle is NULL");
+    VR_REQUIRE(nx <= kMaxDiscSide && ny <= kMaxDiscSide, VR_ERR_DIMS,
+               "vr_threshold_downsample_in_disc: slices of %lld x %lld exceed %d x %d", (long long)nx,
+               (long long)ny, kMaxDiscSide, kMaxDiscSide);
+    return downsample(d_vol, nx, ny, nz, d_keep_bits, d_circle, n_levels, h_levels, atlas, stream);
 }

@@ -1,6 +1,8 @@
 """The preview pipeline for one volume: buffers plus the ordered library calls.
 
 One step, all on one stream with no host synchronisation:
+  optionally, the container's circle in the top slice (Section III-B), after
+    which every voxel outside it is left out of the steps below,
   histogram of the volume and of its first three slices (Section III-D),
   threshold selection and keep mask on the device (Sections III-A, III-D),
   thresholding fused with the box-filtered pyramid (Section II),
@@ -37,6 +39,10 @@ class PreviewConfig:
     bricked: bool = True            # render from the 4^3-brick layout
     pairs: bool = False             # ... of x-tap pairs (two voxels per load, twice the memory)
     skip_empty: bool = True         # with the brick occupancy (exact)
+    container: bool = False         # remove the sample container (Section III-B)
+    container_radii: tuple | None = None   # (r_min, r_max); None: [min side / 8, min side / 2]
+    container_shift: int = 4        # edges: |g|^2 >= 2^-shift of the largest
+    container_margin: int = 2       # kept radius = detected radius - margin
 
 
 def atlas_tiles(nz: int):
@@ -78,6 +84,13 @@ class PreviewPipeline:
         self.view_hist = torch.empty((nv, 256), dtype=torch.int32, device=dev)
         self.view_entropy = torch.empty(nv, dtype=torch.float64, device=dev)
         self.best_view = torch.empty(1, dtype=torch.int32, device=dev)
+        self.circle = self.container_work = None
+        if cfg.container:
+            nz, ny, nx = self.shape
+            self.radii = cfg.container_radii or vr.container_radii(nx, ny)
+            self.circle = torch.zeros(vr.CIRCLE_INTS, dtype=torch.int32, device=dev)
+            self.container_work = torch.empty(vr.vr_container_workspace_size(nx, ny, self.radii[1]),
+                                              dtype=torch.uint8, device=dev)
         self.render_vol = None
         if cfg.bricked:
             nb, nocc = vr.vr_brick_count(rx, ry, rz)
@@ -92,15 +105,35 @@ class PreviewPipeline:
             return None
         return (self.cfg.atlas_level, self.tiles[0], self.tiles[1], 16, self.atlas)
 
-    # the reduction half: three launches-worth of calls (histograms, selection,
-    # pyramid with its atlas written in the same pass)
-    def reduce(self, vol, stream=None):
+    def find_container(self, vol, stream=None):
         c = self.cfg
-        vr.vr_histogram_with_top(vol, c.top_slices, self.hist, self.hist_top, stream)
+        vr.vr_find_container(vol[0], self.radii[0], self.radii[1], c.container_shift,
+                             c.container_margin, self.container_work, self.circle, stream)
+
+    def histograms(self, vol, stream=None):
+        c = self.cfg
+        if self.circle is not None:
+            vr.vr_histogram_in_disc(vol, self.circle, c.top_slices, self.hist, self.hist_top, stream)
+        else:
+            vr.vr_histogram_with_top(vol, c.top_slices, self.hist, self.hist_top, stream)
+
+    def select(self, stream=None):
+        c = self.cfg
         vr.vr_select_threshold(self.hist, self.hist_top, c.rule, c.rule_param, self.result,
                                self.keep, stream)
-        vr.vr_threshold_downsample(vol, self.keep, c.n_levels, self.levels, self._atlas_arg(),
-                                   stream)
+
+    def pyramid(self, vol, stream=None):
+        vr.vr_threshold_downsample(vol, self.keep, self.cfg.n_levels, self.levels, self._atlas_arg(),
+                                   stream, circle=self.circle)
+
+    # the reduction half: (the container's circle,) histograms, selection, pyramid
+    # with its atlas written in the same pass
+    def reduce(self, vol, stream=None):
+        if self.circle is not None:
+            self.find_container(vol, stream)
+        self.histograms(vol, stream)
+        self.select(stream)
+        self.pyramid(vol, stream)
 
     def render(self, stream=None, count=False):
         c = self.cfg
@@ -125,13 +158,11 @@ class PreviewPipeline:
     def calls(self, vol, stream=None):
         """The step as named library calls, in order (for per-call timing)."""
         c = self.cfg
-        out = [
-            ("histograms", lambda: vr.vr_histogram_with_top(vol, c.top_slices, self.hist,
-                                                            self.hist_top, stream)),
-            ("select", lambda: vr.vr_select_threshold(self.hist, self.hist_top, c.rule,
-                                                      c.rule_param, self.result, self.keep, stream)),
-            ("pyramid+atlas", lambda: vr.vr_threshold_downsample(
-                vol, self.keep, c.n_levels, self.levels, self._atlas_arg(), stream)),
+        out = [("container", lambda: self.find_container(vol, stream))] if self.circle is not None else []
+        out += [
+            ("histograms", lambda: self.histograms(vol, stream)),
+            ("select", lambda: self.select(stream)),
+            ("pyramid+atlas", lambda: self.pyramid(vol, stream)),
         ]
         level = self.levels[c.render_level - 1]
         src = level

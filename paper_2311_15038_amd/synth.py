@@ -4,7 +4,10 @@ The paper evaluates on five NOVA arthropod scans (Table II) that are not
 public.  These generators stand in for them: a 16-bit volume of air around a
 specimen made of nested ellipsoids and thin tubes, with per-class noise, and
 both three-slice end slabs left as pure air (the histogram-filtering step of
-Section III-D assumes the top slices hold only the surroundings).
+Section III-D assumes the top slices hold only the surroundings).  Optionally
+the specimen stands in a cylindrical container (a plastic wall about the z
+axis over every slice, Section III-B), which the top slices then show as a
+ring.
 
 This module holds no step of the preview method itself: it only draws inputs.
 Primitive geometry is drawn with NumPy's PCG64 from the seed, so it is the
@@ -20,9 +23,9 @@ import numpy as np
 import torch
 
 # class id -> (mean grey value, noise sigma); ids index these tables.
-AIR, OUTER, MIDDLE, INNER, TUBE = 0, 1, 2, 3, 4
-CLASS_MU = (1000.0, 8000.0, 15000.0, 30000.0, 22000.0)
-CLASS_SIGMA = (40.0, 300.0, 400.0, 500.0, 450.0)
+AIR, OUTER, MIDDLE, INNER, TUBE, CONTAINER = 0, 1, 2, 3, 4, 5
+CLASS_MU = (1000.0, 8000.0, 15000.0, 30000.0, 22000.0, 7000.0)
+CLASS_SIGMA = (40.0, 300.0, 400.0, 500.0, 450.0, 300.0)
 
 BASE = 128.0          # primitives are defined in a 128^3 base frame
 END_SLAB = 3          # slices at each z end that stay pure air
@@ -40,6 +43,9 @@ class VolumeSpec:
     semi_axes: tuple = (50.0, 30.0, 12.0)
     aspect: tuple = (1.0, 0.8, 0.65)
     tube_radius: float = 2.0
+    # cylindrical container: (centre x, centre y, inner radius, wall thickness)
+    # in the base frame, over all slices; None = no container
+    container: tuple | None = None
 
     @property
     def shape(self):
@@ -48,6 +54,12 @@ class VolumeSpec:
 
 SMALL = VolumeSpec(128, 128, 128, seed=2311)
 FULL = VolumeSpec(1024, 1024, 1024, seed=2312, n_extra=477, noise="poisson64")
+# the small and full scenes with a smaller specimen standing in a container
+CONTAINER_RING = (64.6, 63.3, 60.0, 3.0)
+SMALL_CONTAINED = VolumeSpec(128, 128, 128, seed=2313, semi_axes=(40.0, 24.0, 9.0),
+                             container=CONTAINER_RING)
+FULL_CONTAINED = VolumeSpec(1024, 1024, 1024, seed=2314, n_extra=477, noise="poisson64",
+                            semi_axes=(40.0, 24.0, 9.0), container=CONTAINER_RING)
 
 
 @dataclass
@@ -90,12 +102,26 @@ def _index_range(lo_base, hi_base, scale, n):
     return i0, i1
 
 
+def _paint_container(lab: torch.Tensor, spec: VolumeSpec, sc):
+    """The container wall: voxel centres whose base-frame distance from the
+    axis lies in [inner radius, inner radius + thickness], in every slice."""
+    cx, cy, r0, w = spec.container
+    dev = lab.device
+    xs = (torch.arange(spec.nx, device=dev, dtype=torch.float64) + 0.5) / float(sc[0]) - cx
+    ys = (torch.arange(spec.ny, device=dev, dtype=torch.float64) + 0.5) / float(sc[1]) - cy
+    d2 = xs[None, :] ** 2 + ys[:, None] ** 2
+    ring = (d2 >= r0 * r0) & (d2 <= (r0 + w) ** 2)
+    lab.masked_fill_(ring[None, :, :], CONTAINER)
+
+
 def make_labels(spec: VolumeSpec, device="cpu") -> torch.Tensor:
     """Class id per voxel, int8 [nz][ny][nx]; later primitives paint over earlier ones."""
     dev = torch.device(device)
     lab = torch.zeros(spec.shape, dtype=torch.int8, device=dev)
     sc = np.array([spec.nx, spec.ny, spec.nz], dtype=np.float64) / BASE
     n = (spec.nx, spec.ny, spec.nz)
+    if spec.container is not None:
+        _paint_container(lab, spec, sc)
     zlo, zhi = END_SLAB, spec.nz - END_SLAB
     if zhi <= zlo:
         return lab

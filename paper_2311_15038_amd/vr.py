@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvr.so")
 
 NBINS = 65536
 KEEP_WORDS = 2048
+CIRCLE_INTS = 8
 MAX_LEVELS = 4
 MAX_VIEWS_PER_LAUNCH = 48
 RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
@@ -86,6 +87,12 @@ def lib():
         L.vr_threshold_downsample.argtypes = [vp, i64, i64, i64, vp, i32, C.POINTER(vp),
                                               C.POINTER(vr_atlas_spec), vp]
         L.vr_histogram_with_top.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
+        L.vr_container_workspace_size.argtypes = [i64, i64, i32, C.POINTER(C.c_int64)]
+        L.vr_find_container.argtypes = [vp, i64, i64, i32, i32, i32, i32, vp, i64, vp, vp]
+        L.vr_remove_container.argtypes = [vp, i64, i64, i64, vp, vp]
+        L.vr_histogram_in_disc.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp]
+        L.vr_threshold_downsample_in_disc.argtypes = [vp, i64, i64, i64, vp, vp, i32, C.POINTER(vp),
+                                                      C.POINTER(vr_atlas_spec), vp]
         L.vr_pack_slicemap.argtypes = [vp, i64, i64, i64, i32, i32, i32, vp, vp]
         L.vr_raycast.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                  C.POINTER(vr_render_opts), vp, vp, vp]
@@ -108,7 +115,9 @@ def lib():
         L.vr_version.restype = C.c_char_p
         for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
                      "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
-                     "vr_frame_entropy", "vr_entropy_from_counts",
+                     "vr_frame_entropy", "vr_entropy_from_counts", "vr_container_workspace_size",
+                     "vr_find_container", "vr_remove_container", "vr_histogram_in_disc",
+                     "vr_threshold_downsample_in_disc",
                      "vr_brick_count", "vr_histogram_with_top", "vr_batch_workspace_size",
                      "vr_batch_plan_create", "vr_batch_launch", "vr_batch_capture", "vr_batch_status",
                      "vr_batch_item_outputs", "vr_batch_plan_destroy"):
@@ -192,16 +201,73 @@ def vr_select_threshold(hist, hist_top=None, rule=RULE_VALLEY, param=32, result=
     return result, keep_bits
 
 
+# ---------------------------------------------------------- container removal
+def vr_container_workspace_size(nx, ny, r_max):
+    b = C.c_int64(0)
+    _check(lib().vr_container_workspace_size(int(nx), int(ny), int(r_max), C.byref(b)))
+    return int(b.value)
+
+
+def container_radii(nx, ny):
+    """Default radius range of the container search: [min side / 8, min side / 2]."""
+    m = min(nx, ny)
+    return max(1, m // 8), max(1, m // 2)
+
+
+def vr_find_container(slice2d, r_min=None, r_max=None, edge_shift=4, margin=2, work=None, circle=None,
+                      stream=None):
+    """Circle record (int32[8] on the device) of the container in a u16 slice [ny][nx]."""
+    ny, nx = slice2d.shape
+    lo, hi = container_radii(nx, ny)
+    r_min = lo if r_min is None else r_min
+    r_max = hi if r_max is None else r_max
+    need = vr_container_workspace_size(nx, ny, r_max)
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=slice2d.device)
+    if circle is None:
+        circle = torch.empty(CIRCLE_INTS, dtype=torch.int32, device=slice2d.device)
+    _check(lib().vr_find_container(_dev(slice2d, "slice", _U16), nx, ny, int(r_min), int(r_max),
+                                   int(edge_shift), int(margin), _dev(work, "work", torch.uint8, need),
+                                   work.numel(), _dev(circle, "circle", torch.int32, CIRCLE_INTS),
+                                   _stream(stream)))
+    return circle
+
+
+def vr_remove_container(vol, circle, stream=None):
+    """Zero every voxel outside the kept disc, in place; returns vol."""
+    nz, ny, nx = vol.shape
+    _check(lib().vr_remove_container(_dev(vol, "vol", _U16), nx, ny, nz,
+                                     _dev(circle, "circle", torch.int32, CIRCLE_INTS), _stream(stream)))
+    return vol
+
+
+def vr_histogram_in_disc(vol, circle, top_slices=3, hist=None, hist_top=None, stream=None):
+    """Histograms of the voxels inside the kept disc: the whole volume and its
+    first top_slices slices (top_slices 0: no top histogram, returns None)."""
+    nz, ny, nx = vol.shape
+    if hist is None:
+        hist = torch.empty(NBINS, dtype=torch.int64, device=vol.device)
+    if hist_top is None and top_slices:
+        hist_top = torch.empty(NBINS, dtype=torch.int64, device=vol.device)
+    top = _dev(hist_top, "hist_top", torch.int64, NBINS) if top_slices else None
+    _check(lib().vr_histogram_in_disc(_dev(vol, "vol", _U16), nx, ny, nz, int(top_slices),
+                                      _dev(circle, "circle", torch.int32, CIRCLE_INTS),
+                                      _dev(hist, "hist", torch.int64, NBINS), top, _stream(stream)))
+    return hist, (hist_top if top_slices else None)
+
+
 def level_shape(shape, k):
     d = 1 << k
     return tuple(-(-n // d) for n in shape)
 
 
-def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, stream=None):
+def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, stream=None, circle=None):
     """Filtered pyramid levels 1..n_levels (list of uint16 tensors).
 
     atlas: None or (level, tiles_x, tiles_y, out_bits, tensor): the slicemap
     atlas of that level, written in the same pass.
+    circle: None, or a container circle record (vr_find_container): voxels
+    outside its kept disc count as removed (vr_threshold_downsample_in_disc).
     """
     nz, ny, nx = vol.shape
     if levels is None:
@@ -223,8 +289,13 @@ def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, s
         dt = (torch.uint16, torch.int16) if bits == 16 else torch.uint8
         spec = C.byref(vr_atlas_spec(int(lvl), int(tx), int(ty), int(bits),
                                      _dev(t, "atlas", dt, tx * ty * lx * ly).value))
-    _check(lib().vr_threshold_downsample(_dev(vol, "vol", _U16), nx, ny, nz, kb, int(n_levels),
-                                         ptrs, spec, _stream(stream)))
+    if circle is None:
+        _check(lib().vr_threshold_downsample(_dev(vol, "vol", _U16), nx, ny, nz, kb, int(n_levels),
+                                             ptrs, spec, _stream(stream)))
+    else:
+        _check(lib().vr_threshold_downsample_in_disc(
+            _dev(vol, "vol", _U16), nx, ny, nz, kb, _dev(circle, "circle", torch.int32, CIRCLE_INTS),
+            int(n_levels), ptrs, spec, _stream(stream)))
     return levels
 
 

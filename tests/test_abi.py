@@ -98,3 +98,29 @@ def test_brick_validation_on_the_host(lib):
     n, o = C.c_int64(0), C.c_int64(0)
     assert lib.vr_brick_count(9, 5, 4, C.byref(n), C.byref(o)) == 0
     assert n.value == 3 * 2 * 1 and o.value == 6 + 1
+
+
+def test_container_validation_on_the_host(lib):
+    from paper_2311_15038_amd import vr
+    p, b = C.c_void_p(256), C.c_int64(0)
+    a256 = lambda n: (n + 255) // 256 * 256  # noqa: E731
+    assert lib.vr_container_workspace_size(100, 80, 40, C.byref(b)) == 0
+    assert b.value == a256(24) + a256(4 * 41) + a256(4 * 8000) + a256(8 * 8000) + a256(16 * 98 * 78)
+    assert lib.vr_container_workspace_size(2, 80, 40, C.byref(b)) == -2          # slice too small
+    assert lib.vr_container_workspace_size(8193, 80, 40, C.byref(b)) == -2
+    assert lib.vr_container_workspace_size(100, 80, 4097, C.byref(b)) == -3      # radius too large
+    need = b.value if lib.vr_container_workspace_size(100, 80, 40, C.byref(b)) == 0 else 0
+    ok = lambda **k: lib.vr_find_container(k.get("s", p), 100, 80, k.get("r0", 10), k.get("r1", 40),  # noqa: E731
+                                           k.get("sh", 4), k.get("m", 2), k.get("w", p), k.get("wb", need),
+                                           k.get("c", p), None)
+    assert ok(s=None) == -1 and ok(w=None) == -1 and ok(c=None) == -1
+    assert ok(r0=0) == -3 and ok(r0=41) == -3 and ok(sh=17) == -3 and ok(m=-1) == -3
+    assert ok(wb=need - 1) == -7
+    assert ok(w=C.c_void_p(128)) == -3                                           # unaligned workspace
+    assert lib.vr_remove_container(None, 4, 4, 4, p, None) == -1
+    assert lib.vr_remove_container(p, 4, 0, 4, p, None) == -2
+    assert lib.vr_histogram_in_disc(p, 4, 4, 4, 5, p, p, p, None) == -3
+    assert lib.vr_histogram_in_disc(p, 4, 4, 4, 3, None, p, p, None) == -1
+    ptrs = (C.c_void_p * 1)(16)
+    assert lib.vr_threshold_downsample_in_disc(p, 8, 8, 8, None, None, 1, ptrs, None, None) == -1
+    assert lib.vr_threshold_downsample_in_disc(p, 8193, 8, 8, None, p, 1, ptrs, None, None) == -2
