@@ -35,12 +35,16 @@ FLOPS_PER_SAMPLE = 62
 METRIC = "Gsamples/s ray casting + GB/s reduction vs HBM peak; fwd+bwd, batched vs plain"
 
 # HBM bytes of one launch of the dominant kernel (raycast_fwd on this step),
-# FETCH_SIZE + WRITE_SIZE from two rocprofv3 --pmc runs of --traffic-probe,
-# scaled by the same counters on a 1 GiB copy (factor 1.000); valid only for
-# the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"bytes": (1692699 + 147456) * 1024, "fetch_kib": 1692699, "write_kib": 147456,
-                   "scale": 1.000, "sources_sha256_16": "cb58d150cdb591e8"}
-RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "brick_dev.h", "common.h")
+# FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of
+# --traffic-probe, each scaled by what the same counter reads for a kernel of
+# known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
+# 524308 KiB for it (scale 2.000), WRITE_SIZE 1048576 KiB (scale 1.000).
+# Valid only for the kernel sources they were taken on (fingerprint below).
+RAYCAST_TRAFFIC = {"fetch_kib": 1561228, "write_kib": 150920, "fetch_scale": 1048576 / 524308,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "ea5955254bb39b24"}
+RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
+                                      + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
+RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "brick_dev.h", "common.h", "entropy_dev.h")
 
 
 def raycast_traffic():
@@ -137,8 +141,8 @@ def run_fwd_bwd(pipe, steps=200):
     """The 200-step Adam fit: 16 turntable views at 256^2 of a 256^3 f32 grid
     (spacing 2, step 1 = half its voxel, initialised from the 256^3 level)
     against renders of the 512^3 level.  Reports the time per iteration
-    (forward, adjoint, Adam; after two untimed ones) beside the forward alone,
-    and the loss at the first and last step."""
+    (forward, adjoint, projected Adam; after two untimed ones) beside the
+    forward alone, and the loss at the first and last steps."""
     import torch
 
     from paper_2311_15038_amd import autograd as VA
@@ -152,7 +156,7 @@ def run_fwd_bwd(pipe, steps=200):
     target = vr.vr_raycast(L1, tf, cams, 256, 256, 0.5)
     dens = (pipe.levels[1].to(torch.float32) / 65535.0).contiguous().requires_grad_(True)
     tfp = tf.clone().requires_grad_(True)
-    opt = torch.optim.Adam([dens, tfp], lr=1e-2)
+    opt = torch.optim.Adam([dens, tfp], lr=1e-3)
     losses = torch.zeros(steps, dtype=torch.float32, device=dev)
 
     def it(i):
@@ -161,6 +165,9 @@ def run_fwd_bwd(pipe, steps=200):
         loss = ((img - target) ** 2).mean()
         loss.backward()
         opt.step()
+        with torch.no_grad():                 # projected: densities in [0, 1], TF non-negative
+            dens.clamp_(0.0, 1.0)
+            tfp.clamp_(min=0.0)
         losses[i] = loss.detach()
 
     for i in range(2):
@@ -189,6 +196,7 @@ def run_fwd_bwd(pipe, steps=200):
             "samples_fwd": n_fwd, "fwd_Gsamples_per_s": n_fwd / (fwd_ms * 1e-3) / 1e9,
             "iter_Gsamples_per_s": n_fwd / (it_ms * 1e-3) / 1e9,
             "steps": steps, "loss_first": lo[0], "loss_last": lo[-1],
+            "loss_first10_mean": sum(lo[:10]) / 10, "loss_last10_mean": sum(lo[-10:]) / 10,
             "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
 
 
@@ -215,6 +223,76 @@ def run_thresholds(pipe, reps=20):
             out[name]["iterations"] = r[1]
         if rule == vr.RULE_OTSU:
             out[name]["thresholds_scanned"] = 65536 >> param
+    return out
+
+
+def run_container(steps=5):
+    """The 1024^3 scene standing in a cylindrical container, through the preview
+    step with container removal (Section III-B): the circle in the top slice,
+    histograms of the voxels inside it, selection, the pyramid with the disc
+    applied, bricks, 36 views and the best view.  Per-call device times, the
+    circle, and the valley threshold and top-filter effect with and without
+    removal on the same volume."""
+    import numpy as np
+    import torch
+
+    from paper_2311_15038_amd import pipeline as P
+    from paper_2311_15038_amd import synth, vr
+
+    dev = torch.device("cuda:0")
+    vol = synth.make_volume(synth.FULL_CONTAINED, dev)
+    pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(container=True), device=dev)
+    pipe.step(vol)
+    torch.cuda.synchronize()
+    calls = pipe.calls(vol)
+    ev = _events(2)
+    k_ev = {name: _events(2 * steps) for name, _ in calls}
+    ev[0].record()
+    for st in range(steps):
+        for name, fn in calls:
+            k_ev[name][2 * st].record()
+            fn()
+            k_ev[name][2 * st + 1].record()
+    ev[1].record()
+    torch.cuda.synchronize()
+    per = {k: sum(e[2 * st].elapsed_time(e[2 * st + 1]) for st in range(steps)) / steps
+           for k, e in k_ev.items()}
+    rec = pipe.circle.cpu().numpy().tolist()
+    nz, ny, nx = vol.shape
+    X = np.arange(nx)[None, :] - rec[1]
+    Y = np.arange(ny)[:, None] - rec[2]
+    inside = int((X * X + Y * Y <= rec[4] ** 2).sum()) if rec[0] else nx * ny
+    in_b = inside * nz * 2
+    lv_b = sum(l.numel() * 2 for l in pipe.levels)
+    T_disc = int(pipe.result[0].item())
+    removed_disc = 65536 - int(np.unpackbits(pipe.keep.cpu().numpy().view(np.uint8)).sum())
+    plain = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=dev)
+    plain.reduce(vol)
+    torch.cuda.synchronize()
+    T_plain = int(plain.result[0].item())
+    removed_plain = 65536 - int(np.unpackbits(plain.keep.cpu().numpy().view(np.uint8)).sum())
+    # bins of the outer shell (mean +- 3 sigma) that the keep mask holds in each case
+    lo, hi = int(synth.CLASS_MU[synth.OUTER] - 3 * 300), int(synth.CLASS_MU[synth.OUTER] + 3 * 300)
+    outer_bins_kept = {
+        name: int(np.unpackbits(p.keep.cpu().numpy().view(np.uint8), bitorder="little")[lo:hi].sum())
+        for name, p in (("with_removal", pipe), ("without_removal", plain))}
+    del plain
+    out = {
+        "workload": "1024^3 u16 scene in a cylindrical container (wall over every slice), "
+                    "preview step with container removal, 36 x 512^2 views",
+        "ms_per_step": sum(per.values()),
+        "kernel_ms": per,
+        "circle": dict(zip(("found", "cx", "cy", "r", "R", "centre_votes", "radius_votes", "edges"), rec)),
+        "voxels_in_disc": inside * nz,
+        "kernel_GB_per_s": {
+            "histograms": (in_b + inside * 3 * 2) / (per["histograms"] * 1e-3) / 1e9,
+            "pyramid+atlas": (in_b + lv_b + pipe.atlas.numel() * 2) / (per["pyramid+atlas"] * 1e-3) / 1e9},
+        "threshold": {"with_removal": T_disc, "without_removal": T_plain},
+        "bins_removed_by_mask": {"with_removal": removed_disc, "without_removal": removed_plain},
+        "outer_shell_bins_kept": {"range": [lo, hi], **outer_bins_kept},
+    }
+    del pipe, vol
+    torch.cuda.empty_cache()
     return out
 
 
@@ -383,8 +461,10 @@ def cpu_baseline(pipe, vol, budget_s=12.0):
 
 
 def traffic_probe():
-    """One step of the path, then a plain copy of known size (1 GiB read, 1 GiB
-    written by one elementwise kernel) that scales the HBM counters."""
+    """One step of the path, then one elementwise kernel of known traffic that
+    scales the HBM counters: bitwise NOT of 2^28 int32 (1 GiB read, 1 GiB
+    written; an operation nothing else in the run launches, so a kernel-name
+    filter on "bitwise_not" selects exactly that dispatch)."""
     import torch
 
     from paper_2311_15038_amd import pipeline as P
@@ -395,13 +475,13 @@ def traffic_probe():
     pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=dev)
     torch.cuda.synchronize()
     pipe.step(vol)
-    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    dst.copy_(src)
+    torch.bitwise_not(src, out=dst)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "traffic", "copy_bytes_read": src.numel() * 4,
-                      "copy_bytes_written": dst.numel() * 4}), flush=True)
+    print(json.dumps({"probe": "traffic", "calibration_bytes_read": src.numel() * 4,
+                      "calibration_bytes_written": dst.numel() * 4}), flush=True)
 
 
 def main():
@@ -412,7 +492,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="one step plus a 1 GiB elementwise copy, for HBM counter runs")
+                    help="one step plus a 1 GiB-in, 1 GiB-out elementwise kernel, for HBM counter runs")
+    ap.add_argument("--container-only", action="store_true",
+                    help="only the container-removal leg (for kernel profiles)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured window of the serving trace (after 5 s of warm-up)")
     args = ap.parse_args()
@@ -430,6 +512,9 @@ def main():
 
     if args.traffic_probe:
         traffic_probe()
+        return
+    if args.container_only:
+        print(json.dumps({"container": run_container(args.steps)}), flush=True)
         return
     res, pipe, vol = run_gpu(args.steps, args.warmup)
     ms = res["ms_per_step"]
@@ -481,6 +566,11 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(pipe, vol)
     if not args.no_extras:
+        try:
+            line["container"] = run_container()
+        except Exception as e:  # reported, not hidden
+            line["container"] = {"error": repr(e)}
+        log(f"container: {line['container']}")
         try:
             line["fwd_bwd"] = run_fwd_bwd(pipe)
         except Exception as e:  # reported, not hidden

@@ -6,7 +6,7 @@
 // Steps on the device, each its own launch, no host synchronisation:
 //   1. the largest squared Sobel gradient of the slice's interior;
 //   2. the edge list: pixels whose squared gradient is at least 2^-shift of
-//      it, appended with wave-aggregated atomics;
+//      it, gathered per workgroup in LDS and appended with one atomic each;
 //   3. votes: one thread per (edge, step) adds one vote to the cell of the
 //      digital line from the edge against its gradient, for the steps whose
 //      distance along the line lies in [r_min, r_max] (integer arithmetic);
@@ -31,7 +31,7 @@ constexpr int kMaxSide = 8192;             // pixels per slice side
 constexpr int kMaxRadius = 4096;
 constexpr int kIdxBits = 26;               // 8192^2 pixel indices
 constexpr uint64_t kIdxMask = (uint64_t(1) << kIdxBits) - 1;
-constexpr int kSeg = 64;                   // rows per column-window thread
+constexpr int kSeg = 16;                   // rows per column-window thread
 constexpr int kRadBits = 13;               // radius field of the radius key
 
 struct Ws {
@@ -95,49 +95,64 @@ __device__ __forceinline__ void sobel(const uint16_t* __restrict__ s, int64_t nx
     gy = (g + 2 * h + i) - (a + 2 * b + c);
 }
 
+// block-level maximum, one atomic per workgroup
 __global__ void __launch_bounds__(kT) grad_max(const uint16_t* __restrict__ s, int64_t nx, int64_t ny, Ws w)
 {
-    const int64_t iw = nx - 2, n = iw * (ny - 2);
+    __shared__ unsigned long long red[kT / 64];
+    const uint32_t iw = (uint32_t)(nx - 2), n = iw * (uint32_t)(ny - 2);
     unsigned long long m = 0;
-    for (int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x; q < n; q += (int64_t)gridDim.x * kT) {
+    for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
         int gx, gy;
         sobel(s, nx, 1 + q % iw, 1 + q / iw, gx, gy);
         const unsigned long long m2 = (unsigned long long)((int64_t)gx * gx + (int64_t)gy * gy);
         m = m2 > m ? m2 : m;
     }
     m = wave_max(m);
-    if (__lane_id() == 0 && m) atomicMax(w.scal, m);
+    if (__lane_id() == 0) red[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kT / 64; ++i) m = red[i] > m ? red[i] : m;
+        if (m) atomicMax(w.scal, m);
+    }
 }
 
+constexpr int kEdgeBuf = 2048;             // edges a workgroup gathers before one global append
+
+// Each workgroup walks a contiguous run of interior pixels, gathers its edges
+// in LDS and appends them to the list with one global atomic per flush.
 __global__ void __launch_bounds__(kT) edge_list(const uint16_t* __restrict__ s, int64_t nx, int64_t ny, int shift, Ws w)
 {
-    const int64_t iw = nx - 2, n = iw * (ny - 2);
+    __shared__ int4 buf[kEdgeBuf];
+    __shared__ uint32_t count;
+    __shared__ unsigned long long base;
+    const uint32_t iw = (uint32_t)(nx - 2), n = iw * (uint32_t)(ny - 2);
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t q0 = blockIdx.x * per, q1 = min(n, q0 + per);
     const unsigned long long G2 = w.scal[0];
-    const int lane = (int)__lane_id();
-    // the loop bound is uniform over the workgroup, so every ballot sees whole waves
-    for (int64_t base = (int64_t)blockIdx.x * kT; base < n; base += (int64_t)gridDim.x * kT) {
-        const int64_t q = base + threadIdx.x;
-        bool e = false;
-        int gx = 0, gy = 0;
-        int64_t x = 0, y = 0;
-        if (q < n) {
-            x = 1 + q % iw;
-            y = 1 + q / iw;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    auto flush = [&]() {
+        if (threadIdx.x == 0) base = count ? atomicAdd(w.scal + 2, (unsigned long long)count) : 0ull;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < count; i += kT) w.edges[base + i] = buf[i];
+        __syncthreads();
+        if (threadIdx.x == 0) count = 0;
+        __syncthreads();
+    };
+    // the loop bound is uniform over the workgroup, so the barriers are reached by all
+    for (uint32_t b = q0; b < q1; b += kT) {
+        const uint32_t q = b + threadIdx.x;
+        if (q < q1) {
+            const uint32_t x = 1 + q % iw, y = 1 + q / iw;
+            int gx, gy;
             sobel(s, nx, x, y, gx, gy);
             const unsigned long long m2 = (unsigned long long)((int64_t)gx * gx + (int64_t)gy * gy);
-            e = m2 > 0 && (m2 << shift) >= G2;
+            if (m2 > 0 && (m2 << shift) >= G2) buf[atomicAdd(&count, 1u)] = make_int4((int)x, (int)y, gx, gy);
         }
-        const uint64_t b = __ballot(e);
-        if (b == 0) continue;
-        const int leader = __builtin_ctzll(b);
-        unsigned long long first = 0;
-        if (lane == leader) first = atomicAdd(w.scal + 2, (unsigned long long)__popcll(b));
-        first = __shfl(first, leader);
-        if (e) {
-            const uint64_t below = lane ? (b & ((~uint64_t(0)) >> (64 - lane))) : 0;
-            w.edges[first + __popcll(below)] = make_int4((int)x, (int)y, gx, gy);
-        }
+        __syncthreads();
+        if (count > kEdgeBuf - kT) flush();
     }
+    flush();
 }
 
 __device__ __forceinline__ int64_t sgn(int v) { return (v > 0) - (v < 0); }
@@ -148,9 +163,10 @@ __global__ void __launch_bounds__(kT) vote(int64_t nx, int64_t ny, int r_min, in
     const uint64_t E = w.scal[2];
     const uint64_t K = (uint64_t)(r_max - k0 + 1);
     const uint64_t total = E * K;
+    const bool narrow = total < (uint64_t(1) << 32);       // 32-bit division suffices
     const int64_t lo2 = (int64_t)r_min * r_min, hi2 = (int64_t)r_max * r_max;
     for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kT) {
-        const uint64_t e = i / K;
+        const uint64_t e = narrow ? (uint64_t)((uint32_t)i / (uint32_t)K) : i / K;
         const int64_t k = k0 + (int64_t)(i - e * K);
         const int4 p = w.edges[e];
         const int64_t ax = p.z < 0 ? -(int64_t)p.z : p.z, ay = p.w < 0 ? -(int64_t)p.w : p.w;
@@ -158,7 +174,8 @@ __global__ void __launch_bounds__(kT) vote(int64_t nx, int64_t ny, int r_min, in
         const int64_t gmaj = xmaj ? ax : ay, gmin = xmaj ? ay : ax;
         const int64_t d2 = k * k * (ax * ax + ay * ay), g2 = gmaj * gmaj;
         if (d2 < lo2 * g2 || d2 > hi2 * g2) continue;
-        const int64_t j = (2 * k * gmin + gmaj) / (2 * gmaj);
+        // below 2^32: 2 k gmin + gmaj <= 2 * 4096 * 262140 + 262140
+        const int64_t j = (uint32_t)(2 * k * gmin + gmaj) / (uint32_t)(2 * gmaj);
         const int64_t cx = p.x - (xmaj ? k : j) * sgn(p.z);
         const int64_t cy = p.y - (xmaj ? j : k) * sgn(p.w);
         if (cx < 0 || cx >= nx || cy < 0 || cy >= ny) continue;
@@ -217,10 +234,14 @@ __device__ __forceinline__ int64_t round_sqrt(int64_t D)
     return d;
 }
 
+// each workgroup counts its edges' radii in LDS, then adds its non-zero counts
 __global__ void __launch_bounds__(kT) radius_hist(int64_t nx, int r_min, int r_max, Ws w)
 {
+    __shared__ uint32_t h[kMaxRadius + 1];
     const unsigned long long key = w.scal[1];
     if ((key >> kIdxBits) == 0) return;
+    for (int r = threadIdx.x; r <= r_max; r += kT) h[r] = 0u;
+    __syncthreads();
     const int64_t idx = (int64_t)(kIdxMask - (key & kIdxMask));
     const int64_t cx = idx % nx, cy = idx / nx;
     const uint64_t E = w.scal[2];
@@ -229,8 +250,11 @@ __global__ void __launch_bounds__(kT) radius_hist(int64_t nx, int r_min, int r_m
         const int64_t dx = p.x - cx, dy = p.y - cy;
         if ((int64_t)p.z * dx + (int64_t)p.w * dy <= 0) continue;
         const int64_t d = round_sqrt(dx * dx + dy * dy);
-        if (d >= r_min && d <= r_max) atomicAdd(w.rhist + d, 1u);
+        if (d >= r_min && d <= r_max) atomicAdd(h + d, 1u);
     }
+    __syncthreads();
+    for (int r = r_min + threadIdx.x; r <= r_max; r += kT)
+        if (h[r]) atomicAdd(w.rhist + r, h[r]);
 }
 
 __global__ void __launch_bounds__(kT) finish(int64_t nx, int r_min, int r_max, int margin, Ws w, int32_t* rec)
@@ -358,9 +382,10 @@ extern "C" int vr_find_container(const uint16_t* d_slice, int64_t nx, int64_t ny
 
     clear_ws<<<grid_for(n, cap), kT, 0, s>>>(w, n, r_max + 1);
     if ((rc = vr::check_launch("vr_find_container: clear"))) return rc;
-    grad_max<<<grid_for(interior, cap), kT, 0, s>>>(d_slice, nx, ny, w);
+    const int64_t cap2 = (int64_t)vr::num_cus() * 2;
+    grad_max<<<grid_for(interior, cap2), kT, 0, s>>>(d_slice, nx, ny, w);
     if ((rc = vr::check_launch("vr_find_container: gradient"))) return rc;
-    edge_list<<<grid_for(interior, cap), kT, 0, s>>>(d_slice, nx, ny, edge_shift, w);
+    edge_list<<<grid_for(interior, cap2), kT, 0, s>>>(d_slice, nx, ny, edge_shift, w);
     if ((rc = vr::check_launch("vr_find_container: edges"))) return rc;
     vote<<<(unsigned)cap, kT, 0, s>>>(nx, ny, r_min, r_max, k0, w);
     if ((rc = vr::check_launch("vr_find_container: votes"))) return rc;
@@ -368,7 +393,9 @@ extern "C" int vr_find_container(const uint16_t* d_slice, int64_t nx, int64_t ny
     if ((rc = vr::check_launch("vr_find_container: row boxes"))) return rc;
     box_cols<<<grid_for(nx * ((ny + kSeg - 1) / kSeg), cap), kT, 0, s>>>(nx, ny, wb, w);
     if ((rc = vr::check_launch("vr_find_container: column boxes"))) return rc;
-    radius_hist<<<(unsigned)(cap / 2), kT, 0, s>>>(nx, r_min, r_max, w);
+    // the edge count is known on the device only: enough workgroups for a slice
+    // whose interior were all edges, capped at a few per compute unit
+    radius_hist<<<grid_for(interior, (int64_t)vr::num_cus() * 2), kT, 0, s>>>(nx, r_min, r_max, w);
     if ((rc = vr::check_launch("vr_find_container: radii"))) return rc;
     finish<<<1, kT, 0, s>>>(nx, r_min, r_max, margin, w, d_circle);
     return vr::check_launch("vr_find_container: record");

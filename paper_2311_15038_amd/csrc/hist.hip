@@ -111,6 +111,130 @@ __global__ void __launch_bounds__(kThreads) hist_disc_kernel(DiscRange R)
     flush_lds(lds, R.hist);
 }
 
+// n / d for n < 2^32 by a 64-bit reciprocal: m = floor((2^64 - 1) / d) + 1
+// (exact for every such n; d = 1 handled apart).
+struct FastDiv {
+    uint64_t m;
+    uint32_t d;
+};
+
+FastDiv make_div(uint32_t d) { return FastDiv{d > 1 ? (~uint64_t(0)) / d + 1 : 0, d}; }
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f)
+{
+    return f.d == 1 ? n : (uint32_t)__umul64hi((uint64_t)n, f.m);
+}
+
+constexpr int kMaxSpanRows = 4096;       // rows of the streaming variant's span table
+
+// The streaming variant for slabs whose rows are whole 16-byte chunks: the
+// chunk sequence of the slab is walked as in hist_kernel, each chunk's row
+// found by reciprocal division and its kept run read from a table in LDS;
+// chunks outside the disc are not loaded, chunks across its edge are counted
+// voxel by voxel.
+struct DiscStream {
+    const uint4* body;     // 16-byte aligned first voxel of the slab
+    uint32_t n_chunks;     // chunks of the slab
+    uint32_t ny;
+    FastDiv per_row;       // chunks per row
+    FastDiv rows;          // ny
+    const int32_t* rec;
+    uint64_t* hist;
+};
+
+// bits e of the chunk's voxels inside their row's kept run
+__device__ __forceinline__ uint32_t chunk_keep(uint32_t i, const DiscStream& S, const uint32_t* spans)
+{
+    const uint32_t row = fdiv(i, S.per_row);
+    const uint32_t y = row - fdiv(row, S.rows) * S.ny;
+    const int x = (int)(8u * (i - row * S.per_row.d));
+    const uint32_t sp = spans[y];
+    const int lo = max((int)(sp & 0xFFFFu) - x, 0), hi = min((int)(sp >> 16) - x, 7);
+    return lo > hi ? 0u : (0xFFu >> (7 - hi)) & (0xFFu << lo);
+}
+
+// The chunk's voxels whose bit is set in k, in one instruction stream for
+// whole, partial and (per lane) absent chunks: eight predicated additions,
+// or one addition when the wave's kept chunks are all eight copies of one value.
+__device__ __forceinline__ void count_kept(uint32_t* lds, uint64_t* gh, uint4 c, uint32_t k)
+{
+    const uint32_t v0 = c.x & 0xFFFFu;
+    const bool same8 = k == 0xFFu && (c.x >> 16) == v0 && c.y == c.x && c.z == c.x && c.w == c.x;
+    const uint64_t act = __ballot(k != 0u);
+    if (act == 0) return;
+    const uint32_t w0 = __shfl(v0, __builtin_ctzll(act));
+    if (__ballot(k != 0u && same8 && v0 == w0) == act) {
+        if (__lane_id() == (uint32_t)__builtin_ctzll(act)) count_n(lds, gh, w0, 8u * (uint32_t)__popcll(act));
+        return;
+    }
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if ((k >> e) & 1u) count_1(lds, gh, (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+}
+
+__global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
+{
+    __shared__ uint32_t lds[kWords];
+    __shared__ uint32_t spans[kMaxSpanRows];
+    zero_lds(lds);
+    {
+        const vr::disc::Disc d = vr::disc::load_disc(S.rec);
+        const int64_t nx = (int64_t)S.per_row.d * 8;
+        for (uint32_t y = threadIdx.x; y < S.ny; y += kThreads) {
+            int64_t x0, x1;
+            vr::disc::row_span(d, y, nx, x0, x1);
+            spans[y] = x0 > x1 ? 0x0000FFFFu : (uint32_t)x0 | ((uint32_t)x1 << 16);
+        }
+    }
+    __syncthreads();
+    const uint32_t nthr = gridDim.x * kThreads;
+    uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t stride = kUnroll * nthr;
+    if ((uint64_t)i + (kUnroll - 1) * (uint64_t)nthr < S.n_chunks) {
+        uint4 cur[kUnroll];
+        uint32_t kc[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            kc[u] = chunk_keep(i + u * nthr, S, spans);
+            cur[u] = kc[u] ? load_stream(S.body + i + u * nthr) : make_uint4(0u, 0u, 0u, 0u);
+        }
+        for (;;) {
+            const uint64_t nx_ = (uint64_t)i + stride;
+            const bool more = nx_ + (kUnroll - 1) * (uint64_t)nthr < S.n_chunks;
+            uint4 nxt[kUnroll];
+            uint32_t kn[kUnroll];
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    kn[u] = chunk_keep((uint32_t)nx_ + u * nthr, S, spans);
+                    nxt[u] = kn[u] ? load_stream(S.body + nx_ + u * nthr) : make_uint4(0u, 0u, 0u, 0u);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) count_kept(lds, S.hist, cur[u], kc[u]);
+            if (!more) {
+                i = (uint32_t)nx_;
+                break;
+            }
+            i = (uint32_t)nx_;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                cur[u] = nxt[u];
+                kc[u] = kn[u];
+            }
+        }
+    }
+    for (; i < S.n_chunks; i += nthr) {
+        const uint32_t k = chunk_keep(i, S, spans);
+        uint4 c = make_uint4(0u, 0u, 0u, 0u);
+        if (k) c = load_stream(S.body + i);
+        count_kept(lds, S.hist, c, k);
+    }
+    __syncthreads();
+    flush_lds(lds, S.hist);
+}
+
 int check_dims(int64_t nx, int64_t ny, int64_t nz, const char* who)
 {
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, VR_ERR_DIMS, "%s: dims %lld x %lld x %lld", who,
@@ -186,13 +310,25 @@ extern "C" int vr_histogram_in_disc(const uint16_t* d_vol, int64_t nx, int64_t n
     rc = vr::check_launch("vr_histogram_in_disc: fill");
     if (rc) return rc;
     const int cus = vr::num_cus();
+    // whole 16-byte chunks per row, a span table that fits, 32-bit chunk indices
+    const bool stream_ok = nx % 8 == 0 && (reinterpret_cast<uintptr_t>(d_vol) & 15u) == 0 &&
+                           ny <= kMaxSpanRows && nx <= 65536 && nx * ny * nz / 8 < (int64_t(1) << 31);
+    auto launch = [&](int64_t slices, uint64_t* h) {
+        const int blocks = blocks_for(nx * ny * slices, cus);
+        if (stream_ok) {
+            DiscStream S{reinterpret_cast<const uint4*>(d_vol), (uint32_t)(nx * ny * slices / 8), (uint32_t)ny,
+                         make_div((uint32_t)(nx / 8)), make_div((uint32_t)ny), d_circle, h};
+            hist_disc_stream<<<(unsigned)blocks, kThreads, 0, s>>>(S);
+        } else {
+            DiscRange R{d_vol, nx, ny, ny * slices, d_circle, h};
+            hist_disc_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(R);
+        }
+    };
     if (d_hist_top != nullptr) {
-        DiscRange b{d_vol, nx, ny, ny * top_slices, d_circle, d_hist_top};
-        hist_disc_kernel<<<(unsigned)blocks_for(nx * ny * top_slices, cus), kThreads, 0, s>>>(b);
+        launch(top_slices, d_hist_top);
         rc = vr::check_launch("vr_histogram_in_disc: top slices");
         if (rc) return rc;
     }
-    DiscRange a{d_vol, nx, ny, ny * nz, d_circle, d_hist};
-    hist_disc_kernel<<<(unsigned)blocks_for(nx * ny * nz, cus), kThreads, 0, s>>>(a);
+    launch(nz, d_hist);
     return vr::check_launch("vr_histogram_in_disc");
 }

@@ -88,7 +88,7 @@ RECORDS = {
     "outside_slice": [1, 500, 500, 12, 10, 1, 1, 1],
     "not_found": [0, 0, 0, 0, 0, 0, 0, 0],
 }
-SHAPES = [(45, 97, 131), (16, 128, 256), (5, 3, 7)]
+SHAPES = [(45, 97, 131), (16, 128, 256), (5, 3, 7), (7, 61, 24), (3, 1, 8)]
 
 
 def _rand_vol(shape, seed):
