@@ -182,20 +182,22 @@ def run_fwd_bwd(pipe, steps=200):
     it_ms = e[0].elapsed_time(e[1]) / (steps - 2)
     lo = losses.cpu().tolist()
     with torch.no_grad():
+        # the forward alone, as the differentiable render's forward makes it
         cnt = torch.zeros(2, dtype=torch.int64, device=dev)
         fe = _events(2)
         fe[0].record()
         for _ in range(5):
-            vr.vr_raycast(dens.detach(), tfp.detach(), cams, 256, 256, 1.0, (2.0, 2.0, 2.0))
+            VA.render_forward(dens.detach(), tfp.detach(), cams, 256, 256, 1.0, (2.0, 2.0, 2.0))
         fe[1].record()
-        vr.vr_raycast(dens.detach(), tfp.detach(), cams, 256, 256, 1.0, (2.0, 2.0, 2.0), samples=cnt)
+        VA.render_forward(dens.detach(), tfp.detach(), cams, 256, 256, 1.0, (2.0, 2.0, 2.0), samples=cnt)
         torch.cuda.synchronize()
         fwd_ms = fe[0].elapsed_time(fe[1]) / 5
     n_fwd = int(cnt[0].item())
     return {"ms_per_iter": it_ms, "fwd_ms": fwd_ms, "iter_over_fwd": it_ms / fwd_ms,
-            "samples_fwd": n_fwd, "fwd_Gsamples_per_s": n_fwd / (fwd_ms * 1e-3) / 1e9,
+            "samples_fwd": n_fwd, "evaluated_fwd": int(cnt[1].item()), "fwd_Gsamples_per_s": n_fwd / (fwd_ms * 1e-3) / 1e9,
             "iter_Gsamples_per_s": n_fwd / (it_ms * 1e-3) / 1e9,
             "steps": steps, "loss_first": lo[0], "loss_last": lo[-1],
+            "tf_sigma_knots_0_3_after": [float(x) for x in tfp.detach()[:4, 3].cpu().tolist()],
             "loss_first10_mean": sum(lo[:10]) / 10, "loss_last10_mean": sum(lo[-10:]) / 10,
             "views": 16, "image": [256, 256], "grid": [256, 256, 256]}
 
@@ -495,6 +497,8 @@ def main():
                     help="one step plus a 1 GiB-in, 1 GiB-out elementwise kernel, for HBM counter runs")
     ap.add_argument("--container-only", action="store_true",
                     help="only the container-removal leg (for kernel profiles)")
+    ap.add_argument("--fit-only", action="store_true",
+                    help="only the 200-step fit leg (for kernel profiles)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured window of the serving trace (after 5 s of warm-up)")
     args = ap.parse_args()
@@ -515,6 +519,15 @@ def main():
         return
     if args.container_only:
         print(json.dumps({"container": run_container(args.steps)}), flush=True)
+        return
+    if args.fit_only:
+        from paper_2311_15038_amd import pipeline as P
+        from paper_2311_15038_amd import synth
+        vol = synth.make_volume(synth.FULL, torch.device("cuda:0"))
+        pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=torch.device("cuda:0"))
+        pipe.reduce(vol)
+        del vol
+        print(json.dumps({"fwd_bwd": run_fwd_bwd(pipe)}), flush=True)
         return
     res, pipe, vol = run_gpu(args.steps, args.warmup)
     ms = res["ms_per_step"]

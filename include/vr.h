@@ -357,8 +357,14 @@ int vr_entropy_from_counts(const uint32_t* d_hist, int n_views, int64_t pixels, 
  * through the trilinear weights to the eight taps (f32 atomics; the
  * summation order is not deterministic).
  * The density must be VR_F32 in VR_LAYOUT_LINEAR (VR_ERR_DTYPE,
- * VR_ERR_UNSUPPORTED otherwise); vol->occupancy is ignored (samples of empty
- * bricks leave the colour unchanged but do carry gradient).
+ * VR_ERR_UNSUPPORTED otherwise).  vol->occupancy may be NULL, or the
+ * occupancy grid that vr_brick_volume wrote for the same grid: then, when the
+ * TF's first segment has zero extinction (tf[0].sigma = tf[1].sigma = 0,
+ * finite colour), runs of samples whose base tap lies in an empty brick are
+ * not marched.  Their colour, transmittance and density gradient are
+ * unchanged, and the one gradient they carry, len * (grad . (T tf[0].rgb -
+ * (I - P)) + grad_a (1 - I_a)) to tf[0].sigma, is added once per run (the same
+ * value up to floating-point summation order).
  * Errors: as vr_raycast.
  */
 int vr_raycast_backward(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams,

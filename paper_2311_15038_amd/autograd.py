@@ -3,6 +3,14 @@
 The forward saves only its RGBA output; the backward re-marches every ray
 (per-ray recomputation, nothing stored per sample) and scatters gradients to
 the density grid and the transfer-function table.
+
+The forward renders from a 4^3-brick copy of the grid with empty-space
+skipping: a skipped sample has zero extinction, so the frames (and the
+sample where each ray terminates early) are bit-identical to marching the
+linear grid, which is what the adjoint replays.  The adjoint passes over the
+same empty bricks when the first TF segment has zero extinction, adding in
+closed form the one gradient their samples carry (to that knot's
+extinction); otherwise it marches every sample.
 """
 from __future__ import annotations
 
@@ -12,16 +20,29 @@ import torch
 from . import vr
 
 
+def render_forward(density, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
+                   bg=(0.0, 0.0, 0.0, 0.0), skip_empty=True, samples=None, with_occupancy=False):
+    """The frames of an f32 grid as the differentiable render's forward makes them
+    (with with_occupancy, also the brick occupancy grid, or None)."""
+    src = vr.vr_brick_volume(density) if skip_empty else density
+    out = vr.vr_raycast(src, tf, cams, width, height, step, spacing, ert_eps, bg, samples=samples)
+    if with_occupancy:
+        return out, (src.occupancy if skip_empty else None)
+    return out
+
+
 class VolumeRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, density, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0),
-                ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0)):
+                ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0), skip_empty=True):
         if density.dtype != torch.float32:
             raise TypeError("VolumeRender differentiates an f32 density grid")
         density = density.contiguous()
         tf = tf.contiguous()
-        out = vr.vr_raycast(density, tf, cams, width, height, step, spacing, ert_eps, bg)
+        out, occ = render_forward(density, tf, cams, width, height, step, spacing, ert_eps, bg, skip_empty,
+                                  with_occupancy=True)
         ctx.save_for_backward(density, tf, out)
+        ctx.occ = occ
         ctx.args = (np.asarray(cams, dtype=np.float64).copy(), width, height, step, spacing,
                     ert_eps, bg)
         return out
@@ -33,10 +54,11 @@ class VolumeRender(torch.autograd.Function):
         g_density = torch.zeros_like(density)
         g_tf = torch.zeros_like(tf)
         vr.vr_raycast_backward(density, tf, cams, width, height, step, out, grad_out.contiguous(),
-                               g_density, g_tf, spacing, ert_eps, bg)
-        return g_density, g_tf, None, None, None, None, None, None, None
+                               g_density, g_tf, spacing, ert_eps, bg, occupancy=ctx.occ)
+        ctx.occ = None
+        return g_density, g_tf, None, None, None, None, None, None, None, None
 
 
 def render(density, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
-           bg=(0.0, 0.0, 0.0, 0.0)):
-    return VolumeRender.apply(density, tf, cams, width, height, step, spacing, ert_eps, bg)
+           bg=(0.0, 0.0, 0.0, 0.0), skip_empty=True):
+    return VolumeRender.apply(density, tf, cams, width, height, step, spacing, ert_eps, bg, skip_empty)

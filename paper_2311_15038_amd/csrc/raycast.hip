@@ -106,6 +106,15 @@ __device__ __forceinline__ void flush_tf(float* g, int k, float4 a0, float4 a1)
     atomicAdd(g + 4 * k + 7, a1.w);
 }
 
+// the pending density gradient of one cell's eight taps (none when off is unset)
+__device__ __forceinline__ void flush_cell(float* gvol, const uint32_t (&off)[8], const float (&gc)[8])
+{
+    if (off[0] == 0xFFFFFFFFu) return;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        if (gc[t] != 0.0f) atomicAdd(gvol + off[t], gc[t]);
+}
+
 template <int LAYOUT>
 __global__ void __launch_bounds__(kThreads)
 raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
@@ -117,6 +126,10 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
     tf_s[threadIdx.x] = tf[threadIdx.x];
     for (int q = threadIdx.x; q < 1024; q += kThreads) gtf_s[q] = 0.0f;
     __syncthreads();
+    // empty bricks may be passed over when the first TF segment has zero extinction
+    // (a sample at density 0 then has neither extinction nor a density gradient)
+    const bool skipping = S.occ != nullptr && tf_s[0].w == 0.0f && tf_s[1].w == 0.0f && isfinite(tf_s[0].x) &&
+                          isfinite(tf_s[0].y) && isfinite(tf_s[0].z);
     int view, i, j;
     pixel_of(S, (int)gridDim.x, view, i, j);
     const float* vol = static_cast<const float*>(S.data);
@@ -133,11 +146,65 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
             float Tr = 1.0f, Pr = 0.0f, Pg = 0.0f, Pb = 0.0f;
             int kc = -1;
             float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-            for (int k = 0; k < n; ++k) {
+            float u0[3], gr[3], ig[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u0[a] = fmaf(p[a], S.inv_sp[a], -0.5f);
+                gr[a] = d[a] * S.inv_sp[a];
+                ig[a] = gr[a] != 0.0f ? 1.0f / gr[a] : 0.0f;
+            }
+            uint32_t cur_b = 0xFFFFFFFFu;
+            bool cur_full = true;
+            uint32_t cell_off[8];        // taps of the cell whose density gradient is pending
+            float cell_g[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                cell_off[t] = 0xFFFFFFFFu;
+                cell_g[t] = 0.0f;
+            }
+            for (int k = 0; k < n;) {
                 const float len = (k < n - 1) ? S.step : last;
                 const float off = fmaf(0.5f, len, (float)k * S.step);
+                const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
+                if (skipping) {
+                    const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
+                    if (b != cur_b) {
+                        cur_b = b;
+                        cur_full = S.occ[b] != 0;
+                    }
+                    if (!cur_full) {
+                        // a run of samples whose eight taps are all 0: density 0, zero
+                        // extinction and colour weight, so the colour, the transmittance and
+                        // the density gradient are unchanged; each sample's only gradient is
+                        // len * q to the first knot's extinction, added for the whole run
+                        const uint32_t m[3] = {c.x0 >> 4, c.y0 >> 4, c.z0 >> 4};
+                        const uint32_t mi = (m[2] * (uint32_t)S.nmy + m[1]) * (uint32_t)S.nmx + m[0];
+                        int next;
+                        if (S.occ[S.macro_off + mi] == 0) {
+                            const int nm[3] = {S.nmx, S.nmy, S.nmz};
+                            next = skip_to(S, u0, gr, ig, m, nm, 4, k, n);
+                        } else {
+                            const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
+                            const int nb[3] = {S.nbx, S.nby, S.nbz};
+                            next = skip_to(S, u0, gr, ig, bb, nb, 2, k, n);
+                        }
+                        const float lsum = next < n ? (float)(next - k) * S.step
+                                                    : fmaf((float)(n - 1 - k), S.step, last);
+                        const float q = g.x * (Tr * tf_s[0].x - (I.x - Pr)) + g.y * (Tr * tf_s[0].y - (I.y - Pg)) +
+                                        g.z * (Tr * tf_s[0].z - (I.z - Pb)) + ga;
+                        if (kc != 0) {
+                            if (kc >= 0) flush_tf(gtf_s, kc, a0, a1);
+                            kc = 0;
+                            a0 = make_float4(0.f, 0.f, 0.f, 0.f);
+                            a1 = a0;
+                        }
+                        a0.w = fmaf(lsum, q, a0.w);
+                        k = next;
+                        continue;
+                    }
+                }
                 Sample sm;
-                sample<float, LAYOUT>(S, vol, cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2])), sm);
+                sample<float, LAYOUT>(S, vol, c, sm);
                 const TfHit h = tf_lookup(tf_s, sm.s);
                 const float e = __expf(-(h.q.w * len));
                 const float ta = Tr * (1.0f - e);
@@ -165,18 +232,30 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                     const float ds = 255.0f * ((kb.x - ka.x) * G.x + (kb.y - ka.y) * G.y +
                                                (kb.z - ka.z) * G.z + (kb.w - ka.w) * G.w);
                     if (ds != 0.0f) {
+                        // consecutive samples of one cell add to the same eight taps: their
+                        // gradients are summed in registers and scattered once per cell
+                        if (sm.off[0] != cell_off[0] || sm.off[7] != cell_off[7]) {
+                            flush_cell(gvol, cell_off, cell_g);
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) {
+                                cell_off[t] = sm.off[t];
+                                cell_g[t] = 0.0f;
+                            }
+                        }
                         const float ax = 1.0f - sm.wx, ay = 1.0f - sm.wy, az = 1.0f - sm.wz;
                         const float w[8] = {ax * ay * az, sm.wx * ay * az, ax * sm.wy * az, sm.wx * sm.wy * az,
                                             ax * ay * sm.wz, sm.wx * ay * sm.wz, ax * sm.wy * sm.wz,
                                             sm.wx * sm.wy * sm.wz};
 #pragma unroll
-                        for (int t = 0; t < 8; ++t) atomicAdd(gvol + sm.off[t], w[t] * ds);
+                        for (int t = 0; t < 8; ++t) cell_g[t] = fmaf(w[t], ds, cell_g[t]);
                     }
                 }
                 Tr = te;
+                ++k;
                 if (Tr < S.eps) break;
             }
             if (kc >= 0) flush_tf(gtf_s, kc, a0, a1);
+            flush_cell(gvol, cell_off, cell_g);
         }
     }
     __syncthreads();
@@ -244,7 +323,9 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
     VR_REQUIRE(vol->dtype == VR_F32, VR_ERR_DTYPE, "vr_raycast_backward: density must be VR_F32");
     VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR, VR_ERR_UNSUPPORTED,
                "vr_raycast_backward: the density gradient is produced for the linear layout only");
-    S.occ = nullptr;   // passing over empty bricks is exact for colours, not for gradients
+    // the occupancy of vr_brick_volume on the same grid, if given, lets the adjoint
+    // pass over empty bricks (build_scene keeps it for the brick layouts only)
+    S.occ = vol->occupancy;
     VR_REQUIRE(d_rgba_fwd && d_grad_rgba && d_grad_density && d_grad_tf, VR_ERR_NULL,
                "vr_raycast_backward: NULL buffer");
     hipStream_t s = vr::as_stream(stream);

@@ -443,9 +443,13 @@ def vr_entropy_from_counts(hist, pixels, entropy=None, best=None, stream=None):
 
 def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba, grad_density,
                         grad_tf, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
-                        bg=(0.0, 0.0, 0.0, 0.0), stream=None):
-    """Adds dLoss/dDensity and dLoss/dTF into grad_density / grad_tf (zero them first)."""
+                        bg=(0.0, 0.0, 0.0, 0.0), stream=None, occupancy=None):
+    """Adds dLoss/dDensity and dLoss/dTF into grad_density / grad_tf (zero them first).
+    occupancy: the occupancy grid vr_brick_volume wrote for the same grid, or None
+    (with it, runs of samples in empty bricks are not marched)."""
     vol = make_volume(data, spacing)
+    if occupancy is not None:
+        vol.occupancy = _dev(occupancy, "occupancy", torch.uint8).value
     ca, nv = make_cameras(cams)
     opts = make_opts(width, height, step, ert_eps, bg)
     n = nv * height * width * 4

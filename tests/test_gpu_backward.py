@@ -163,3 +163,76 @@ def test_adam_fit_200_steps(small_volume):
     first, last = np.mean(losses[:10]), np.mean(losses[-10:])
     assert losses[-1] < losses[0]
     assert last < 0.5 * first, (first, last)
+
+
+def _sparse_density(n, seed):
+    """Blobs of density in zero space: most bricks are empty."""
+    rng = np.random.default_rng(seed)
+    idx = np.indices((n, n, n)).astype(np.float64)
+    a = np.zeros((n, n, n))
+    for _ in range(5):
+        c = rng.uniform(0.2, 0.8, 3) * n
+        r = rng.uniform(2, 4)
+        d2 = ((idx - c[:, None, None, None]) ** 2).sum(axis=0)
+        a += 0.6 * np.exp(-d2 / (2 * r * r)) * (d2 < 9 * r * r)
+    return np.clip(a, 0, 1)
+
+
+@pytest.mark.parametrize("ert", [0.0, 2.0 ** -14])
+def test_skipping_forward_is_bit_identical(ert):
+    """The differentiable render's forward marches f32 bricks with empty-space
+    skipping; its frames equal the linear march bit for bit.  The adjoint
+    passes over the same empty bricks and adds their samples' one gradient
+    (to the first knot's extinction) per run, so the gradients equal the
+    full march's up to summation order: density gradients within 1e-5 of the
+    largest (the same terms, atomics in another order), TF gradients within
+    1e-4 (a run's m equal terms summed once instead of one by one, whose FP32
+    rounding grows with m)."""
+    banner(f"backward: skipping forward, ert {ert}")
+    n, W, H = 40, 32, 28
+    dens = _sparse_density(n, 6)
+    tf = synth.default_tf(sigma_scale=3.0)
+    assert tf[0, 3] == 0.0
+    cams = np.concatenate([synth.turntable_cameras(n, n, n, n_views=5), synth.front_ortho_camera(n, n, n)])
+    sp = (2.0, 2.0, 2.0)
+    d = torch.tensor(dens, dtype=torch.float32, device=dev())
+    t = torch.tensor(tf, dtype=torch.float32, device=dev())
+    c1 = torch.zeros(2, dtype=torch.int64, device=dev())
+    c2 = torch.zeros(2, dtype=torch.int64, device=dev())
+    a = VA.render_forward(d, t, cams, W, H, 1.0, sp, ert, skip_empty=True, samples=c1)
+    b = VA.render_forward(d, t, cams, W, H, 1.0, sp, ert, skip_empty=False, samples=c2)
+    assert torch.equal(a, b)
+    assert c1[0].item() == c2[0].item() and c1[1].item() < c2[1].item()
+    target = torch.rand((len(cams), H, W, 4), generator=torch.Generator().manual_seed(2)).to(dev())
+    grads = []
+    for skip in (True, False):
+        dd = d.clone().requires_grad_(True)
+        tt = t.clone().requires_grad_(True)
+        img = VA.render(dd, tt, cams, W, H, 1.0, sp, ert, skip_empty=skip)
+        ((img - target) ** 2).mean().backward()
+        grads.append((dd.grad.cpu().numpy(), tt.grad.cpu().numpy()))
+    for (g_skip, g_full), tol in zip(zip(*grads), (1e-5, 1e-4)):
+        s = np.abs(g_full).max()
+        assert s > 0 and np.abs(g_skip - g_full).max() <= tol * s, (tol, np.abs(g_skip - g_full).max() / s)
+
+
+def test_skipping_adjoint_matches_fp64_autograd():
+    """The adjoint with empty bricks passed over, against the FP64 autograd
+    gradient on a grid that is mostly empty space."""
+    banner("backward: skipping adjoint vs fp64 autograd")
+    n, W, H, step = 24, 20, 18, 0.5
+    dens = _sparse_density(n, 8)
+    tf = synth.default_tf(sigma_scale=3.0).astype(np.float64)
+    cams = np.concatenate([synth.turntable_cameras(n, n, n, n_views=3), synth.front_ortho_camera(n, n, n)])
+    target = np.random.default_rng(4).uniform(0, 1, size=(4, H, W, 4))
+    img_ref, gd_ref, gt_ref = _ref_grads(dens, tf, cams, W, H, step, target, (0.0, 0.0, 0.0, 0.0))
+    d = torch.tensor(dens, dtype=torch.float32, device=dev(), requires_grad=True)
+    t = torch.tensor(tf, dtype=torch.float32, device=dev(), requires_grad=True)
+    img = VA.render(d, t, cams, W, H, step, ert_eps=0.0)
+    ((img - torch.tensor(target, dtype=torch.float32, device=dev())) ** 2).mean().backward()
+    assert np.abs(img.detach().cpu().numpy() - img_ref).max() <= 2e-4
+    gd, gt = d.grad.cpu().numpy(), t.grad.cpu().numpy()
+    sd, st = np.abs(gd_ref).max(), np.abs(gt_ref).max()
+    assert sd > 0 and st > 0 and gt_ref[0, 3] != 0.0
+    assert np.abs(gd - gd_ref).max() <= 2e-3 * sd, np.abs(gd - gd_ref).max() / sd
+    assert np.abs(gt - gt_ref).max() <= 2e-3 * st, np.abs(gt - gt_ref).max() / st
