@@ -10,7 +10,11 @@
 // voxels) adds them with one LDS atomic (ballot test per 8-voxel chunk).  The
 // streaming loop keeps the next chunks' loads in flight while it counts the
 // current ones.  At the end each workgroup adds its non-zero counters to the
-// global bins; whole waves of empty words are skipped by ballot.
+// global bins; whole waves of empty words are skipped by ballot.  While every
+// bin's total stays below 2^32 (fewer voxels than that), the global bins are
+// kept in pairs, two 32-bit counters per 64-bit word, so one atomic adds a
+// whole LDS word; a last one-workgroup pass spreads the pairs into 64-bit bins
+// (the flush's atomics were a sixth of the histogram's time).
 #include "disc_dev.h"
 #include "hist_dev.h"
 
@@ -36,15 +40,54 @@ struct Range {
     int blocks;          // workgroups given to this range
 };
 
+template <bool PAIRED>
 __global__ void __launch_bounds__(kThreads) hist_kernel(Range R)
 {
     __shared__ uint32_t lds[kWords];
     zero_lds(lds);
     __syncthreads();
     const int64_t gtid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    count_range(lds, R.hist, R.vol, R.n, gtid, (int64_t)R.blocks * kThreads);
+    count_range<PAIRED>(lds, R.hist, R.vol, R.n, gtid, (int64_t)R.blocks * kThreads);
     __syncthreads();
-    flush_lds(lds, R.hist);
+    flush_lds<PAIRED>(lds, R.hist);
+}
+
+// One workgroup per histogram: the 32768 words of bin pairs are read into
+// registers, then written out as 65536 64-bit bins in the same buffer.
+constexpr int kPairWords = VR_NBINS / 2;
+constexpr int kPairsPerThread = kPairWords / kThreads;
+
+__global__ void __launch_bounds__(kThreads) unpack_pairs(uint64_t* __restrict__ h0, uint64_t* __restrict__ h1)
+{
+    uint64_t* h = blockIdx.x == 0 ? h0 : h1;
+    uint64_t v[kPairsPerThread];
+#pragma unroll
+    for (int i = 0; i < kPairsPerThread; ++i) v[i] = h[threadIdx.x + i * kThreads];
+    // every word is read before any bin is written: the fence waits for this
+    // thread's loads to return, the barrier for every thread's
+    __threadfence();
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPairsPerThread; ++i) {
+        const int w = threadIdx.x + i * kThreads;
+        h[2 * w] = v[i] & 0xFFFFFFFFull;
+        h[2 * w + 1] = v[i] >> 32;
+    }
+}
+
+// whether the bins of a run of n voxels may be kept in pairs
+bool paired_for(int64_t n) { return n < (int64_t(1) << 32); }
+
+int launch_unpack(hipStream_t s, uint64_t* h0, uint64_t* h1, const char* who)
+{
+    unpack_pairs<<<h1 ? 2 : 1, kThreads, 0, s>>>(h0, h1);
+    return vr::check_launch(who);
+}
+
+void launch_hist(const Range& r, bool paired, hipStream_t s)
+{
+    if (paired) hist_kernel<true><<<(unsigned)r.blocks, kThreads, 0, s>>>(r);
+    else hist_kernel<false><<<(unsigned)r.blocks, kThreads, 0, s>>>(r);
 }
 
 Range make_range(const uint16_t* p, int64_t n, uint64_t* hist)
@@ -67,13 +110,14 @@ int blocks_for(int64_t n, int cap)
 // The voxels p[0 .. n) of one row, counted by the 64 lanes of a wave: the
 // voxels before the first 16-byte boundary and after the last one by single
 // lanes, the body in 16-byte chunks, four chunks per lane in flight.
+template <bool PAIRED>
 __device__ __forceinline__ void count_row(uint32_t* lds, uint64_t* gh, const uint16_t* p, int64_t n, int lane)
 {
     int64_t head = (int64_t)(((16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) / 2u);
     if (head > n) head = n;
     const int64_t nch = (n - head) / 8, tail = head + nch * 8;
-    if (lane < head) count_n(lds, gh, p[lane], 1u);
-    if (lane < n - tail) count_n(lds, gh, p[tail + lane], 1u);
+    if (lane < head) count_n<PAIRED>(lds, gh, p[lane], 1u);
+    if (lane < n - tail) count_n<PAIRED>(lds, gh, p[tail + lane], 1u);
     const uint4* b = reinterpret_cast<const uint4*>(p + head);
     for (int64_t i = lane; i < nch; i += 4 * 64) {
         uint4 c[4];
@@ -82,7 +126,7 @@ __device__ __forceinline__ void count_row(uint32_t* lds, uint64_t* gh, const uin
             if (i + u * 64 < nch) c[u] = load_stream(b + i + u * 64);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (i + u * 64 < nch) count_chunk(lds, gh, c[u]);
+            if (i + u * 64 < nch) count_chunk<PAIRED>(lds, gh, c[u]);
     }
 }
 
@@ -94,6 +138,7 @@ struct DiscRange {
     uint64_t* hist;
 };
 
+template <bool PAIRED>
 __global__ void __launch_bounds__(kThreads) hist_disc_kernel(DiscRange R)
 {
     __shared__ uint32_t lds[kWords];
@@ -105,10 +150,10 @@ __global__ void __launch_bounds__(kThreads) hist_disc_kernel(DiscRange R)
     for (int64_t row = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; row < R.rows; row += nw) {
         int64_t x0, x1;
         vr::disc::row_span(d, row % R.ny, R.nx, x0, x1);
-        if (x0 <= x1) count_row(lds, R.hist, R.vol + row * R.nx + x0, x1 - x0 + 1, lane);
+        if (x0 <= x1) count_row<PAIRED>(lds, R.hist, R.vol + row * R.nx + x0, x1 - x0 + 1, lane);
     }
     __syncthreads();
-    flush_lds(lds, R.hist);
+    flush_lds<PAIRED>(lds, R.hist);
 }
 
 // n / d for n < 2^32 by a 64-bit reciprocal: m = floor((2^64 - 1) / d) + 1
@@ -156,6 +201,7 @@ __device__ __forceinline__ uint32_t chunk_keep(uint32_t i, const DiscStream& S, 
 // The chunk's voxels whose bit is set in k, in one instruction stream for
 // whole, partial and (per lane) absent chunks: eight predicated additions,
 // or one addition when the wave's kept chunks are all eight copies of one value.
+template <bool PAIRED>
 __device__ __forceinline__ void count_kept(uint32_t* lds, uint64_t* gh, uint4 c, uint32_t k)
 {
     const uint32_t v0 = c.x & 0xFFFFu;
@@ -164,15 +210,16 @@ __device__ __forceinline__ void count_kept(uint32_t* lds, uint64_t* gh, uint4 c,
     if (act == 0) return;
     const uint32_t w0 = __shfl(v0, __builtin_ctzll(act));
     if (__ballot(k != 0u && same8 && v0 == w0) == act) {
-        if (__lane_id() == (uint32_t)__builtin_ctzll(act)) count_n(lds, gh, w0, 8u * (uint32_t)__popcll(act));
+        if (__lane_id() == (uint32_t)__builtin_ctzll(act)) count_n<PAIRED>(lds, gh, w0, 8u * (uint32_t)__popcll(act));
         return;
     }
     const uint32_t w[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-        if ((k >> e) & 1u) count_1(lds, gh, (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        if ((k >> e) & 1u) count_1<PAIRED>(lds, gh, (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
 }
 
+template <bool PAIRED>
 __global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
 {
     __shared__ uint32_t lds[kWords];
@@ -212,7 +259,7 @@ __global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) count_kept(lds, S.hist, cur[u], kc[u]);
+            for (int u = 0; u < kUnroll; ++u) count_kept<PAIRED>(lds, S.hist, cur[u], kc[u]);
             if (!more) {
                 i = (uint32_t)nx_;
                 break;
@@ -229,10 +276,10 @@ __global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
         const uint32_t k = chunk_keep(i, S, spans);
         uint4 c = make_uint4(0u, 0u, 0u, 0u);
         if (k) c = load_stream(S.body + i);
-        count_kept(lds, S.hist, c, k);
+        count_kept<PAIRED>(lds, S.hist, c, k);
     }
     __syncthreads();
-    flush_lds(lds, S.hist);
+    flush_lds<PAIRED>(lds, S.hist);
 }
 
 int check_dims(int64_t nx, int64_t ny, int64_t nz, const char* who)
@@ -263,8 +310,11 @@ extern "C" int vr_histogram(const uint16_t* d_vol, int64_t nx, int64_t ny, int64
 
     Range a = make_range(d_vol + z0 * nx * ny, nx * ny * nz_range, d_hist);
     a.blocks = blocks_for(a.n, vr::num_cus());
-    hist_kernel<<<(unsigned)a.blocks, kThreads, 0, s>>>(a);
-    return vr::check_launch("vr_histogram");
+    const bool paired = paired_for(a.n);
+    launch_hist(a, paired, s);
+    rc = vr::check_launch("vr_histogram");
+    if (rc || !paired) return rc;
+    return launch_unpack(s, d_hist, nullptr, "vr_histogram: unpack");
 }
 
 extern "C" int vr_histogram_with_top(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
@@ -285,15 +335,18 @@ extern "C" int vr_histogram_with_top(const uint16_t* d_vol, int64_t nx, int64_t 
     // size warrants, then the whole volume on every compute unit (one launch
     // sharing the compute units between the two runs measured slower)
     const int cus = vr::num_cus();
+    const bool paired = paired_for(nx * ny * nz);
     Range b = make_range(d_vol, nx * ny * top_slices, d_hist_top);
     b.blocks = blocks_for(b.n, cus);
-    hist_kernel<<<(unsigned)b.blocks, kThreads, 0, s>>>(b);
+    launch_hist(b, paired, s);
     rc = vr::check_launch("vr_histogram_with_top: top slices");
     if (rc) return rc;
     Range a = make_range(d_vol, nx * ny * nz, d_hist);
     a.blocks = blocks_for(a.n, cus);
-    hist_kernel<<<(unsigned)a.blocks, kThreads, 0, s>>>(a);
-    return vr::check_launch("vr_histogram_with_top");
+    launch_hist(a, paired, s);
+    rc = vr::check_launch("vr_histogram_with_top");
+    if (rc || !paired) return rc;
+    return launch_unpack(s, d_hist, d_hist_top, "vr_histogram_with_top: unpack");
 }
 
 extern "C" int vr_histogram_in_disc(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz, int64_t top_slices,
@@ -313,15 +366,18 @@ extern "C" int vr_histogram_in_disc(const uint16_t* d_vol, int64_t nx, int64_t n
     // whole 16-byte chunks per row, a span table that fits, 32-bit chunk indices
     const bool stream_ok = nx % 8 == 0 && (reinterpret_cast<uintptr_t>(d_vol) & 15u) == 0 &&
                            ny <= kMaxSpanRows && nx <= 65536 && nx * ny * nz / 8 < (int64_t(1) << 31);
+    const bool paired = paired_for(nx * ny * nz);
     auto launch = [&](int64_t slices, uint64_t* h) {
         const int blocks = blocks_for(nx * ny * slices, cus);
         if (stream_ok) {
             DiscStream S{reinterpret_cast<const uint4*>(d_vol), (uint32_t)(nx * ny * slices / 8), (uint32_t)ny,
                          make_div((uint32_t)(nx / 8)), make_div((uint32_t)ny), d_circle, h};
-            hist_disc_stream<<<(unsigned)blocks, kThreads, 0, s>>>(S);
+            if (paired) hist_disc_stream<true><<<(unsigned)blocks, kThreads, 0, s>>>(S);
+            else hist_disc_stream<false><<<(unsigned)blocks, kThreads, 0, s>>>(S);
         } else {
             DiscRange R{d_vol, nx, ny, ny * slices, d_circle, h};
-            hist_disc_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(R);
+            if (paired) hist_disc_kernel<true><<<(unsigned)blocks, kThreads, 0, s>>>(R);
+            else hist_disc_kernel<false><<<(unsigned)blocks, kThreads, 0, s>>>(R);
         }
     };
     if (d_hist_top != nullptr) {
@@ -330,5 +386,7 @@ extern "C" int vr_histogram_in_disc(const uint16_t* d_vol, int64_t nx, int64_t n
         if (rc) return rc;
     }
     launch(nz, d_hist);
-    return vr::check_launch("vr_histogram_in_disc");
+    rc = vr::check_launch("vr_histogram_in_disc");
+    if (rc || !paired) return rc;
+    return launch_unpack(s, d_hist, d_hist_top, "vr_histogram_in_disc: unpack");
 }
