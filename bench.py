@@ -298,6 +298,56 @@ def run_container(steps=5):
     return out
 
 
+def run_small(reps=20, warm=3):
+    """The 128^3 configuration (launch-bound, about 9 MB moved): histograms,
+    valley selection, one 2x level with its 512^2 slicemap (8 x 8 tiles), one
+    orthographic 256^2 view at step 0.5 and its entropy; per-call device
+    microseconds, median of `reps` after `warm` warm-ups."""
+    import torch
+
+    from paper_2311_15038_amd import pipeline as P
+    from paper_2311_15038_amd import synth
+
+    dev = torch.device("cuda:0")
+    vol = synth.make_volume(synth.SMALL, dev)
+    cfg = P.PreviewConfig(n_levels=1, atlas_level=1, render_level=1, n_views=1, width=256, height=256,
+                          ortho=True)
+    pipe = P.PreviewPipeline(vol.shape, cfg, device=dev)
+    calls = pipe.calls(vol)
+    for _ in range(warm):
+        for _, fn in calls:
+            fn()
+    torch.cuda.synchronize()
+    ev = {name: _events(2 * reps) for name, _ in calls}
+    tot = _events(2 * reps)
+    for r in range(reps):
+        tot[2 * r].record()
+        for name, fn in calls:
+            ev[name][2 * r].record()
+            fn()
+            ev[name][2 * r + 1].record()
+        tot[2 * r + 1].record()
+    torch.cuda.synchronize()
+    med = lambda e: sorted(e[2 * r].elapsed_time(e[2 * r + 1]) for r in range(reps))[reps // 2] * 1e3  # noqa: E731
+    return {"workload": "128^3 u16 (seed 2311): histograms, valley, 64^3 level + 512^2 slicemap, "
+                        "one orthographic 256^2 view at step 0.5, best view",
+            "us_per_call": {name: med(e) for name, e in ev.items()}, "us_per_step": med(tot),
+            "threshold": int(pipe.result[0].item()), "reps": reps}
+
+
+def run_bandwidth(reps=5):
+    """A measured HBM ceiling on this GPU: a 1 GiB device-to-device copy (2 GiB
+    moved), median of `reps`."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    copy_ms = _median_ms(lambda: dst.copy_(src), reps)
+    del src, dst
+    return {"copy_GB_per_s": 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9}
+
+
 def _median_ms(fn, reps=5):
     import torch
     fn()
@@ -576,6 +626,10 @@ def main():
                             for k, b in res["kernel_bytes"].items()},
     }
     line["threshold_rules"] = run_thresholds(pipe)
+    bw = run_bandwidth()
+    line["measured_bandwidth"] = bw
+    line["reduction"]["frac_of_measured_copy"] = red_gbs / bw["copy_GB_per_s"]
+    line["small"] = run_small()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(pipe, vol)
     if not args.no_extras:

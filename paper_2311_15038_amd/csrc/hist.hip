@@ -75,8 +75,10 @@ __global__ void __launch_bounds__(kThreads) unpack_pairs(uint64_t* __restrict__ 
     }
 }
 
-// whether the bins of a run of n voxels may be kept in pairs
-bool paired_for(int64_t n) { return n < (int64_t(1) << 32); }
+// Whether the bins of a run of n voxels are kept in pairs: every bin's total
+// must stay below 2^32, and the run must be large enough (32 M voxels, every
+// compute unit busy) for the saved flush atomics to outweigh the unpack pass.
+bool paired_for(int64_t n) { return n >= (int64_t(1) << 25) && n < (int64_t(1) << 32); }
 
 int launch_unpack(hipStream_t s, uint64_t* h0, uint64_t* h1, const char* who)
 {

@@ -263,3 +263,24 @@ def test_reduction_chain_small_config(small_volume):
     assert u32_np(res)[0] == T
     assert (u16_np(L1) == L1o).all()
     assert (u16_np(atlas) == O.slicemap(L1o, 8, 8)).all()
+
+
+def test_histograms_with_paired_bins_ragged():
+    """A volume large enough (>= 2^25 voxels) for the bins to be kept in 32-bit
+    pairs during counting, with a ragged shape and uniform values (every bin
+    busy): all three histogram calls against the oracle."""
+    from oracle import container as K
+    shape = (1000, 257, 131)                                # 33.7 M voxels
+    banner(f"histogram paired bins {shape}")
+    a = _rand_vol(shape, 12)
+    assert a.size >= 1 << 25
+    v = to_dev_u16(a)
+    H = O.histogram(a)
+    assert np.array_equal(u64_np(vr.vr_histogram(v)), H)
+    assert np.array_equal(u64_np(vr.vr_histogram(v, 100, 900)), O.histogram(a, 100, 900))
+    h, ht = vr.vr_histogram_with_top(v, 3)
+    assert np.array_equal(u64_np(h), H) and np.array_equal(u64_np(ht), O.histogram(a, 0, 3))
+    rec = np.array([1, 70, 120, 100, 96, 1, 1, 1], dtype=np.int32)
+    h, ht = vr.vr_histogram_in_disc(v, torch.from_numpy(rec).to(dev()), 3)
+    assert np.array_equal(u64_np(h), K.histogram_in_disc(a, rec))
+    assert np.array_equal(u64_np(ht), K.histogram_in_disc(a, rec, 0, 3))
