@@ -487,9 +487,10 @@ extern "C" int vr_batch_plan_create(const vr_batch_item* items, int n_items, con
         return rc;
     }
     P->dev.tf = reinterpret_cast<const float4*>(d_tf);
-    hipGetDevice(&P->device);
+    hipError_t e = hipGetDevice(&P->device);
     // descriptors and tasks to the device; counters, histograms and flags start at zero
-    hipError_t e = hipMemcpy(const_cast<ItemDev*>(P->dev.items), P->items.data(), sizeof(ItemDev) * n_items,
+    if (e == hipSuccess)
+        e = hipMemcpy(const_cast<ItemDev*>(P->dev.items), P->items.data(), sizeof(ItemDev) * n_items,
                              hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(const_cast<Task*>(P->dev.tasks), tasks.data(), sizeof(Task) * tasks.size(),
@@ -569,8 +570,13 @@ extern "C" int vr_batch_plan_destroy(vr_batch_plan* plan)
 {
     vr::clear_error();
     if (plan == nullptr) return VR_OK;
-    if (plan->exec) hipGraphExecDestroy(plan->exec);
-    if (plan->graph) hipGraphDestroy(plan->graph);
+    hipError_t e = hipSuccess;
+    if (plan->exec) e = hipGraphExecDestroy(plan->exec);
+    if (plan->graph) {
+        const hipError_t g = hipGraphDestroy(plan->graph);
+        if (e == hipSuccess) e = g;
+    }
     delete plan;
+    VR_REQUIRE(e == hipSuccess, VR_ERR_HIP, "vr_batch_plan_destroy: %s", hipGetErrorString(e));
     return VR_OK;
 }
