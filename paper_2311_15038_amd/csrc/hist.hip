@@ -158,44 +158,42 @@ __global__ void __launch_bounds__(kThreads) hist_disc_kernel(DiscRange R)
     flush_lds<PAIRED>(lds, R.hist);
 }
 
-// n / d for n < 2^32 by a 64-bit reciprocal: m = floor((2^64 - 1) / d) + 1
-// (exact for every such n; d = 1 handled apart).
-struct FastDiv {
-    uint64_t m;
-    uint32_t d;
-};
-
-FastDiv make_div(uint32_t d) { return FastDiv{d > 1 ? (~uint64_t(0)) / d + 1 : 0, d}; }
-
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f)
-{
-    return f.d == 1 ? n : (uint32_t)__umul64hi((uint64_t)n, f.m);
-}
-
 constexpr int kMaxSpanRows = 4096;       // rows of the streaming variant's span table
 
 // The streaming variant for slabs whose rows are whole 16-byte chunks: the
-// chunk sequence of the slab is walked as in hist_kernel, each chunk's row
-// found by reciprocal division and its kept run read from a table in LDS;
-// chunks outside the disc are not loaded, chunks across its edge are counted
-// voxel by voxel.
+// chunk sequence of the slab is walked as in hist_kernel; each thread carries
+// the (column, row) of its current chunk forward by its fixed stride, and
+// reads the row's kept run from a table in LDS.  Chunks outside the disc are
+// not loaded, chunks across its edge are counted voxel by voxel.
 struct DiscStream {
     const uint4* body;     // 16-byte aligned first voxel of the slab
     uint32_t n_chunks;     // chunks of the slab
     uint32_t ny;
-    FastDiv per_row;       // chunks per row
-    FastDiv rows;          // ny
+    uint32_t per_row;      // chunks per row
     const int32_t* rec;
     uint64_t* hist;
 };
 
-// bits e of the chunk's voxels inside their row's kept run
-__device__ __forceinline__ uint32_t chunk_keep(uint32_t i, const DiscStream& S, const uint32_t* spans)
+// column and image row (row of the slab modulo ny) of a chunk
+struct ChunkPos {
+    uint32_t col, y;
+};
+
+// advance by a stride of dcol columns and drow rows (dcol < per_row, drow < ny)
+__device__ __forceinline__ void advance(ChunkPos& p, uint32_t dcol, uint32_t drow, uint32_t per_row, uint32_t ny)
 {
-    const uint32_t row = fdiv(i, S.per_row);
-    const uint32_t y = row - fdiv(row, S.rows) * S.ny;
-    const int x = (int)(8u * (i - row * S.per_row.d));
-    const uint32_t sp = spans[y];
+    p.col += dcol;
+    const uint32_t carry = p.col >= per_row ? 1u : 0u;
+    p.col -= carry * per_row;
+    p.y += drow + carry;
+    if (p.y >= ny) p.y -= ny;
+}
+
+// bits e of the chunk's voxels inside their row's kept run
+__device__ __forceinline__ uint32_t chunk_keep(const ChunkPos& p, const uint32_t* spans)
+{
+    const int x = (int)(8u * p.col);
+    const uint32_t sp = spans[p.y];
     const int lo = max((int)(sp & 0xFFFFu) - x, 0), hi = min((int)(sp >> 16) - x, 7);
     return lo > hi ? 0u : (0xFFu >> (7 - hi)) & (0xFFu << lo);
 }
@@ -229,7 +227,7 @@ __global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
     zero_lds(lds);
     {
         const vr::disc::Disc d = vr::disc::load_disc(S.rec);
-        const int64_t nx = (int64_t)S.per_row.d * 8;
+        const int64_t nx = (int64_t)S.per_row * 8;
         for (uint32_t y = threadIdx.x; y < S.ny; y += kThreads) {
             int64_t x0, x1;
             vr::disc::row_span(d, y, nx, x0, x1);
@@ -240,15 +238,19 @@ __global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
     const uint32_t nthr = gridDim.x * kThreads;
     uint32_t i = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t stride = kUnroll * nthr;
+    const uint32_t dcol = nthr % S.per_row, drow = (nthr / S.per_row) % S.ny;
+    ChunkPos p{i % S.per_row, (i / S.per_row) % S.ny};   // position of chunk i
     if ((uint64_t)i + (kUnroll - 1) * (uint64_t)nthr < S.n_chunks) {
         uint4 cur[kUnroll];
         uint32_t kc[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            kc[u] = chunk_keep(i + u * nthr, S, spans);
+            kc[u] = chunk_keep(p, spans);
             cur[u] = kc[u] ? load_stream(S.body + i + u * nthr) : make_uint4(0u, 0u, 0u, 0u);
+            advance(p, dcol, drow, S.per_row, S.ny);
         }
         for (;;) {
+            // p is the position of chunk i + stride here
             const uint64_t nx_ = (uint64_t)i + stride;
             const bool more = nx_ + (kUnroll - 1) * (uint64_t)nthr < S.n_chunks;
             uint4 nxt[kUnroll];
@@ -256,17 +258,15 @@ __global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
             if (more) {
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    kn[u] = chunk_keep((uint32_t)nx_ + u * nthr, S, spans);
+                    kn[u] = chunk_keep(p, spans);
                     nxt[u] = kn[u] ? load_stream(S.body + nx_ + u * nthr) : make_uint4(0u, 0u, 0u, 0u);
+                    advance(p, dcol, drow, S.per_row, S.ny);
                 }
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) count_kept<PAIRED>(lds, S.hist, cur[u], kc[u]);
-            if (!more) {
-                i = (uint32_t)nx_;
-                break;
-            }
             i = (uint32_t)nx_;
+            if (!more) break;
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 cur[u] = nxt[u];
@@ -275,10 +275,11 @@ __global__ void __launch_bounds__(kThreads) hist_disc_stream(DiscStream S)
         }
     }
     for (; i < S.n_chunks; i += nthr) {
-        const uint32_t k = chunk_keep(i, S, spans);
+        const uint32_t k = chunk_keep(p, spans);
         uint4 c = make_uint4(0u, 0u, 0u, 0u);
         if (k) c = load_stream(S.body + i);
         count_kept<PAIRED>(lds, S.hist, c, k);
+        advance(p, dcol, drow, S.per_row, S.ny);
     }
     __syncthreads();
     flush_lds<PAIRED>(lds, S.hist);
@@ -373,7 +374,7 @@ extern "C" int vr_histogram_in_disc(const uint16_t* d_vol, int64_t nx, int64_t n
         const int blocks = blocks_for(nx * ny * slices, cus);
         if (stream_ok) {
             DiscStream S{reinterpret_cast<const uint4*>(d_vol), (uint32_t)(nx * ny * slices / 8), (uint32_t)ny,
-                         make_div((uint32_t)(nx / 8)), make_div((uint32_t)ny), d_circle, h};
+                         (uint32_t)(nx / 8), d_circle, h};
             if (paired) hist_disc_stream<true><<<(unsigned)blocks, kThreads, 0, s>>>(S);
             else hist_disc_stream<false><<<(unsigned)blocks, kThreads, 0, s>>>(S);
         } else {
