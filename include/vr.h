@@ -254,6 +254,19 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
 int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t nx, int64_t ny, int64_t nz,
                     void* d_bricked, uint8_t* d_occupancy, void* stream);
 
+/*
+ * Inverse of vr_brick_volume for VR_LAYOUT_BRICK4: writes the [nz][ny][nx]
+ * volume whose brick layout is d_bricked (the padding voxels past the
+ * volume's end are dropped).  Used to bring a density gradient that
+ * vr_raycast_backward produced in the brick layout back to the grid's own
+ * layout.
+ *   d_bricked: vr_brick_count(...) * 64 elements of u16 (VR_U16_NORM) or f32.
+ *   d_dst: nx * ny * nz elements of the same type, overwritten.
+ * Errors: VR_ERR_NULL, VR_ERR_DTYPE, VR_ERR_DIMS, VR_ERR_HIP.
+ */
+int vr_unbrick_volume(const void* d_bricked, int dtype, int64_t nx, int64_t ny, int64_t nz, void* d_dst,
+                      void* stream);
+
 /* Number of 4x4x4 bricks of an nx x ny x nz volume and the size of its
  * occupancy (nullable) in bytes (host only). */
 int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_t* occupancy_bytes);
@@ -356,8 +369,12 @@ int vr_entropy_from_counts(const uint32_t* d_hist, int n_views, int64_t pixels, 
  * then through the transfer-function interpolation to the two knots, and
  * through the trilinear weights to the eight taps (f32 atomics; the
  * summation order is not deterministic).
- * The density must be VR_F32 in VR_LAYOUT_LINEAR (VR_ERR_DTYPE,
- * VR_ERR_UNSUPPORTED otherwise).  vol->occupancy may be NULL, or the
+ * The density must be VR_F32 in VR_LAYOUT_LINEAR or VR_LAYOUT_BRICK4
+ * (VR_ERR_DTYPE, VR_ERR_UNSUPPORTED otherwise); d_grad_density has the
+ * density's layout ([nz][ny][nx], or vr_brick_count(...) * 64 elements in
+ * bricks, to be brought back with vr_unbrick_volume).  The brick layout is
+ * the faster one: a cell's eight taps share one or two cache lines there, and
+ * the gradient's atomics go out a cache line at a time.  vol->occupancy may be NULL, or the
  * occupancy grid that vr_brick_volume wrote for the same grid: then, when the
  * TF's first segment has zero extinction (tf[0].sigma = tf[1].sigma = 0,
  * finite colour), runs of samples whose base tap lies in an empty brick are

@@ -87,3 +87,50 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
     }
     return vr::check_launch("vr_brick_volume");
 }
+
+namespace {
+
+// Inverse of the brick layout: thread (x4, y, z) copies the 4-voxel row of
+// brick (x4, y >> 2, z >> 2) at in-brick row (y & 3, z & 3) to voxels
+// [4 x4, 4 x4 + 4) of row (y, z) of the linear volume, clipped at nx.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+unbrick_kernel(const T* __restrict__ src, int64_t nx, int64_t ny, int64_t nz, int64_t nbx, int64_t nby,
+               T* __restrict__ dst)
+{
+    const int64_t rows = nbx * ny * nz;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < rows; t += (int64_t)gridDim.x * kThreads) {
+        const int64_t bx = t % nbx, yz = t / nbx, y = yz % ny, z = yz / ny;
+        const int64_t b = ((z >> 2) * nby + (y >> 2)) * nbx + bx;
+        const T* row = src + b * 64 + ((z & 3) << 4) + ((y & 3) << 2);
+        T* out = dst + (z * ny + y) * nx + bx * 4;
+        const int64_t m = nx - bx * 4 < 4 ? nx - bx * 4 : 4;
+        for (int64_t q = 0; q < m; ++q) out[q] = row[q];
+    }
+}
+
+}  // namespace
+
+extern "C" int vr_unbrick_volume(const void* d_bricked, int dtype, int64_t nx, int64_t ny, int64_t nz,
+                                 void* d_dst, void* stream)
+{
+    vr::clear_error();
+    VR_REQUIRE(d_bricked && d_dst, VR_ERR_NULL, "vr_unbrick_volume: NULL pointer");
+    VR_REQUIRE(dtype == VR_U16_NORM || dtype == VR_F32, VR_ERR_DTYPE, "vr_unbrick_volume: dtype %d",
+               dtype);
+    VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
+               VR_ERR_DIMS, "vr_unbrick_volume: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
+               (long long)nz);
+    const int64_t nbx = (nx + 3) / 4, nby = (ny + 3) / 4;
+    const int64_t rows = nbx * ny * nz;
+    hipStream_t s = vr::as_stream(stream);
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((int64_t)vr::num_cus() * 16,
+                                                             vr::ceil_div<int64_t>(rows, kThreads)));
+    if (dtype == VR_U16_NORM)
+        unbrick_kernel<uint16_t><<<(unsigned)g, kThreads, 0, s>>>(static_cast<const uint16_t*>(d_bricked), nx, ny,
+                                                                  nz, nbx, nby, static_cast<uint16_t*>(d_dst));
+    else
+        unbrick_kernel<float><<<(unsigned)g, kThreads, 0, s>>>(static_cast<const float*>(d_bricked), nx, ny, nz,
+                                                               nbx, nby, static_cast<float*>(d_dst));
+    return vr::check_launch("vr_unbrick_volume");
+}

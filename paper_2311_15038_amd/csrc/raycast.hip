@@ -106,13 +106,47 @@ __device__ __forceinline__ void flush_tf(float* g, int k, float4 a0, float4 a1)
     atomicAdd(g + 4 * k + 7, a1.w);
 }
 
-// the pending density gradient of one cell's eight taps (none when off is unset)
-__device__ __forceinline__ void flush_cell(float* gvol, const uint32_t (&off)[8], const float (&gc)[8])
+// Density-gradient atomics go to the memory side of the fabric (the XCDs' L2s
+// are not coherent with each other), one request per cache line and
+// instruction, so their cost follows the number of (instruction, line)
+// pairs.  A lane that holds one cell's eight taps would issue eight
+// instructions whose lanes hit unrelated lines.  Instead the lanes of a wave
+// that flush a cell write its (offset, gradient) pairs to the wave's slice of
+// LDS, and the active lanes then take consecutive entries: the taps of one
+// cell (x pairs adjacent in memory) and of the neighbouring rays' cells go out
+// in the same instruction and share lines.
+constexpr int kFlushSlots = 64 * 8;   // entries per wave: every lane flushing one cell
+
+__device__ __forceinline__ void wave_flush(bool f, const uint32_t (&off)[8], const float (&gc)[8],
+                                           float* __restrict__ gvol, uint2* __restrict__ buf)
 {
-    if (off[0] == 0xFFFFFFFFu) return;
+    const uint64_t m = __ballot(f);
+    if (m == 0) return;
+    const uint32_t lane = __lane_id();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+    if (f) {
+        const int r = __popcll(m & below);
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-        if (gc[t] != 0.0f) atomicAdd(gvol + off[t], gc[t]);
+        for (int t = 0; t < 8; ++t) buf[8 * r + t] = make_uint2(off[t], __float_as_uint(gc[t]));
+    }
+    // the wave's own LDS writes above are complete before any lane reads them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t act = __ballot(true);
+    const int n_act = __popcll(act), me = __popcll(act & below);
+    const int n = 8 * __popcll(m);
+    for (int base = 0; base < n; base += n_act) {
+        const int q = base + me;
+        if (q < n) {
+            const uint2 e = buf[q];
+            const float v = __uint_as_float(e.y);
+            if (v != 0.0f) atomicAdd(gvol + e.x, v);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int LAYOUT>
@@ -123,6 +157,8 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
 {
     __shared__ float4 tf_s[256];
     __shared__ float gtf_s[256 * 4];
+    __shared__ uint2 flush_s[kThreads / 64][kFlushSlots];
+    uint2* const fbuf = flush_s[threadIdx.x >> 6];
     tf_s[threadIdx.x] = tf[threadIdx.x];
     for (int q = threadIdx.x; q < 1024; q += kThreads) gtf_s[q] = 0.0f;
     __syncthreads();
@@ -133,6 +169,13 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
     int view, i, j;
     pixel_of(S, (int)gridDim.x, view, i, j);
     const float* vol = static_cast<const float*>(S.data);
+    uint32_t cell_off[8];        // taps of the cell whose density gradient is pending
+    float cell_g[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        cell_off[t] = 0xFFFFFFFFu;
+        cell_g[t] = 0.0f;
+    }
     if (i < S.W && j < S.H) {
         const View& v = V.v[view];
         float p[3], d[3], L;
@@ -155,13 +198,6 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
             }
             uint32_t cur_b = 0xFFFFFFFFu;
             bool cur_full = true;
-            uint32_t cell_off[8];        // taps of the cell whose density gradient is pending
-            float cell_g[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                cell_off[t] = 0xFFFFFFFFu;
-                cell_g[t] = 0.0f;
-            }
             for (int k = 0; k < n;) {
                 const float len = (k < n - 1) ? S.step : last;
                 const float off = fmaf(0.5f, len, (float)k * S.step);
@@ -227,37 +263,40 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                 a0.z = fmaf(w0, G.z, a0.z); a0.w = fmaf(w0, G.w, a0.w);
                 a1.x = fmaf(h.w, G.x, a1.x); a1.y = fmaf(h.w, G.y, a1.y);
                 a1.z = fmaf(h.w, G.z, a1.z); a1.w = fmaf(h.w, G.w, a1.w);
+                float ds = 0.0f;
                 if (sm.s >= 0.0f && sm.s <= 1.0f) {
                     const float4 ka = tf_s[h.k], kb = tf_s[h.k + 1];
-                    const float ds = 255.0f * ((kb.x - ka.x) * G.x + (kb.y - ka.y) * G.y +
-                                               (kb.z - ka.z) * G.z + (kb.w - ka.w) * G.w);
-                    if (ds != 0.0f) {
-                        // consecutive samples of one cell add to the same eight taps: their
-                        // gradients are summed in registers and scattered once per cell
-                        if (sm.off[0] != cell_off[0] || sm.off[7] != cell_off[7]) {
-                            flush_cell(gvol, cell_off, cell_g);
+                    ds = 255.0f * ((kb.x - ka.x) * G.x + (kb.y - ka.y) * G.y + (kb.z - ka.z) * G.z +
+                                   (kb.w - ka.w) * G.w);
+                }
+                // consecutive samples of one cell add to the same eight taps: their
+                // gradients are summed in registers and scattered once per cell
+                const bool change = ds != 0.0f && (sm.off[0] != cell_off[0] || sm.off[7] != cell_off[7]);
+                wave_flush(change && cell_off[0] != 0xFFFFFFFFu, cell_off, cell_g, gvol, fbuf);
+                if (change) {
 #pragma unroll
-                            for (int t = 0; t < 8; ++t) {
-                                cell_off[t] = sm.off[t];
-                                cell_g[t] = 0.0f;
-                            }
-                        }
-                        const float ax = 1.0f - sm.wx, ay = 1.0f - sm.wy, az = 1.0f - sm.wz;
-                        const float w[8] = {ax * ay * az, sm.wx * ay * az, ax * sm.wy * az, sm.wx * sm.wy * az,
-                                            ax * ay * sm.wz, sm.wx * ay * sm.wz, ax * sm.wy * sm.wz,
-                                            sm.wx * sm.wy * sm.wz};
-#pragma unroll
-                        for (int t = 0; t < 8; ++t) cell_g[t] = fmaf(w[t], ds, cell_g[t]);
+                    for (int t = 0; t < 8; ++t) {
+                        cell_off[t] = sm.off[t];
+                        cell_g[t] = 0.0f;
                     }
+                }
+                if (ds != 0.0f) {
+                    const float ax = 1.0f - sm.wx, ay = 1.0f - sm.wy, az = 1.0f - sm.wz;
+                    const float w[8] = {ax * ay * az, sm.wx * ay * az, ax * sm.wy * az, sm.wx * sm.wy * az,
+                                        ax * ay * sm.wz, sm.wx * ay * sm.wz, ax * sm.wy * sm.wz,
+                                        sm.wx * sm.wy * sm.wz};
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) cell_g[t] = fmaf(w[t], ds, cell_g[t]);
                 }
                 Tr = te;
                 ++k;
                 if (Tr < S.eps) break;
             }
             if (kc >= 0) flush_tf(gtf_s, kc, a0, a1);
-            flush_cell(gvol, cell_off, cell_g);
         }
     }
+    // the last pending cell of every ray, with the whole wave converged
+    wave_flush(cell_off[0] != 0xFFFFFFFFu, cell_off, cell_g, gvol, fbuf);
     __syncthreads();
     for (int q = threadIdx.x; q < 1024; q += kThreads) {
         const float x = gtf_s[q];
@@ -321,8 +360,8 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
     int rc = build_scene(vol, d_tf, h_cams, n_views, opts, S);
     if (rc) return rc;
     VR_REQUIRE(vol->dtype == VR_F32, VR_ERR_DTYPE, "vr_raycast_backward: density must be VR_F32");
-    VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR, VR_ERR_UNSUPPORTED,
-               "vr_raycast_backward: the density gradient is produced for the linear layout only");
+    VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4, VR_ERR_UNSUPPORTED,
+               "vr_raycast_backward: the density gradient is produced for the linear and brick layouts only");
     // the occupancy of vr_brick_volume on the same grid, if given, lets the adjoint
     // pass over empty bricks (build_scene keeps it for the brick layouts only)
     S.occ = vol->occupancy;
@@ -337,9 +376,15 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
         S.view0 = v0;
         const int64_t blocks = (int64_t)S.tiles_x * S.tiles_y * nv;
         VR_REQUIRE(blocks < (int64_t(1) << 31), VR_ERR_DIMS, "vr_raycast_backward: too many tiles");
-        raycast_bwd<VR_LAYOUT_LINEAR><<<(unsigned)blocks, kThreads, 0, s>>>(
-            V, S, reinterpret_cast<const float4*>(d_tf), reinterpret_cast<const float4*>(d_rgba_fwd),
-            reinterpret_cast<const float4*>(d_grad_rgba), d_grad_density, d_grad_tf);
+        const auto* tf4 = reinterpret_cast<const float4*>(d_tf);
+        const auto* fwd4 = reinterpret_cast<const float4*>(d_rgba_fwd);
+        const auto* grad4 = reinterpret_cast<const float4*>(d_grad_rgba);
+        if (vol->layout == VR_LAYOUT_BRICK4)
+            raycast_bwd<VR_LAYOUT_BRICK4><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf4, fwd4, grad4,
+                                                                                d_grad_density, d_grad_tf);
+        else
+            raycast_bwd<VR_LAYOUT_LINEAR><<<(unsigned)blocks, kThreads, 0, s>>>(V, S, tf4, fwd4, grad4,
+                                                                                d_grad_density, d_grad_tf);
         rc = vr::check_launch("vr_raycast_backward");
         if (rc) return rc;
     }

@@ -99,6 +99,7 @@ def lib():
         L.vr_raycast_backward.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                           C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
         L.vr_brick_volume.argtypes = [vp, i32, i32, i64, i64, i64, vp, vp, vp]
+        L.vr_unbrick_volume.argtypes = [vp, i32, i64, i64, i64, vp, vp]
         L.vr_frame_entropy.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.vr_entropy_from_counts.argtypes = [vp, i32, i64, vp, vp, vp]
         L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -115,7 +116,7 @@ def lib():
         L.vr_version.restype = C.c_char_p
         for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
                      "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
-                     "vr_frame_entropy", "vr_entropy_from_counts", "vr_container_workspace_size",
+                     "vr_unbrick_volume", "vr_frame_entropy", "vr_entropy_from_counts", "vr_container_workspace_size",
                      "vr_find_container", "vr_remove_container", "vr_histogram_in_disc",
                      "vr_threshold_downsample_in_disc",
                      "vr_brick_count", "vr_histogram_with_top", "vr_batch_workspace_size",
@@ -352,6 +353,22 @@ def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False
     return out
 
 
+def vr_unbrick_volume(bricked, out=None, stream=None):
+    """The [nz][ny][nx] volume of a BrickedVolume in VR_LAYOUT_BRICK4 (a new
+    tensor, or written into out)."""
+    if bricked.layout != LAYOUT_BRICK4:
+        raise ValueError("vr_unbrick_volume takes the 4^3 brick layout")
+    nz, ny, nx = bricked.shape
+    nb, _ = vr_brick_count(nx, ny, nz)
+    t = bricked.data
+    dt = U16_NORM if t.dtype in _U16 else F32
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=t.dtype, device=t.device)
+    _check(lib().vr_unbrick_volume(_dev(t, "bricked", (*_U16, torch.float32), nb * 64), dt, nx, ny, nz,
+                                   _dev(out, "out", t.dtype, nx * ny * nz), _stream(stream)))
+    return out
+
+
 def make_volume(data, spacing=(1.0, 1.0, 1.0)):
     """vr_volume for a uint16 (normalised) or float32 tensor [nz][ny][nx], or a BrickedVolume."""
     if isinstance(data, BrickedVolume):
@@ -445,6 +462,8 @@ def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba
                         grad_tf, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
                         bg=(0.0, 0.0, 0.0, 0.0), stream=None, occupancy=None):
     """Adds dLoss/dDensity and dLoss/dTF into grad_density / grad_tf (zero them first).
+    data: an f32 [nz][ny][nx] tensor, or its BrickedVolume (4^3 bricks); grad_density
+    has the same layout (vr_unbrick_volume brings a bricked one back).
     occupancy: the occupancy grid vr_brick_volume wrote for the same grid, or None
     (with it, runs of samples in empty bricks are not marched)."""
     vol = make_volume(data, spacing)
@@ -453,10 +472,15 @@ def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba
     ca, nv = make_cameras(cams)
     opts = make_opts(width, height, step, ert_eps, bg)
     n = nv * height * width * 4
+    if isinstance(data, BrickedVolume):
+        nz, ny, nx = data.shape
+        n_grad = vr_brick_count(nx, ny, nz)[0] * 64
+    else:
+        n_grad = int(np.prod(vol_shape(data)))
     _check(lib().vr_raycast_backward(
         C.byref(vol), _dev(tf, "tf", torch.float32, 1024), ca, nv, C.byref(opts),
         _dev(rgba_fwd, "rgba_fwd", torch.float32, n), _dev(grad_rgba, "grad_rgba", torch.float32, n),
-        _dev(grad_density, "grad_density", torch.float32, int(np.prod(vol_shape(data)))),
+        _dev(grad_density, "grad_density", torch.float32, n_grad),
         _dev(grad_tf, "grad_tf", torch.float32, 1024), _stream(stream)))
     return grad_density, grad_tf
 

@@ -95,6 +95,9 @@ def test_brick_validation_on_the_host(lib):
     assert lib.vr_brick_volume(p, vr.U16_NORM, 7, 8, 8, 8, p, None, None) == -3
     assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 0, 8, 8, p, None, None) == -2
     assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 8, 8, 8, C.c_void_p(258), None, None) == -3
+    assert lib.vr_unbrick_volume(None, vr.F32, 8, 8, 8, p, None) == -1
+    assert lib.vr_unbrick_volume(p, 7, 8, 8, 8, p, None) == -4
+    assert lib.vr_unbrick_volume(p, vr.U16_NORM, 8, 0, 8, p, None) == -2
     n, o = C.c_int64(0), C.c_int64(0)
     assert lib.vr_brick_count(9, 5, 4, C.byref(n), C.byref(o)) == 0
     assert n.value == 3 * 2 * 1 and o.value == 6 + 1
