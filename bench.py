@@ -348,6 +348,30 @@ def run_bandwidth(reps=5):
     return {"copy_GB_per_s": 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9}
 
 
+def run_hollow(pipe, reps=20):
+    """The hollow data preview (Section II) of the rendered 512^3 level: device
+    time of one vr_hollow launch (median of `reps`) at thicknesses 1, 2 and 4,
+    its rate against the HBM peak (the level read once, the hollow level
+    written once), and the share of the level's non-zero voxels it keeps."""
+    import torch
+
+    from paper_2311_15038_amd import vr
+
+    level = pipe.levels[pipe.cfg.render_level - 1]
+    out = torch.empty_like(level)
+    kept = torch.zeros(1, dtype=torch.int64, device=level.device)
+    nonzero = int(torch.count_nonzero(level).item())
+    nbytes = 2 * level.numel() * level.element_size()
+    res = {"level": list(level.shape), "algorithmic_bytes": nbytes, "nonzero_voxels": nonzero}
+    for t in (1, 2, 4):
+        ms = _median_ms(lambda t=t: vr.vr_hollow(level, t, out=out, kept=kept), reps)
+        k = int(kept.item())
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[f"t{t}"] = {"ms": ms, "GB_per_s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                        "kept_voxels": k, "kept_of_nonzero": k / max(nonzero, 1)}
+    return res
+
+
 def _median_ms(fn, reps=5):
     import torch
     fn()
@@ -549,6 +573,8 @@ def main():
                     help="only the container-removal leg (for kernel profiles)")
     ap.add_argument("--fit-only", action="store_true",
                     help="only the 200-step fit leg (for kernel profiles)")
+    ap.add_argument("--hollow-only", action="store_true",
+                    help="only the hollow data-preview leg (for kernel profiles)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured window of the serving trace (after 5 s of warm-up)")
     args = ap.parse_args()
@@ -569,6 +595,15 @@ def main():
         return
     if args.container_only:
         print(json.dumps({"container": run_container(args.steps)}), flush=True)
+        return
+    if args.hollow_only:
+        from paper_2311_15038_amd import pipeline as P
+        from paper_2311_15038_amd import synth
+        vol = synth.make_volume(synth.FULL, torch.device("cuda:0"))
+        pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=torch.device("cuda:0"))
+        pipe.reduce(vol)
+        del vol
+        print(json.dumps({"hollow": run_hollow(pipe)}), flush=True)
         return
     if args.fit_only:
         from paper_2311_15038_amd import pipeline as P
@@ -626,6 +661,7 @@ def main():
                             for k, b in res["kernel_bytes"].items()},
     }
     line["threshold_rules"] = run_thresholds(pipe)
+    line["hollow"] = run_hollow(pipe)
     bw = run_bandwidth()
     line["measured_bandwidth"] = bw
     line["reduction"]["frac_of_measured_copy"] = red_gbs / bw["copy_GB_per_s"]

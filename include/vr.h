@@ -214,6 +214,25 @@ int vr_threshold_downsample_in_disc(const uint16_t* d_vol, int64_t nx, int64_t n
                                     uint16_t* const* h_levels, const vr_atlas_spec* atlas, void* stream);
 
 /*
+ * Hollow data preview (Section II: a preview that keeps the object's outer
+ * geometry and drops its interior volume; the paper gives no algorithm).
+ * A voxel of the [nz][ny][nx] u16 volume d_src is kept when it is non-zero
+ * and some voxel within city-block distance `thickness` of it is zero or lies
+ * outside the volume: the shell that `thickness` binary erosions of the
+ * non-zero set with the 6-neighbourhood (zero border) take away.  Kept voxels
+ * keep their value in d_dst; every other voxel of d_dst becomes 0.  Cavities
+ * inside the object are background too, so their walls are kept.
+ *   thickness: 1 .. VR_HOLLOW_MAX_THICKNESS voxels.
+ *   d_dst: nx*ny*nz u16, overwritten; must not overlap d_src.
+ *   d_kept: NULL or one u64, overwritten with the number of kept voxels.
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (thickness, overlap),
+ * VR_ERR_HIP.
+ */
+#define VR_HOLLOW_MAX_THICKNESS 8
+int vr_hollow(const uint16_t* d_src, int64_t nx, int64_t ny, int64_t nz, int thickness, uint16_t* d_dst,
+              uint64_t* d_kept, void* stream);
+
+/*
  * Slicemap atlas of a volume level (Section III, slicemaps of the cited
  * prior work): a 2D image of tiles_y x tiles_x tiles of nx x ny pixels in
  * which atlas pixel (tx*nx + x, ty*ny + y) = L[z][y][x] with

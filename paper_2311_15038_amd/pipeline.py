@@ -43,6 +43,8 @@ class PreviewConfig:
     container_radii: tuple | None = None   # (r_min, r_max); None: [min side / 8, min side / 2]
     container_shift: int = 4        # edges: |g|^2 >= 2^-shift of the largest
     container_margin: int = 2       # kept radius = detected radius - margin
+    hollow: int = 0                 # data preview (Section II): render the shell of this
+                                    # thickness of the rendered level (0: the whole level)
 
 
 def atlas_tiles(nz: int):
@@ -91,6 +93,10 @@ class PreviewPipeline:
             self.circle = torch.zeros(vr.CIRCLE_INTS, dtype=torch.int32, device=dev)
             self.container_work = torch.empty(vr.vr_container_workspace_size(nx, ny, self.radii[1]),
                                               dtype=torch.uint8, device=dev)
+        self.hollow_level = self.hollow_kept = None
+        if cfg.hollow:
+            self.hollow_level = torch.empty((rz, ry, rx), dtype=torch.uint16, device=dev)
+            self.hollow_kept = torch.zeros(1, dtype=torch.int64, device=dev)
         self.render_vol = None
         if cfg.bricked:
             nb, nocc = vr.vr_brick_count(rx, ry, rz)
@@ -135,9 +141,16 @@ class PreviewPipeline:
         self.select(stream)
         self.pyramid(vol, stream)
 
+    def hollow(self, stream=None):
+        vr.vr_hollow(self.levels[self.cfg.render_level - 1], self.cfg.hollow, out=self.hollow_level,
+                     kept=self.hollow_kept, stream=stream)
+
     def render(self, stream=None, count=False):
         c = self.cfg
         src = self.levels[c.render_level - 1]
+        if self.hollow_level is not None:
+            self.hollow(stream)
+            src = self.hollow_level
         if self.render_vol is not None:
             vr.vr_brick_volume(src, out=self.render_vol, stream=stream, pairs=self.cfg.pairs)
             src = self.render_vol
@@ -165,6 +178,9 @@ class PreviewPipeline:
             ("pyramid+atlas", lambda: self.pyramid(vol, stream)),
         ]
         level = self.levels[c.render_level - 1]
+        if self.hollow_level is not None:
+            out.append(("hollow", lambda: self.hollow(stream)))
+            level = self.hollow_level
         src = level
         if self.render_vol is not None:
             out.append(("bricks", lambda: vr.vr_brick_volume(level, out=self.render_vol, stream=stream,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libvr.so")
 NBINS = 65536
 KEEP_WORDS = 2048
 CIRCLE_INTS = 8
+HOLLOW_MAX_THICKNESS = 8
 MAX_LEVELS = 4
 MAX_VIEWS_PER_LAUNCH = 48
 RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
@@ -90,6 +91,7 @@ def lib():
         L.vr_container_workspace_size.argtypes = [i64, i64, i32, C.POINTER(C.c_int64)]
         L.vr_find_container.argtypes = [vp, i64, i64, i32, i32, i32, i32, vp, i64, vp, vp]
         L.vr_remove_container.argtypes = [vp, i64, i64, i64, vp, vp]
+        L.vr_hollow.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp]
         L.vr_histogram_in_disc.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp]
         L.vr_threshold_downsample_in_disc.argtypes = [vp, i64, i64, i64, vp, vp, i32, C.POINTER(vp),
                                                       C.POINTER(vr_atlas_spec), vp]
@@ -118,7 +120,7 @@ def lib():
                      "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
                      "vr_unbrick_volume", "vr_frame_entropy", "vr_entropy_from_counts", "vr_container_workspace_size",
                      "vr_find_container", "vr_remove_container", "vr_histogram_in_disc",
-                     "vr_threshold_downsample_in_disc",
+                     "vr_threshold_downsample_in_disc", "vr_hollow",
                      "vr_brick_count", "vr_histogram_with_top", "vr_batch_workspace_size",
                      "vr_batch_plan_create", "vr_batch_launch", "vr_batch_capture", "vr_batch_status",
                      "vr_batch_item_outputs", "vr_batch_plan_destroy"):
@@ -240,6 +242,21 @@ def vr_remove_container(vol, circle, stream=None):
     _check(lib().vr_remove_container(_dev(vol, "vol", _U16), nx, ny, nz,
                                      _dev(circle, "circle", torch.int32, CIRCLE_INTS), _stream(stream)))
     return vol
+
+
+def vr_hollow(vol, thickness, out=None, kept=None, stream=None):
+    """Hollow data preview: the non-zero voxels within city-block distance
+    `thickness` of a zero voxel or of the volume's outside keep their value,
+    every other voxel is 0.  out: a new tensor unless given (must not overlap
+    vol); kept: None or an int64 tensor of one element, overwritten with the
+    number of kept voxels.  Returns out."""
+    nz, ny, nx = vol.shape
+    if out is None:
+        out = torch.empty_like(vol)
+    kp = None if kept is None else _dev(kept, "kept", torch.int64, 1)
+    _check(lib().vr_hollow(_dev(vol, "vol", _U16), nx, ny, nz, int(thickness),
+                           _dev(out, "out", _U16, nx * ny * nz), kp, _stream(stream)))
+    return out
 
 
 def vr_histogram_in_disc(vol, circle, top_slices=3, hist=None, hist_top=None, stream=None):

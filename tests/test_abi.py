@@ -95,6 +95,12 @@ def test_brick_validation_on_the_host(lib):
     assert lib.vr_brick_volume(p, vr.U16_NORM, 7, 8, 8, 8, p, None, None) == -3
     assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 0, 8, 8, p, None, None) == -2
     assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 8, 8, 8, C.c_void_p(258), None, None) == -3
+    assert lib.vr_hollow(None, 8, 8, 8, 1, p, None, None) == -1
+    assert lib.vr_hollow(p, 8, 0, 8, 1, C.c_void_p(1 << 20), None, None) == -2
+    assert lib.vr_hollow(p, 8, 8, 8, 0, C.c_void_p(1 << 20), None, None) == -3
+    assert lib.vr_hollow(p, 8, 8, 8, vr.HOLLOW_MAX_THICKNESS + 1, C.c_void_p(1 << 20), None, None) == -3
+    assert lib.vr_hollow(p, 8, 8, 8, 2, C.c_void_p(p.value + 1000), None, None) == -3   # overlap
+    assert "overlaps" in lib.vr_last_error().decode()
     assert lib.vr_unbrick_volume(None, vr.F32, 8, 8, 8, p, None) == -1
     assert lib.vr_unbrick_volume(p, 7, 8, 8, 8, p, None) == -4
     assert lib.vr_unbrick_volume(p, vr.U16_NORM, 8, 0, 8, p, None) == -2
