@@ -34,7 +34,9 @@ def _blobs(shape, seed, fill=0.0):
     return a
 
 
-SHAPES = [(21, 37, 70), (8, 8, 32), (17, 9, 33), (5, 3, 7), (1, 1, 1), (2, 40, 3), (40, 1, 65)]
+# x sides that are multiples of 4 take the 8-byte path, the others the voxel path
+SHAPES = [(21, 37, 70), (8, 8, 32), (17, 9, 33), (5, 3, 7), (1, 1, 1), (2, 40, 3), (40, 1, 65),
+          (21, 37, 68), (9, 50, 100), (33, 17, 4), (3, 5, 36)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -74,6 +76,24 @@ def test_degenerate_volumes(name):
         got = vr.vr_hollow(to_dev_u16(a), t, kept=kept)
         assert np.array_equal(u16_np(got), HW.hollow(a, t)), t
         assert int(kept.item()) == HW.kept_count(a, t)
+
+
+@pytest.mark.parametrize("t", [1, 3, 8])
+def test_unaligned_views_take_the_voxel_path(t):
+    """Volumes whose first voxel is not 8-byte aligned (views one voxel into a
+    buffer), with nx a multiple of 4: same result as the oracle."""
+    banner(f"hollow unaligned views t={t}")
+    shape = (13, 21, 44)
+    a = _blobs(shape, 40 + t, fill=0.02)
+    n = int(np.prod(shape))
+    buf = torch.zeros(n + 4, dtype=torch.uint16, device=dev())
+    buf[1:n + 1] = to_dev_u16(a).reshape(-1)
+    src = buf[1:n + 1].view(shape)
+    obuf = torch.zeros(n + 4, dtype=torch.uint16, device=dev())
+    out = obuf[3:n + 3].view(shape)
+    vr.vr_hollow(src, t, out=out)
+    assert np.array_equal(u16_np(out.contiguous()), HW.hollow(a, t))
+    assert not u16_np(obuf[:3]).any() and not u16_np(obuf[n + 3:]).any()     # nothing written outside
 
 
 def test_output_buffer_reuse_and_no_count():
