@@ -64,6 +64,7 @@ hollow_kernel(const uint16_t* __restrict__ src, int nx, int ny, int nz, int tile
 {
     using S = Shape<T>;
     __shared__ uint64_t bg[2][S::ROWS];   // background bits of each staged row (bit j: voxel j), dilated in turn
+    __shared__ uint2 tile[S::TZ][S::TY][kTX / 4];   // the tile's own voxels, 4 to an element
     __shared__ uint32_t wsum[kThreads / 64];
     const int b = tile_of_block((int)blockIdx.x, n_tiles);
     const int tx = b % tiles_x, tyz = b / tiles_x, ty = tyz % tiles_y, tz = tyz / tiles_y;
@@ -99,6 +100,13 @@ hollow_kernel(const uint16_t* __restrict__ src, int nx, int ny, int nz, int tile
             if (!in[i]) zero = (1u << W) - 1u;
             if (zero) atomicOr(reinterpret_cast<unsigned long long*>(&bg[0][row]),
                                (unsigned long long)zero << (g * W));
+            // keep the tile's own voxels for the output
+            const int ry = row % S::RY, rz = row / S::RY, ix = g * W - S::HP;
+            if (ry >= T && ry < T + S::TY && rz >= T && rz < T + S::TZ && ix >= 0 && ix < kTX) {
+                uint16_t* t16 = reinterpret_cast<uint16_t*>(&tile[rz - T][ry - T][0]);
+                if (VEC) tile[rz - T][ry - T][ix >> 2] = w;
+                else t16[ix] = (uint16_t)w.x;
+            }
         }
     }
     __syncthreads();
@@ -122,29 +130,19 @@ hollow_kernel(const uint16_t* __restrict__ src, int nx, int ny, int nz, int tile
         __syncthreads();
     }
     const uint64_t* D = bg[T & 1];
-    // a non-zero voxel is kept when background lies within distance t; the
-    // tile's own voxels are read again (from L2, this workgroup just read them)
+    // a non-zero voxel is kept when background lies within distance t
     uint32_t n_keep = 0;
     constexpr int GO = kTX / W;                       // output groups per tile row
-    constexpr int NO = GO * S::TY * S::TZ, PO = (NO + kThreads - 1) / kThreads;
-    for (int i0 = 0; i0 < PO; i0 += kBatch) {
-        uint2 val[kBatch];
-        bool in[kBatch];
-#pragma unroll
-        for (int i = 0; i < kBatch; ++i) {
-            const int q = (int)threadIdx.x + (i0 + i) * kThreads;
-            const int g = q % GO, r = q / GO, iy = r % S::TY, iz = r / S::TY;
-            val[i] = load_group<VEC>(src, nx, ny, nz, tx * kTX + g * W, y0 + T + iy, z0 + T + iz, in[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < kBatch; ++i) {
-            const int q = (int)threadIdx.x + (i0 + i) * kThreads;
-            if (q >= NO || !in[i]) continue;
-            const int g = q % GO, r = q / GO, iy = r % S::TY, iz = r / S::TY;
+    for (int q = (int)threadIdx.x; q < GO * S::TY * S::TZ; q += kThreads) {
+        const int g = q % GO, r = q / GO, iy = r % S::TY, iz = r / S::TY;
+        const int x = tx * kTX + g * W, y = y0 + T + iy, z = z0 + T + iz;
+        if (x >= nx || y >= ny || z >= nz) continue;
+        {
             const int row = (iz + T) * S::RY + (iy + T);
             const uint32_t near = (uint32_t)(D[row] >> (S::HP + g * W));
-            uint16_t* o = dst + ((int64_t)(z0 + T + iz) * ny + (y0 + T + iy)) * nx + tx * kTX + g * W;
-            const uint2 w = val[i];
+            uint16_t* o = dst + ((int64_t)z * ny + y) * nx + x;
+            const uint2 w = VEC ? tile[iz][iy][g]
+                                : make_uint2(reinterpret_cast<const uint16_t*>(&tile[iz][iy][0])[g], 0u);
             if (VEC) {
                 const uint32_t v0 = w.x & 0xFFFFu, v1 = w.x >> 16, v2 = w.y & 0xFFFFu, v3 = w.y >> 16;
                 const bool k0 = v0 && (near & 1u), k1 = v1 && (near & 2u), k2 = v2 && (near & 4u),
