@@ -47,6 +47,19 @@ RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRA
 RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "brick_dev.h", "common.h", "entropy_dev.h")
 
 
+# The paper's own timings (other hardware, other workloads): context beside
+# this build's threshold-rule and best-view figures, never a target.
+PAPER_FIGURES = {
+    "note": "context only: the paper's timings of its CPU/OBJ implementation, other hardware and data",
+    "otsu_256_bins_ms": {"A": 20.73, "B": 21.23, "C": 20.71, "D": 17.63, "E": 18.65, "mean": 19.79},
+    "its_256_bins_ms": {"A": 0.9269, "B": 0.7093, "C": 0.8231, "D": 0.6433, "E": 0.7626, "mean": 0.773},
+    "threshold_hardware": "MacBook Pro, 64-bit quad-core Intel Core i7 at 2.60 GHz, 16 GB DDR3; "
+                          "8-bit slicemaps of the 512^3 scheme, mean of 10 runs (Section IV-A, Fig. 5)",
+    "best_view_search_s": {"A": 2.10, "B": 3.28, "C": 3.78, "D": 3.40, "E": 3.49, "mean": 3.21},
+    "best_view_hardware": "not stated; Z-axis rotation of OBJ meshes converted from the slices (Section IV, Fig. 6)",
+}
+
+
 def raycast_traffic():
     """The counted traffic of the ray caster, or None once its sources changed."""
     import hashlib
@@ -661,6 +674,7 @@ def main():
                             for k, b in res["kernel_bytes"].items()},
     }
     line["threshold_rules"] = run_thresholds(pipe)
+    line["paper_figures"] = PAPER_FIGURES
     line["hollow"] = run_hollow(pipe)
     bw = run_bandwidth()
     line["measured_bandwidth"] = bw
