@@ -154,8 +154,8 @@ def run_fwd_bwd(pipe, steps=200):
     """The 200-step Adam fit: 16 turntable views at 256^2 of a 256^3 f32 grid
     (spacing 2, step 1 = half its voxel, initialised from the 256^3 level)
     against renders of the 512^3 level.  Reports the time per iteration
-    (forward, adjoint, projected Adam; after two untimed ones) beside the
-    forward alone, and the loss at the first and last steps."""
+    (forward, adjoint, projected Adam in torch's fused form; after two untimed
+    ones) beside the forward alone, and the loss at the first and last steps."""
     import torch
 
     from paper_2311_15038_amd import autograd as VA
@@ -169,7 +169,7 @@ def run_fwd_bwd(pipe, steps=200):
     target = vr.vr_raycast(L1, tf, cams, 256, 256, 0.5)
     dens = (pipe.levels[1].to(torch.float32) / 65535.0).contiguous().requires_grad_(True)
     tfp = tf.clone().requires_grad_(True)
-    opt = torch.optim.Adam([dens, tfp], lr=1e-3)
+    opt = torch.optim.Adam([dens, tfp], lr=1e-3, fused=True)   # one device kernel per step
     losses = torch.zeros(steps, dtype=torch.float32, device=dev)
 
     def it(i):
