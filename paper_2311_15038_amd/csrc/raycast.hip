@@ -111,23 +111,34 @@ __device__ __forceinline__ void flush_tf(float* g, int k, float4 a0, float4 a1)
 // instruction, so their cost follows the number of (instruction, line)
 // pairs.  A lane that holds one cell's eight taps would issue eight
 // instructions whose lanes hit unrelated lines.  Instead the lanes of a wave
-// that flush a cell write its (offset, gradient) pairs to the wave's slice of
-// LDS, and the active lanes then take consecutive entries: the taps of one
-// cell (x pairs adjacent in memory) and of the neighbouring rays' cells go out
-// in the same instruction and share lines.
+// that flush a cell write its non-zero (offset, gradient) pairs, packed, to
+// the wave's slice of LDS, and the active lanes then take consecutive
+// entries: the taps of one cell (x pairs adjacent in memory) and of the
+// neighbouring rays' cells go out in the same instruction and share lines.
 constexpr int kFlushSlots = 64 * 8;   // entries per wave: every lane flushing one cell
 
 __device__ __forceinline__ void wave_flush(bool f, const uint32_t (&off)[8], const float (&gc)[8],
                                            float* __restrict__ gvol, uint2* __restrict__ buf)
 {
-    const uint64_t m = __ballot(f);
-    if (m == 0) return;
+    if (__ballot(f) == 0) return;
     const uint32_t lane = __lane_id();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
-    if (f) {
-        const int r = __popcll(m & below);
+    // the lane's non-zero entries, packed after those of the lanes below it
+    int c = 0;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) buf[8 * r + t] = make_uint2(off[t], __float_as_uint(gc[t]));
+    for (int t = 0; t < 8; ++t) c += (f && gc[t] != 0.0f) ? 1 : 0;
+    int first = 0, n = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+        const uint64_t m = __ballot((c >> bit) & 1);
+        first += __popcll(m & below) << bit;
+        n += __popcll(m) << bit;
+    }
+    if (f) {
+        int q = first;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (gc[t] != 0.0f) buf[q++] = make_uint2(off[t], __float_as_uint(gc[t]));
     }
     // the wave's own LDS writes above are complete before any lane reads them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -135,13 +146,11 @@ __device__ __forceinline__ void wave_flush(bool f, const uint32_t (&off)[8], con
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint64_t act = __ballot(true);
     const int n_act = __popcll(act), me = __popcll(act & below);
-    const int n = 8 * __popcll(m);
     for (int base = 0; base < n; base += n_act) {
         const int q = base + me;
         if (q < n) {
             const uint2 e = buf[q];
-            const float v = __uint_as_float(e.y);
-            if (v != 0.0f) atomicAdd(gvol + e.x, v);
+            atomicAdd(gvol + e.x, __uint_as_float(e.y));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -270,14 +279,33 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                                    (kb.w - ka.w) * G.w);
                 }
                 // consecutive samples of one cell add to the same eight taps: their
-                // gradients are summed in registers and scattered once per cell
+                // gradients are summed in registers.  When the ray moves on, the taps
+                // the new cell shares with the pending one keep their sums (each old
+                // tap goes to the first new tap with its offset) and only the others
+                // are scattered.
                 const bool change = ds != 0.0f && (sm.off[0] != cell_off[0] || sm.off[7] != cell_off[7]);
+                float carry[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) carry[t] = 0.0f;
+                if (change) {
+#pragma unroll
+                    for (int a = 0; a < 8; ++a) {
+                        bool moved = false;
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+                            const bool hit = !moved && cell_off[a] == sm.off[t];
+                            carry[t] += hit ? cell_g[a] : 0.0f;
+                            moved = moved || hit;
+                        }
+                        if (moved) cell_g[a] = 0.0f;
+                    }
+                }
                 wave_flush(change && cell_off[0] != 0xFFFFFFFFu, cell_off, cell_g, gvol, fbuf);
                 if (change) {
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
                         cell_off[t] = sm.off[t];
-                        cell_g[t] = 0.0f;
+                        cell_g[t] = carry[t];
                     }
                 }
                 if (ds != 0.0f) {
