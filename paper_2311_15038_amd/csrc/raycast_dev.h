@@ -80,6 +80,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * q + min(x, r) + i;
 }
 
+// Pixel (i, j) and view of this thread in a launch of 16 x 16-pixel ray tiles
+// (256 threads: four 8 x 8 waves), nb workgroups in all, XCD-aware order.
+__device__ __forceinline__ void tile_pixel(const Scene& S, int nb, int& view, int& i, int& j)
+{
+    const int b = xcd_remap((int)blockIdx.x, nb);
+    const int per_view = S.tiles_x * S.tiles_y;
+    view = b / per_view;
+    const int t = b - view * per_view;
+    const int tx = t % S.tiles_x, ty = t / S.tiles_x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    i = tx * kTile + (w & 1) * 8 + (lane & 7);
+    j = ty * kTile + (w >> 1) * 8 + (lane >> 3);
+}
+
 // Everything one sample needs: the eight tap offsets, the trilinear weights
 // and the interpolated (normalised) density.
 struct Sample {
