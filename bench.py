@@ -660,7 +660,10 @@ def main():
                      "algorithmic_bytes": res["raycast_alg_bytes"],
                      "kernel": "raycast_fwd<u16,brick4>", "flops_per_sample": FLOPS_PER_SAMPLE,
                      "samples": "evaluated",
-                     "kernel_ms": rc_ms},
+                     "kernel_ms": rc_ms,
+                     "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
+                                 "TD_busy": 0.83, "TA_busy": 0.59, "VALU_busy": 0.66,
+                                 "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "raycast_Gsamples_per_s": samples / (rc_ms * 1e-3) / 1e9,
         "raycast_evaluated_Gsamples_per_s": evaluated / (rc_ms * 1e-3) / 1e9,
         "samples_per_step": samples,
