@@ -1,4 +1,6 @@
 // Render layout of a volume level (layout and occupancy described in brick_dev.h).
+#include <type_traits>
+
 #include "brick_dev.h"
 
 namespace {
@@ -92,20 +94,27 @@ namespace {
 
 // Inverse of the brick layout: thread (x4, y, z) copies the 4-voxel row of
 // brick (x4, y >> 2, z >> 2) at in-brick row (y & 3, z & 3) to voxels
-// [4 x4, 4 x4 + 4) of row (y, z) of the linear volume, clipped at nx.
-template <typename T>
+// [4 x4, 4 x4 + 4) of row (y, z) of the linear volume, clipped at nx.  VEC:
+// nx is a multiple of 4 and dst is aligned to a whole row of four, so each
+// row moves as one vector (brick rows are always aligned).
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(kThreads)
 unbrick_kernel(const T* __restrict__ src, int64_t nx, int64_t ny, int64_t nz, int64_t nbx, int64_t nby,
                T* __restrict__ dst)
 {
+    using V = typename std::conditional<sizeof(T) == 2, uint2, float4>::type;   // four voxels
     const int64_t rows = nbx * ny * nz;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < rows; t += (int64_t)gridDim.x * kThreads) {
         const int64_t bx = t % nbx, yz = t / nbx, y = yz % ny, z = yz / ny;
         const int64_t b = ((z >> 2) * nby + (y >> 2)) * nbx + bx;
         const T* row = src + b * 64 + ((z & 3) << 4) + ((y & 3) << 2);
         T* out = dst + (z * ny + y) * nx + bx * 4;
-        const int64_t m = nx - bx * 4 < 4 ? nx - bx * 4 : 4;
-        for (int64_t q = 0; q < m; ++q) out[q] = row[q];
+        if (VEC) {
+            *reinterpret_cast<V*>(out) = *reinterpret_cast<const V*>(row);
+        } else {
+            const int64_t m = nx - bx * 4 < 4 ? nx - bx * 4 : 4;
+            for (int64_t q = 0; q < m; ++q) out[q] = row[q];
+        }
     }
 }
 
@@ -126,11 +135,20 @@ extern "C" int vr_unbrick_volume(const void* d_bricked, int dtype, int64_t nx, i
     hipStream_t s = vr::as_stream(stream);
     const int64_t g = std::max<int64_t>(1, std::min<int64_t>((int64_t)vr::num_cus() * 16,
                                                              vr::ceil_div<int64_t>(rows, kThreads)));
-    if (dtype == VR_U16_NORM)
-        unbrick_kernel<uint16_t><<<(unsigned)g, kThreads, 0, s>>>(static_cast<const uint16_t*>(d_bricked), nx, ny,
-                                                                  nz, nbx, nby, static_cast<uint16_t*>(d_dst));
-    else
-        unbrick_kernel<float><<<(unsigned)g, kThreads, 0, s>>>(static_cast<const float*>(d_bricked), nx, ny, nz,
-                                                               nbx, nby, static_cast<float*>(d_dst));
+    const int64_t esz = dtype == VR_U16_NORM ? 2 : 4;
+    const bool vec = nx % 4 == 0 && (reinterpret_cast<uintptr_t>(d_dst) % (4 * esz)) == 0 &&
+                     (reinterpret_cast<uintptr_t>(d_bricked) % (4 * esz)) == 0;
+    const auto* su = static_cast<const uint16_t*>(d_bricked);
+    const auto* sf = static_cast<const float*>(d_bricked);
+    auto* du = static_cast<uint16_t*>(d_dst);
+    auto* df = static_cast<float*>(d_dst);
+    const unsigned gb = (unsigned)g;
+    if (dtype == VR_U16_NORM) {
+        if (vec) unbrick_kernel<uint16_t, true><<<gb, kThreads, 0, s>>>(su, nx, ny, nz, nbx, nby, du);
+        else unbrick_kernel<uint16_t, false><<<gb, kThreads, 0, s>>>(su, nx, ny, nz, nbx, nby, du);
+    } else {
+        if (vec) unbrick_kernel<float, true><<<gb, kThreads, 0, s>>>(sf, nx, ny, nz, nbx, nby, df);
+        else unbrick_kernel<float, false><<<gb, kThreads, 0, s>>>(sf, nx, ny, nz, nbx, nby, df);
+    }
     return vr::check_launch("vr_unbrick_volume");
 }

@@ -238,7 +238,8 @@ def test_skipping_adjoint_matches_fp64_autograd():
     assert np.abs(gt - gt_ref).max() <= 2e-3 * st, np.abs(gt - gt_ref).max() / st
 
 
-@pytest.mark.parametrize("shape", [(5, 7, 9), (27, 30, 33), (4, 4, 4), (1, 1, 1)])
+# x sides that are multiples of 4 move whole rows as vectors, the others voxel by voxel
+@pytest.mark.parametrize("shape", [(5, 7, 9), (27, 30, 33), (4, 4, 4), (1, 1, 1), (6, 10, 12), (9, 13, 44)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.uint16])
 def test_unbrick_inverts_brick(shape, dtype):
     banner(f"backward: unbrick round trip {shape} {dtype}")
