@@ -26,10 +26,10 @@ __device__ __forceinline__ void flush_tf(float* g, int k, float4 a0, float4 a1)
     atomicAdd(g + 4 * k + 7, a1.w);
 }
 
-// Density-gradient atomics go to the memory side of the fabric (the XCDs' L2s
-// are not coherent with each other), one request per cache line and
-// instruction, so their cost follows the number of (instruction, line)
-// pairs.  A lane that holds one cell's eight taps would issue eight
+// Density-gradient atomics are performed at the memory side of the fabric (on
+// this device every one of them shows in the memory-side atomic count), one
+// request per cache line and instruction, so their cost follows the number
+// of (instruction, line) pairs.  A lane that holds one cell's eight taps would issue eight
 // instructions whose lanes hit unrelated lines.  Instead the lanes of a wave
 // that flush a cell write its non-zero (offset, gradient) pairs, packed, to
 // the wave's slice of LDS, and the active lanes then take consecutive
