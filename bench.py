@@ -434,6 +434,18 @@ def run_batched(n_volumes=64, n_views=12, res=256):
             p.step(v)
 
     plain_ms = _median_ms(plain)
+    # the plain path's device time per library call, summed over the 64 volumes
+    by_call, marks = {}, []
+    for v, p in zip(vols, pipes):
+        for name, fn in p.calls(v):
+            e = _events(2)
+            e[0].record()
+            fn()
+            e[1].record()
+            marks.append((name, e))
+    torch.cuda.synchronize()
+    for name, e in marks:
+        by_call[name] = by_call.get(name, 0.0) + e[0].elapsed_time(e[1])
     del pipes, vols
     torch.cuda.empty_cache()
     return {"volumes": n_volumes, "voxels": voxels, "views_per_volume": n_views, "image": [res, res],
@@ -441,7 +453,7 @@ def run_batched(n_volumes=64, n_views=12, res=256):
             "samples": taken, "evaluated": evald,
             "batched_Gsamples_per_s": taken / (batched_ms * 1e-3) / 1e9,
             "plain_Gsamples_per_s": taken / (plain_ms * 1e-3) / 1e9,
-            "tuning": best, "status": max(st, st2)}
+            "plain_ms_by_call": by_call, "tuning": best, "status": max(st, st2)}
 
 
 def run_served(seconds=20.0, warmup_s=5.0, rate=50.0, slots=4, budget_gib=64.0, burst=200):
@@ -586,6 +598,8 @@ def main():
                     help="only the container-removal leg (for kernel profiles)")
     ap.add_argument("--fit-only", action="store_true",
                     help="only the 200-step fit leg (for kernel profiles)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched leg (for kernel profiles)")
     ap.add_argument("--hollow-only", action="store_true",
                     help="only the hollow data-preview leg (for kernel profiles)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -608,6 +622,9 @@ def main():
         return
     if args.container_only:
         print(json.dumps({"container": run_container(args.steps)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": run_batched()}), flush=True)
         return
     if args.hollow_only:
         from paper_2311_15038_amd import pipeline as P
