@@ -11,6 +11,10 @@
 //   DOWN   fused threshold + level-1 tiles                 (after SEL3)
 //   BRICK  level 1 to the brick layout + occupancy         (after all DOWN)
 //   RENDER one ray tile of one view                        (after all BRICK)
+// RENDER tiles are not run as workgroup tasks: once the queue of the other
+// tasks is empty, each wave takes wave-sized pieces of them (16 per tile) from
+// a render queue of its own and waits, alone, for its item's bricks.  A
+// workgroup barrier per tile would hold 16 waves for the slowest ray.
 // A task waits (thread 0 spins with agent-scope acquire loads) until the
 // counters of the phase it depends on reach their totals; a finished task
 // bumps its phase counter with a release.  Tasks are claimed in table order
@@ -71,6 +75,9 @@ struct BatchDev {
     uint32_t* head;          // queue position
     uint32_t* finished;      // workgroups done
     uint32_t* status;        // non-zero after a spin time-out
+    uint32_t* render_head;   // render queue position (in wave pieces)
+    int64_t n_pre;           // tasks before the render phase (the workgroup queue)
+    int64_t n_render_waves;  // render pieces: 16 waves per render tile
     unsigned long long* samples;   // [2] samples taken / evaluated (accumulated)
     const float4* tf;
     int n_items;
@@ -205,15 +212,49 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
         signal(cnt + C_BRICK);
         break;
     }
-    case T_RENDER: {
-        // a = view, b = tile index
-        wait_ge(B, cnt + C_BRICK, it.need[C_BRICK]);
-        vr::rc::stage_tf(L.tf, B.tf, tid, kT);
-        __syncthreads();
+    default:
+        break;
+    }
+}
+
+// wait_ge for one wave: every lane reads the counter with acquire (no barrier)
+__device__ inline void wave_wait_ge(const BatchDev& B, const uint32_t* c, uint32_t need)
+{
+    uint64_t spins = 0;
+    for (;;) {
+        const uint32_t v = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        if (v >= need) break;
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > kSpinLimit) {
+            if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_or(B.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+    }
+}
+
+// The render phase, one wave at a time: piece r is wave r % 16 of render tile
+// r / 16 (the render tasks at the end of the table), pieces of one tile being
+// consecutive so that neighbouring waves render neighbouring pixels.
+__device__ void render_waves(const BatchDev& B, const BatchLds& L)
+{
+    const int lane = threadIdx.x & 63;
+    const int tile_w = B.wave_w * B.waves_x, tile_h = B.wave_h * (16 / B.waves_x);
+    int ready = -1;   // item whose bricks this wave has seen complete
+    for (;;) {
+        uint32_t r = 0;
+        if (lane == 0) r = __hip_atomic_fetch_add(B.render_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        r = __builtin_amdgcn_readfirstlane(r);
+        if ((int64_t)r >= B.n_render_waves) break;
+        const Task t = B.tasks[B.n_pre + r / 16];
+        const int w = (int)(r % 16);
+        const ItemDev& it = B.items[t.item];
+        if (t.item != ready) {
+            wave_wait_ge(B, B.counters + (int64_t)t.item * C_COUNT + C_BRICK, it.need[C_BRICK]);
+            ready = t.item;
+        }
         const vr::rc::Scene& S = it.S;
         const bool skip = vr::rc::can_skip(S, L.tf);
-        const int w = tid >> 6, lane = tid & 63;
-        const int tile_w = B.wave_w * B.waves_x, tile_h = B.wave_h * (16 / B.waves_x);
         const int tx = (int)(t.b % B.tiles_per_row), ty = (int)(t.b / B.tiles_per_row);
         const int i = tx * tile_w + (w % B.waves_x) * B.wave_w + lane % B.wave_w;
         const int j = ty * tile_h + (w / B.waves_x) * B.wave_h + lane / B.wave_w;
@@ -233,11 +274,6 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
             if (lane == 0 && c) atomicAdd(B.samples, c);
             if (lane == 0 && e) atomicAdd(B.samples + 1, e);
         }
-        __syncthreads();
-        break;
-    }
-    default:
-        break;
     }
 }
 
@@ -250,7 +286,7 @@ __global__ void __launch_bounds__(kT) batch_kernel(const BatchDev B)
     __syncthreads();
     for (;;) {
         const int64_t cur = s_task[0];
-        if (cur >= B.n_tasks) break;
+        if (cur >= B.n_pre) break;
         // claim the next task now, so its queue latency overlaps this one
         if (threadIdx.x == 0)
             s_task[1] = __hip_atomic_fetch_add(B.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -260,13 +296,21 @@ __global__ void __launch_bounds__(kT) batch_kernel(const BatchDev B)
         if (threadIdx.x == 0) s_task[0] = s_task[1];
         __syncthreads();
     }
-    // the last workgroup out resets the queue for the next launch
+    // every other task is claimed: render, one wave at a time (the TF is staged once)
+    if (B.n_render_waves > 0) {
+        vr::rc::stage_tf(L.tf, B.tf, (int)threadIdx.x, kT);
+        __syncthreads();
+        render_waves(B, L);
+    }
+    __syncthreads();
+    // the last workgroup out resets the queues for the next launch
     if (threadIdx.x == 0) {
         __threadfence();
         const uint32_t done = __hip_atomic_fetch_add(B.finished, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (done == gridDim.x - 1) {
             for (int64_t i = 0; i < (int64_t)B.n_items * C_COUNT; ++i) B.counters[i] = 0;
             *B.head = 0;
+            *B.render_head = 0;
             __threadfence();
             __hip_atomic_store(B.finished, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -431,9 +475,13 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
     if (cfg->rule == VR_RULE_NONE)
         for (auto& it : P->items) it.need[C_SEL2] = 0, it.need[C_SEL1] = 0;
     for (auto& ph : phase) tasks->insert(tasks->end(), ph.begin(), ph.end());
+    const int64_t n_render = (int64_t)phase[T_RENDER].size();
+    VR_REQUIRE(16 * n_render < (int64_t(1) << 31), VR_ERR_DIMS, "vr_batch: too many render tiles");
 
     BatchDev& B = P->dev;
     B.n_tasks = (int64_t)tasks->size();
+    B.n_pre = B.n_tasks - n_render;
+    B.n_render_waves = 16 * n_render;
     B.n_items = n_items;
     B.rule = cfg->rule;
     B.rule_param = cfg->rule_param;
@@ -448,6 +496,7 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
     B.head = B.counters ? B.counters + C_COUNT * n_items : nullptr;
     B.finished = B.head ? B.head + 1 : nullptr;
     B.status = B.head ? B.head + 2 : nullptr;
+    B.render_head = B.head ? B.head + 3 : nullptr;
     B.samples = static_cast<unsigned long long*>(C.take(16));
     return VR_OK;
 }
