@@ -342,9 +342,21 @@ def run_small(reps=20, warm=3):
         tot[2 * r + 1].record()
     torch.cuda.synchronize()
     med = lambda e: sorted(e[2 * r].elapsed_time(e[2 * r + 1]) for r in range(reps))[reps // 2] * 1e3  # noqa: E731
+    # the same step captured once in a HIP graph and replayed (no host work per launch)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pipe.step(vol)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pipe.step(vol)
+    torch.cuda.synchronize()
+    graph_us = _median_ms(graph.replay, reps) * 1e3
     return {"workload": "128^3 u16 (seed 2311): histograms, valley, 64^3 level + 512^2 slicemap, "
                         "one orthographic 256^2 view at step 0.5, best view",
             "us_per_call": {name: med(e) for name, e in ev.items()}, "us_per_step": med(tot),
+            "graph_us_per_step": graph_us,
             "threshold": int(pipe.result[0].item()), "reps": reps}
 
 
