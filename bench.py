@@ -159,6 +159,7 @@ def run_fwd_bwd(pipe, steps=200):
     import torch
 
     from paper_2311_15038_amd import autograd as VA
+    from paper_2311_15038_amd import fit as VF
     from paper_2311_15038_amd import synth, vr
 
     dev = pipe.device
@@ -167,21 +168,14 @@ def run_fwd_bwd(pipe, steps=200):
     cams = synth.turntable_cameras(rx, ry, rz, n_views=16)
     tf = pipe.tf
     target = vr.vr_raycast(L1, tf, cams, 256, 256, 0.5)
-    dens = (pipe.levels[1].to(torch.float32) / 65535.0).contiguous().requires_grad_(True)
-    tfp = tf.clone().requires_grad_(True)
-    opt = torch.optim.Adam([dens, tfp], lr=1e-3, fused=True)   # one device kernel per step
+    # projected Adam (densities in [0, 1], TF non-negative), torch's fused kernel
+    f = VF.PreviewFit(pipe.levels[1].to(torch.float32) / 65535.0, tf, cams, 256, 256, 1.0, target,
+                      spacing=(2.0, 2.0, 2.0), lr=1e-3)
+    dens, tfp = f.density, f.tf
     losses = torch.zeros(steps, dtype=torch.float32, device=dev)
 
     def it(i):
-        opt.zero_grad(set_to_none=False)
-        img = VA.render(dens, tfp, cams, 256, 256, 1.0, (2.0, 2.0, 2.0))
-        loss = ((img - target) ** 2).mean()
-        loss.backward()
-        opt.step()
-        with torch.no_grad():                 # projected: densities in [0, 1], TF non-negative
-            dens.clamp_(0.0, 1.0)
-            tfp.clamp_(min=0.0)
-        losses[i] = loss.detach()
+        losses[i] = f.step()
 
     for i in range(2):
         it(i)

@@ -269,3 +269,37 @@ def test_torch_twin_gradient_matches_finite_differences():
         fm[k, c] -= h
         fd = (L(d, fp) - L(d, fm)) / (2 * h)
         assert abs(fd - tt.grad[k, c].item()) < 1e-6 * max(1.0, abs(fd)) + 1e-9
+
+
+def test_torch_twin_gradient_analytic_single_material():
+    """A box of constant density s seen along +y, a TF of constant colour and
+    sigma(s) = c s: the pixel is Beer-Lambert, I = rgb (1 - e) + bg e with
+    e = exp(-c s L), whatever the sampling.  Closed-form gradients: the summed
+    density gradient is dI/ds = (rgb - bg) c L e; the two TF knots around s
+    carry (1 - w) and w of dI/dsigma = (rgb - bg) L e (w = 255 s - k), the
+    colour knots (1 - w) and w of dI/drgb = 1 - e."""
+    nx, ny, nz = 4, 6, 5
+    s0, c = 0.3, 0.9
+    rgb = np.array([0.7, 0.2, 0.4])
+    L = float(ny)
+    dens = torch.full((nz, ny, nx), s0, dtype=torch.float64, requires_grad=True)
+    tf = torch.tensor(_linear_tf(rgb, c), dtype=torch.float64, requires_grad=True)
+    cam = synth.front_ortho_camera(nx, ny, nz)
+    img = RT.render(dens, tf, cam, 9, 7, 0.35, bg=BG)
+    hit = (img[0] - torch.tensor(BG, dtype=torch.float64)).abs().amax(dim=-1) > 0
+    pix = hit.nonzero()[len(hit.nonzero()) // 2]
+    I = img[0, pix[0], pix[1], 0]                  # red channel of one hitting pixel
+    I.backward()
+    e = math.exp(-c * s0 * L)
+    assert abs(I.item() - (rgb[0] * (1 - e) + BG[0] * e)) < 1e-13
+    assert abs(dens.grad.sum().item() - (rgb[0] - BG[0]) * c * L * e) < 1e-12
+    k = int(255 * s0)
+    w = 255 * s0 - k
+    g_sigma = (rgb[0] - BG[0]) * L * e
+    assert abs(tf.grad[k, 3].item() - (1 - w) * g_sigma) < 1e-12
+    assert abs(tf.grad[k + 1, 3].item() - w * g_sigma) < 1e-12
+    assert abs(tf.grad[k, 0].item() - (1 - w) * (1 - e)) < 1e-12
+    assert abs(tf.grad[k + 1, 0].item() - w * (1 - e)) < 1e-12
+    others = torch.ones(256, dtype=torch.bool)
+    others[k] = others[k + 1] = False
+    assert tf.grad[others].abs().max().item() == 0.0
