@@ -40,8 +40,8 @@ METRIC = "Gsamples/s ray casting + GB/s reduction vs HBM peak; fwd+bwd, batched 
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
 # 524308 KiB for it (scale 2.000), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 1564628, "write_kib": 150920, "fetch_scale": 1048576 / 524308,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "ed6350bae503db7d"}
+RAYCAST_TRAFFIC = {"fetch_kib": 2227273, "write_kib": 156652, "fetch_scale": 1048576 / 524308,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "2e2d31423c1d0cb2"}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
 RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "brick_dev.h", "common.h", "entropy_dev.h")
@@ -685,7 +685,7 @@ def main():
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
-                                 "TD_busy": 0.83, "TA_busy": 0.59, "VALU_busy": 0.66,
+                                 "TD_busy": 0.85, "TA_busy": 0.65, "VALU_busy": 0.80,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "raycast_Gsamples_per_s": samples / (rc_ms * 1e-3) / 1e9,
         "raycast_evaluated_Gsamples_per_s": evaluated / (rc_ms * 1e-3) / 1e9,

@@ -96,7 +96,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
     const bool skipping = S.occ != nullptr && tf_s[0].w == 0.0f && tf_s[1].w == 0.0f && isfinite(tf_s[0].x) &&
                           isfinite(tf_s[0].y) && isfinite(tf_s[0].z);
     int view, i, j;
-    tile_pixel(S, (int)gridDim.x, view, i, j);
+    tile_pixel<16, 16>(S, (int)gridDim.x, view, i, j);   // four 8 x 8 waves
     const float* vol = static_cast<const float*>(S.data);
     uint32_t cell_off[8];        // taps of the cell whose density gradient is pending
     float cell_g[8];
@@ -263,6 +263,7 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
     Scene S{};
     int rc = build_scene(vol, d_tf, h_cams, n_views, opts, S);
     if (rc) return rc;
+    set_tiles<16, 16>(S);
     VR_REQUIRE(vol->dtype == VR_F32, VR_ERR_DTYPE, "vr_raycast_backward: density must be VR_F32");
     VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4, VR_ERR_UNSUPPORTED,
                "vr_raycast_backward: the density gradient is produced for the linear and brick layouts only");

@@ -16,7 +16,6 @@ namespace vr {
 namespace rc {
 
 constexpr int kMaxViews = VR_MAX_VIEWS_PER_LAUNCH;
-constexpr int kTile = 16;      // pixels per side of a standalone ray tile
 
 struct View {
     float eye[3];   // perspective origin, or centre of the orthographic view
@@ -58,20 +57,15 @@ struct Scene {
 // never passed over.
 constexpr float kSkipMarginVox = 1.0f / 128.0f;
 
-// Transfer function staged in LDS: the knots and the difference to the next
-// knot, so a lookup is one fma per channel (the same value as lerpf).
+// Transfer function staged in LDS: the 256 knots (4 KiB, so that LDS does not
+// bound the occupancy of one-wave workgroups).
 struct TfLds {
     float4 a[256];
-    float4 d[256];
 };
 
 __device__ __forceinline__ void stage_tf(TfLds& t, const float4* __restrict__ tf, int tid, int nthreads)
 {
-    for (int q = tid; q < 256; q += nthreads) {
-        const float4 a = tf[q], b = tf[q < 255 ? q + 1 : 255];
-        t.a[q] = a;
-        t.d[q] = make_float4(b.x - a.x, b.y - a.y, b.z - a.z, b.w - a.w);
-    }
+    for (int q = tid; q < 256; q += nthreads) t.a[q] = tf[q];
 }
 
 __device__ __forceinline__ int xcd_remap(int b, int nb)
@@ -80,8 +74,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * q + min(x, r) + i;
 }
 
-// Pixel (i, j) and view of this thread in a launch of 16 x 16-pixel ray tiles
-// (256 threads: four 8 x 8 waves), nb workgroups in all, XCD-aware order.
+// Ray tiles of TW x TH pixels, one workgroup each, made of 8 x 8-pixel waves
+// (TW / 8 across, TH / 8 down): the tile counts of an image.
+template <int TW, int TH>
+inline void set_tiles(Scene& S)
+{
+    static_assert(TW % 8 == 0 && TH % 8 == 0, "a tile is whole 8 x 8 waves");
+    S.tiles_x = (S.W + TW - 1) / TW;
+    S.tiles_y = (S.H + TH - 1) / TH;
+}
+
+// Pixel (i, j) and view of this thread in a launch of TW x TH-pixel ray tiles,
+// nb workgroups in all, in XCD-aware order: the tiles of one view that run
+// at the same time cast neighbouring rays on one XCD.
+template <int TW, int TH>
 __device__ __forceinline__ void tile_pixel(const Scene& S, int nb, int& view, int& i, int& j)
 {
     const int b = xcd_remap((int)blockIdx.x, nb);
@@ -90,8 +96,8 @@ __device__ __forceinline__ void tile_pixel(const Scene& S, int nb, int& view, in
     const int t = b - view * per_view;
     const int tx = t % S.tiles_x, ty = t / S.tiles_x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    i = tx * kTile + (w & 1) * 8 + (lane & 7);
-    j = ty * kTile + (w >> 1) * 8 + (lane >> 3);
+    i = tx * TW + (w % (TW / 8)) * 8 + (lane & 7);
+    j = ty * TH + (w / (TW / 8)) * 8 + (lane >> 3);
 }
 
 // Everything one sample needs: the eight tap offsets, the trilinear weights
@@ -199,8 +205,8 @@ __device__ __forceinline__ TfHit tf_lookup(const TfLds& t, float s)
     const float x = fminf(fmaxf(s, 0.0f), 1.0f) * 255.0f;
     h.k = min((int)x, 254);
     h.w = x - (float)h.k;
-    const float4 a = t.a[h.k], d = t.d[h.k];
-    h.q = make_float4(fmaf(h.w, d.x, a.x), fmaf(h.w, d.y, a.y), fmaf(h.w, d.z, a.z), fmaf(h.w, d.w, a.w));
+    const float4 a = t.a[h.k], b = t.a[h.k + 1];
+    h.q = make_float4(lerpf(a.x, b.x, h.w), lerpf(a.y, b.y, h.w), lerpf(a.z, b.z, h.w), lerpf(a.w, b.w, h.w));
     return h;
 }
 
@@ -581,8 +587,6 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
     S.step = o->step;
     S.eps = o->ert_eps;
     for (int c = 0; c < 4; ++c) S.bg[c] = o->bg[c];
-    S.tiles_x = (o->width + kTile - 1) / kTile;
-    S.tiles_y = (o->height + kTile - 1) / kTile;
     return VR_OK;
 }
 
