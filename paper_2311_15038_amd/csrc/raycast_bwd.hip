@@ -12,7 +12,10 @@ namespace {
 
 using namespace vr::rc;
 
-constexpr int kThreads = 256;
+// One wave per workgroup (an 8 x 8-pixel tile), as in the forward: a
+// workgroup's slot frees only when its last ray ends.  Registers (over 100 per
+// lane) allow four waves per SIMD, the 12 KiB of LDS thirteen workgroups per CU.
+constexpr int kThreads = 64;
 
 __device__ __forceinline__ void flush_tf(float* g, int k, float4 a0, float4 a1)
 {
@@ -88,7 +91,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
     __shared__ float gtf_s[256 * 4];
     __shared__ uint2 flush_s[kThreads / 64][kFlushSlots];
     uint2* const fbuf = flush_s[threadIdx.x >> 6];
-    tf_s[threadIdx.x] = tf[threadIdx.x];
+    for (int q = threadIdx.x; q < 256; q += kThreads) tf_s[q] = tf[q];
     for (int q = threadIdx.x; q < 1024; q += kThreads) gtf_s[q] = 0.0f;
     __syncthreads();
     // empty bricks may be passed over when the first TF segment has zero extinction
@@ -96,7 +99,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
     const bool skipping = S.occ != nullptr && tf_s[0].w == 0.0f && tf_s[1].w == 0.0f && isfinite(tf_s[0].x) &&
                           isfinite(tf_s[0].y) && isfinite(tf_s[0].z);
     int view, i, j;
-    tile_pixel<16, 16>(S, (int)gridDim.x, view, i, j);   // four 8 x 8 waves
+    tile_pixel<8, 8>(S, (int)gridDim.x, view, i, j);
     const float* vol = static_cast<const float*>(S.data);
     uint32_t cell_off[8];        // taps of the cell whose density gradient is pending
     float cell_g[8];
@@ -263,7 +266,7 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
     Scene S{};
     int rc = build_scene(vol, d_tf, h_cams, n_views, opts, S);
     if (rc) return rc;
-    set_tiles<16, 16>(S);
+    set_tiles<8, 8>(S);
     VR_REQUIRE(vol->dtype == VR_F32, VR_ERR_DTYPE, "vr_raycast_backward: density must be VR_F32");
     VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4, VR_ERR_UNSUPPORTED,
                "vr_raycast_backward: the density gradient is produced for the linear and brick layouts only");
