@@ -38,10 +38,10 @@ METRIC = "Gsamples/s ray casting + GB/s reduction vs HBM peak; fwd+bwd, batched 
 # FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of
 # --traffic-probe, each scaled by what the same counter reads for a kernel of
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
-# 524308 KiB for it (scale 2.000), WRITE_SIZE 1048576 KiB (scale 1.000).
+# 524307 KiB for it (scale 2.000), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 2227273, "write_kib": 156652, "fetch_scale": 1048576 / 524308,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "2e2d31423c1d0cb2"}
+RAYCAST_TRAFFIC = {"fetch_kib": 2249506, "write_kib": 156652, "fetch_scale": 1048576 / 524307,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "733e972dd5099254"}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
 RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "brick_dev.h", "common.h", "entropy_dev.h")

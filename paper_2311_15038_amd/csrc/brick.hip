@@ -13,24 +13,30 @@ __global__ void __launch_bounds__(kThreads) fill_u8(uint8_t* __restrict__ p, int
         p[i] = 0;
 }
 
-template <typename T, bool PAIRS>
+template <typename T, bool PAIRS, bool VEC>
 __global__ void __launch_bounds__(kThreads)
 brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
              typename ElemOf<T, PAIRS>::type* __restrict__ dst, uint8_t* __restrict__ occ,
              uint8_t* __restrict__ macro, int nmx, int nmy)
 {
     __shared__ SlabLds<T, PAIRS> G;
-    slab_body<T, PAIRS>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, blockIdx.x * 16, blockIdx.y,
+    slab_body<T, PAIRS, VEC>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, blockIdx.x * 16, blockIdx.y,
                         blockIdx.z, true, threadIdx.x, G);
 }
 
+// Rows load four voxels at a time when nx is a multiple of 4 and src is
+// aligned to four voxels.
 template <typename T, bool PAIRS>
 void launch_brick(dim3 grid, hipStream_t s, const void* src, int nx, int ny, int nz, int nbx, int nby,
                   void* dst, uint8_t* occ, uint8_t* macro, int nmx, int nmy)
 {
-    brick_kernel<T, PAIRS><<<grid, kThreads, 0, s>>>(
-        static_cast<const T*>(src), nx, ny, nz, nbx, nby,
-        static_cast<typename ElemOf<T, PAIRS>::type*>(dst), occ, macro, nmx, nmy);
+    const bool vec = nx % 4 == 0 && reinterpret_cast<uintptr_t>(src) % (4 * sizeof(T)) == 0;
+    const auto* sp = static_cast<const T*>(src);
+    auto* dp = static_cast<typename ElemOf<T, PAIRS>::type*>(dst);
+    if (vec)
+        brick_kernel<T, PAIRS, true><<<grid, kThreads, 0, s>>>(sp, nx, ny, nz, nbx, nby, dp, occ, macro, nmx, nmy);
+    else
+        brick_kernel<T, PAIRS, false><<<grid, kThreads, 0, s>>>(sp, nx, ny, nz, nbx, nby, dp, occ, macro, nmx, nmy);
 }
 
 }  // namespace

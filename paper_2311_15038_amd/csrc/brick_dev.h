@@ -18,6 +18,8 @@
 // four elements instead of eight voxels.  Elements past the volume's end are 0.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace vr {
@@ -40,6 +42,22 @@ __device__ __forceinline__ float2 make_pair(float lo, float hi) { return make_fl
 template <typename T, bool PAIRS> struct ElemOf { typedef T type; };
 template <typename T> struct ElemOf<T, true> { typedef typename PairOf<T>::type type; };
 
+// Four consecutive voxels from one vector load.
+__device__ __forceinline__ void unpack4(uint2 w, uint16_t (&v)[4])
+{
+    v[0] = (uint16_t)(w.x & 0xFFFFu);
+    v[1] = (uint16_t)(w.x >> 16);
+    v[2] = (uint16_t)(w.y & 0xFFFFu);
+    v[3] = (uint16_t)(w.y >> 16);
+}
+__device__ __forceinline__ void unpack4(float4 w, float (&v)[4])
+{
+    v[0] = w.x;
+    v[1] = w.y;
+    v[2] = w.z;
+    v[3] = w.w;
+}
+
 // LDS of one slab group.
 template <typename T, bool PAIRS = false>
 struct SlabLds {
@@ -54,8 +72,9 @@ struct SlabLds {
 // are 16-byte pieces of whole bricks.  The occupancy marks of the slab (its 16
 // bricks and the neighbours at -1 in x, y and z) are gathered in LDS and
 // written once per slab, to the brick grid and to the 16^3 group grid.
-// Inactive groups take the same barriers.
-template <typename T, bool PAIRS = false>
+// Inactive groups take the same barriers.  VEC: nx is a multiple of 4 and
+// src is aligned to four voxels, so each thread's four voxels are one load.
+template <typename T, bool PAIRS = false, bool VEC = false>
 __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
                                  typename ElemOf<T, PAIRS>::type* __restrict__ dst, uint8_t* __restrict__ occ,
                                  uint8_t* __restrict__ macro, int nmx, int nmy, int bx0, int by, int bz,
@@ -70,8 +89,18 @@ __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int 
         T v[4];
         const bool rowok = y < ny && z < nz;
         const T* row = src + ((int64_t)z * ny + y) * nx;
+        if constexpr (VEC) {
+            using V4 = typename std::conditional<sizeof(T) == 2, uint2, float4>::type;
+            if (rowok && x0 < nx) {
+                unpack4(*reinterpret_cast<const V4*>(row + x0), v);
+            } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (rowok && x0 + e < nx) ? row[x0 + e] : (T)0;
+                for (int e = 0; e < 4; ++e) v[e] = (T)0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (rowok && x0 + e < nx) ? row[x0 + e] : (T)0;
+        }
         if constexpr (PAIRS) {
             // the voxel after the four (clamped to the row's last voxel)
             const T nxt = (rowok && x0 + 4 < nx) ? row[x0 + 4] : v[3];

@@ -150,7 +150,9 @@ def _brick_ref(a):
     return br, np.concatenate([occ.reshape(-1), macro.reshape(-1)])
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (70, 33, 81)])
+# nx a multiple of 4 takes whole-row vector loads: (8, 8, 8), (7, 5, 12), (13, 30, 64)
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (70, 33, 81), (7, 5, 12),
+                                   (13, 30, 64)])
 def test_brick_layout_and_occupancy(shape):
     banner(f"brick layout {shape}")
     rng = np.random.default_rng(31)
@@ -170,6 +172,29 @@ def test_brick_layout_and_occupancy(shape):
     assert (bf.occupancy.cpu().numpy() == occ).all()
 
 
+def test_brick_layout_from_unaligned_source():
+    """nx a multiple of 4 but the source one voxel past an aligned address: the voxel-by-voxel path."""
+    banner("brick layout from an unaligned source")
+    rng = np.random.default_rng(33)
+    shape = (6, 9, 16)
+    a = rng.integers(0, 65536, size=shape).astype(np.uint16)
+    a[rng.random(shape) < 0.5] = 0
+    flat = torch.zeros(a.size + 8, dtype=torch.int16, device=dev())
+    flat[1:1 + a.size] = torch.from_numpy(a.reshape(-1).view(np.int16)).to(dev())
+    src = flat[1:1 + a.size].view(shape)
+    assert src.data_ptr() % 8 != 0
+    bv = vr.vr_brick_volume(src)
+    br, occ = _brick_ref(a)
+    assert (bv.data.cpu().view(torch.int16).numpy().view(np.uint16) == br).all()
+    assert (bv.occupancy.cpu().numpy() == occ).all()
+    f = torch.zeros(a.size + 8, dtype=torch.float32, device=dev())
+    f[2:2 + a.size] = torch.from_numpy(a.reshape(-1).astype(np.float32) / 5.0).to(dev())
+    fs = f[2:2 + a.size].view(shape)
+    assert fs.data_ptr() % 16 != 0
+    bf = vr.vr_brick_volume(fs)
+    assert (bf.data.cpu().numpy() == _brick_ref(a.astype(np.float32) / 5.0)[0]).all()
+
+
 def _pairs_ref(a):
     """The layout of x-tap pairs: element (x, y, z) = (a[z, y, x], a[z, y, min(x + 1, nx - 1)]),
     in brick order, as the interleaved low/high voxels."""
@@ -182,7 +207,7 @@ def _pairs_ref(a):
     return pad.reshape(nbz, 4, nby, 4, nbx, 4, 2).transpose(0, 2, 4, 1, 3, 5, 6).reshape(-1)
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (5, 3, 4)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (5, 3, 4), (7, 5, 12)])
 def test_pair_layout(shape):
     banner(f"pair layout {shape}")
     rng = np.random.default_rng(32)
