@@ -8,16 +8,25 @@
  * This file follows the reading used throughout the project:
  *   - emission-absorption model with extinction sigma per world unit;
  *   - front-to-back compositing, midpoint samples of step "step" with a
- *     last step that ends the steps exactly at t_out; the step count is
- *     n = max(1, ceil(L/step - 2^-10)), so a segment that is a whole number
- *     of steps up to rounding of the clipped length is not given an extra
- *     sliver of a step (the last step then exceeds "step" by < step/1024);
+ *     last step that ends the steps exactly at t_out: n = max(1, ceil(L/step))
+ *     samples for the clipped length L = t_out - t_in (see or_segment), the
+ *     last one of length L - (n-1) step;
  *   - density = trilinear interpolation of cell-centred voxels, taps clamped
  *     to the volume (clamp-to-edge), u16 voxels scaled by 1/65535;
  *   - 256-entry piecewise-linear (r, g, b, sigma) transfer function.
  * Everything is evaluated in double precision, one ray at a time, with no
  * early termination; the number of samples a renderer with early termination
  * at T < ert_eps would take is counted alongside.
+ *
+ * Count bounds.  A renderer in lower precision takes the same two integer
+ * decisions per ray, the step count ceil(L/step) and the sample at which T
+ * first falls below ert_eps, from slightly different numbers.  Where either
+ * decision sits within a relative margin `tol` of its boundary it may go the
+ * other way, each by one sample.  Besides the count, the march therefore
+ * reports [lo, hi]: the count with the threshold raised (lowered) by the
+ * factor 1 + tol (1 - tol) and the step count taken from L/step - tol
+ * (L/step + tol).  The transmittance before an extra sample past the last one
+ * is the ray's final transmittance.
  */
 #include <math.h>
 #include <stdint.h>
@@ -129,11 +138,20 @@ void or_ray(const or_camera* c, int W, int H, int i, int j, double o[3], double 
     }
 }
 
-/* Slab test against [0, n*spacing] per axis; returns 0 when the ray misses. */
-int or_clip(const or_volume* v, const double o[3], const double d[3], double* t0, double* t1)
+/* The ray's segment inside the box [0, n*spacing]: *t0 = max(entry, 0) by the
+ * slab test, and *L = the distance from the entry point p = o + t0 d to the
+ * first face it leaves through, min over axes of (far_a - p_a) / d_a.  That
+ * is t_out - t_in, evaluated from coordinates inside the box rather than as
+ * the difference of two long distances from the eye, whose low bits rounding
+ * would lose (an axis-aligned ray across the box then has L = n * spacing
+ * exactly).  Returns 0 when the ray misses (L <= 0, or parallel to a pair of
+ * faces outside them: then *L = -inf). */
+int or_segment(const or_volume* v, const double o[3], const double d[3], double* t0, double* L)
 {
     const double ext[3] = { v->nx * v->spacing[0], v->ny * v->spacing[1], v->nz * v->spacing[2] };
-    double tin = -INFINITY, tout = INFINITY;
+    double tin = -INFINITY;
+    *t0 = 0.0;
+    *L = -INFINITY;
     for (int a = 0; a < 3; ++a) {
         if (d[a] == 0.0) {
             if (o[a] < 0.0 || o[a] > ext[a]) return 0;
@@ -141,31 +159,47 @@ int or_clip(const or_volume* v, const double o[3], const double d[3], double* t0
         }
         double ta = (0.0 - o[a]) / d[a];
         double tb = (ext[a] - o[a]) / d[a];
-        double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
+        double lo = ta < tb ? ta : tb;
         if (lo > tin) tin = lo;
-        if (hi < tout) tout = hi;
     }
     if (tin < 0.0) tin = 0.0;
-    if (!(tout > tin)) return 0;
+    double len = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) continue;
+        double p = o[a] + tin * d[a];
+        double la = ((d[a] > 0.0 ? ext[a] : 0.0) - p) / d[a];
+        if (la < len) len = la;
+    }
     *t0 = tin;
-    *t1 = tout;
-    return 1;
+    *L = len;
+    return len > 0.0;
 }
 
-/* One ray: writes rgba, returns the number of samples taken before T < ert_eps. */
+/* One ray: writes rgba, returns the number of samples taken before T < ert_eps.
+ * bounds: NULL, or [lo, hi] of that count under the margin tol (see above). */
 long or_march(const or_volume* v, const double* tf, const double o[3], const double d[3],
-              double step, double ert_eps, const double bg[4], double rgba[4])
+              double step, double ert_eps, const double bg[4], double rgba[4], double tol,
+              long bounds[2])
 {
-    double t0, t1;
-    if (!or_clip(v, o, d, &t0, &t1)) {
+    double t0, L;
+    if (!or_segment(v, o, d, &t0, &L)) {
         for (int c = 0; c < 4; ++c) rgba[c] = bg[c];
+        if (bounds) {
+            /* a ray missing the box by less than tol steps may graze it: one sample */
+            bounds[0] = 0;
+            bounds[1] = (L > -tol * step) ? 1 : 0;
+        }
         return 0;
     }
-    double L = t1 - t0;
-    long n = (long)ceil(L / step - 1.0 / 1024.0);
+    double r = L / step;
+    long n = (long)ceil(r);
     if (n < 1) n = 1;
+    long n_lo = (long)ceil(r - tol), n_hi = (long)ceil(r + tol);
+    if (n_lo < 0) n_lo = 0;
+    if (n_hi < 1) n_hi = 1;
+    const double eps_hi = ert_eps * (1.0 + tol), eps_lo = ert_eps * (1.0 - tol);
     double T = 1.0, C[3] = { 0.0, 0.0, 0.0 };
-    long counted = 0;
+    long counted = 0, lo = 0, hi = 0;
     for (long i = 0; i < n; ++i) {
         double len = (i < n - 1) ? step : L - (double)(n - 1) * step;
         double t = t0 + (double)i * step + 0.5 * len;
@@ -175,11 +209,18 @@ long or_march(const or_volume* v, const double* tf, const double o[3], const dou
         double e = exp(-q[3] * len);
         double alpha = 1.0 - e;
         if (T >= ert_eps) counted++;
+        if (i < n_lo && T >= eps_hi) lo++;
+        if (i < n_hi && T >= eps_lo) hi++;
         for (int c = 0; c < 3; ++c) C[c] += T * alpha * q[c];
         T *= e;
     }
+    if (n_hi > n && T >= eps_lo) hi++;
     for (int c = 0; c < 3; ++c) rgba[c] = C[c] + T * bg[c];
     rgba[3] = 1.0 - T * (1.0 - bg[3]);
+    if (bounds) {
+        bounds[0] = lo;
+        bounds[1] = hi;
+    }
     return counted;
 }
 
@@ -192,37 +233,55 @@ int or_threads(void)
 #endif
 }
 
-/* All pixels of all views: out[view][j][i][4]; samples[view] = counted samples. */
+/* All pixels of all views: out[view][j][i][4]; samples[view] = counted
+ * samples; bounds: NULL or [view][2], the summed [lo, hi] of the counts. */
 void or_render(const or_volume* v, const double* tf, const or_camera* cams, int n_views,
                int W, int H, double step, double ert_eps, const double bg[4],
-               double* out, long long* samples)
+               double* out, long long* samples, double tol, long long* bounds)
 {
     for (int vw = 0; vw < n_views; ++vw) {
-        long long cnt = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : cnt)
+        long long cnt = 0, lo = 0, hi = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : cnt, lo, hi)
         for (int j = 0; j < H; ++j) {
             for (int i = 0; i < W; ++i) {
                 double o[3], d[3];
+                long b[2];
                 or_ray(&cams[vw], W, H, i, j, o, d);
                 double* px = out + (((size_t)vw * H + j) * W + i) * 4;
-                cnt += or_march(v, tf, o, d, step, ert_eps, bg, px);
+                cnt += or_march(v, tf, o, d, step, ert_eps, bg, px, tol, b);
+                lo += b[0];
+                hi += b[1];
             }
         }
         samples[vw] = cnt;
+        if (bounds) {
+            bounds[2 * vw] = lo;
+            bounds[2 * vw + 1] = hi;
+        }
     }
 }
 
-/* A subset of pixels given as (view, j, i) triples: out[k][4]. */
+/* A subset of pixels given as (view, j, i) triples: out[k][4]; *samples = the
+ * counted samples of all of them; counts: NULL or [k][3], per pixel the count
+ * and its [lo, hi]. */
 void or_render_pixels(const or_volume* v, const double* tf, const or_camera* cams,
                       int W, int H, double step, double ert_eps, const double bg[4],
-                      long n_pix, const int32_t* pix, double* out, long long* samples)
+                      long n_pix, const int32_t* pix, double* out, long long* samples,
+                      double tol, long long* counts)
 {
     long long cnt = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : cnt)
     for (long k = 0; k < n_pix; ++k) {
         double o[3], d[3];
+        long b[2];
         or_ray(&cams[pix[3 * k]], W, H, pix[3 * k + 2], pix[3 * k + 1], o, d);
-        cnt += or_march(v, tf, o, d, step, ert_eps, bg, out + 4 * k);
+        long c = or_march(v, tf, o, d, step, ert_eps, bg, out + 4 * k, tol, b);
+        cnt += c;
+        if (counts) {
+            counts[3 * k] = c;
+            counts[3 * k + 1] = b[0];
+            counts[3 * k + 2] = b[1];
+        }
     }
     *samples = cnt;
 }

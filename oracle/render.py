@@ -4,6 +4,12 @@ Loads oracle/liboracle_render.so (plain C, gcc, OpenMP over rays), building it
 with gcc when it is missing.  Cameras are rows of 11 numbers: eye[3],
 target[3], up[3], vertical field of view in degrees (> 0 perspective) and the
 orthographic half height (used when the field of view is 0).
+
+Sample counts come with bounds: a renderer that takes the step count
+ceil(L/step) and the early-termination test T < ert_eps in lower precision
+may decide either one differently, by one sample, on rays where the decision
+lies within COUNT_TOL (relative) of its boundary.  [lo, hi] is the count with
+both decisions moved to the edges of that margin (see render.c).
 """
 from __future__ import annotations
 
@@ -19,6 +25,7 @@ _SO = os.path.join(_HERE, "liboracle_render.so")
 _lib = None
 
 U16, F32, F64 = 0, 1, 2
+COUNT_TOL = 2.0 ** -10
 
 
 class _Vol(C.Structure):
@@ -47,10 +54,11 @@ def lib():
         P = C.POINTER
         L.or_render.argtypes = [P(_Vol), P(C.c_double), P(_Cam), C.c_int, C.c_int, C.c_int,
                                 C.c_double, C.c_double, P(C.c_double), P(C.c_double),
-                                P(C.c_longlong)]
+                                P(C.c_longlong), C.c_double, P(C.c_longlong)]
         L.or_render_pixels.argtypes = [P(_Vol), P(C.c_double), P(_Cam), C.c_int, C.c_int,
                                        C.c_double, C.c_double, P(C.c_double), C.c_long,
-                                       P(C.c_int32), P(C.c_double), P(C.c_longlong)]
+                                       P(C.c_int32), P(C.c_double), P(C.c_longlong),
+                                       C.c_double, P(C.c_longlong)]
         L.or_density_many.argtypes = [P(_Vol), C.c_long, P(C.c_double), P(C.c_double)]
         L.or_threads.restype = C.c_int
         _lib = L
@@ -85,23 +93,28 @@ def _cams(cams):
     return arr, len(cams)
 
 
-def render(vol, spacing, tf, cams, W, H, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0)):
-    """FP64 render of every pixel of every view -> (rgba [V][H][W][4], samples [V])."""
+def render(vol, spacing, tf, cams, W, H, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0),
+           bounds=False):
+    """FP64 render of every pixel of every view -> (rgba [V][H][W][4], samples [V]),
+    and with bounds=True also the count bounds [V][2] = (lo, hi) under COUNT_TOL."""
     v, keep = _volume(vol, spacing)
     tf = np.ascontiguousarray(tf, dtype=np.float64).reshape(256, 4)
     ca, nv = _cams(cams)
     bga = np.asarray(bg, dtype=np.float64)
     out = np.zeros((nv, H, W, 4), dtype=np.float64)
     samples = np.zeros(nv, dtype=np.int64)
+    lohi = np.zeros((nv, 2), dtype=np.int64)
     lib().or_render(C.byref(v), _ptr(tf, C.c_double), ca, nv, W, H, float(step), float(ert_eps),
-                    _ptr(bga, C.c_double), _ptr(out, C.c_double), _ptr(samples, C.c_longlong))
+                    _ptr(bga, C.c_double), _ptr(out, C.c_double), _ptr(samples, C.c_longlong),
+                    COUNT_TOL, _ptr(lohi, C.c_longlong))
     del keep
-    return out, samples
+    return (out, samples, lohi) if bounds else (out, samples)
 
 
 def render_pixels(vol, spacing, tf, cams, W, H, step, pix, ert_eps=2.0 ** -14,
-                  bg=(0.0, 0.0, 0.0, 0.0)):
-    """FP64 render of selected pixels pix[k] = (view, j, i) -> (rgba [K][4], samples)."""
+                  bg=(0.0, 0.0, 0.0, 0.0), per_pixel=False):
+    """FP64 render of selected pixels pix[k] = (view, j, i) -> (rgba [K][4], samples),
+    and with per_pixel=True also [K][3]: each pixel's count and its (lo, hi)."""
     v, keep = _volume(vol, spacing)
     tf = np.ascontiguousarray(tf, dtype=np.float64).reshape(256, 4)
     ca, _ = _cams(cams)
@@ -109,11 +122,13 @@ def render_pixels(vol, spacing, tf, cams, W, H, step, pix, ert_eps=2.0 ** -14,
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
     out = np.zeros((len(pix), 4), dtype=np.float64)
     cnt = np.zeros(1, dtype=np.int64)
+    counts = np.zeros((len(pix), 3), dtype=np.int64)
     lib().or_render_pixels(C.byref(v), _ptr(tf, C.c_double), ca, W, H, float(step),
                            float(ert_eps), _ptr(bga, C.c_double), len(pix), _ptr(pix, C.c_int32),
-                           _ptr(out, C.c_double), _ptr(cnt, C.c_longlong))
+                           _ptr(out, C.c_double), _ptr(cnt, C.c_longlong), COUNT_TOL,
+                           _ptr(counts, C.c_longlong))
     del keep
-    return out, int(cnt[0])
+    return (out, int(cnt[0]), counts) if per_pixel else (out, int(cnt[0]))
 
 
 def density_at(vol, spacing, pts):

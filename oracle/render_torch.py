@@ -53,18 +53,22 @@ def render(density: torch.Tensor, tf: torch.Tensor, cams, W, H, step, spacing=(1
     ext = np.array([nx, ny, nz], dtype=np.float64) * sp
     o, d = rays(cams, W, H)
     R = o.shape[0]
-    # slab test per axis
+    # slab test per axis for the entry; the length from the entry point to the
+    # first exit face (t_out - t_in without the cancellation of two long distances)
     with np.errstate(divide="ignore", invalid="ignore"):
         ta = (0.0 - o) / d
         tb = (ext - o) / d
-    lo = np.where(d == 0.0, np.where((o >= 0.0) & (o <= ext), -np.inf, np.inf), np.minimum(ta, tb))
-    hi = np.where(d == 0.0, np.where((o >= 0.0) & (o <= ext), np.inf, -np.inf), np.maximum(ta, tb))
-    t_in = np.maximum(lo.max(axis=1), 0.0)
-    t_out = hi.min(axis=1)
-    hit = t_out > t_in
-    Lr = np.where(hit, t_out - t_in, 0.0)
+    outside = ((d == 0.0) & ((o < 0.0) | (o > ext))).any(axis=1)
+    lo = np.where(d == 0.0, -np.inf, np.minimum(ta, tb))
+    t_in = np.where(outside, 0.0, np.maximum(lo.max(axis=1), 0.0))
+    p_in = o + t_in[:, None] * d
+    with np.errstate(divide="ignore", invalid="ignore"):
+        la = np.where(d == 0.0, np.inf, (np.where(d > 0.0, ext, 0.0) - p_in) / d)
+    Lr = np.where(outside, -np.inf, la.min(axis=1))
+    hit = Lr > 0.0
+    Lr = np.where(hit, Lr, 0.0)
     t_in = np.where(hit, t_in, 0.0)
-    n = np.where(hit, np.maximum(1, np.ceil(Lr / step - 1.0 / 1024.0)), 0).astype(np.int64)
+    n = np.where(hit, np.maximum(1, np.ceil(Lr / step)), 0).astype(np.int64)
     nmax = int(n.max()) if R else 0
 
     flat = density.reshape(-1)

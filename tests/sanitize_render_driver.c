@@ -27,7 +27,8 @@ typedef struct {
 } or_volume;
 
 void or_render(const or_volume* v, const double* tf, const or_camera* cams, int n_views, int W, int H,
-               double step, double ert_eps, const double bg[4], double* out, long long* samples);
+               double step, double ert_eps, const double bg[4], double* out, long long* samples,
+               double tol, long long* bounds);
 
 static void* take(FILE* f, size_t n)
 {
@@ -67,12 +68,14 @@ int main(int argc, char** argv)
     or_volume v = {data, dtype, nx, ny, nz, {p[0], p[1], p[2]}};
     double* out = malloc((size_t)nv * H * W * 4 * sizeof(double));
     long long* samples = malloc((size_t)nv * sizeof(long long));
-    or_render(&v, tf, cams, nv, W, H, p[3], p[4], p + 5, out, samples);
+    long long* bounds = malloc((size_t)nv * 2 * sizeof(long long));
+    or_render(&v, tf, cams, nv, W, H, p[3], p[4], p + 5, out, samples, 1.0 / 1024.0, bounds);
     FILE* g = fopen(argv[2], "wb");
     if (!g) return 2;
     fwrite(out, sizeof(double), (size_t)nv * H * W * 4, g);
     fwrite(samples, sizeof(long long), (size_t)nv, g);
+    fwrite(bounds, sizeof(long long), (size_t)nv * 2, g);
     fclose(g);
-    free(out); free(samples); free(cams); free(data); free(c); free(tf); free(p); free(h);
+    free(out); free(samples); free(bounds); free(cams); free(data); free(c); free(tf); free(p); free(h);
     return 0;
 }

@@ -227,6 +227,105 @@ def test_sample_count():
     assert cnt[0] == 32 * 32 * per_ray
 
 
+def _front_march_brute(vol, sp, tf, cam, W, H, step, ert_eps):
+    """Hand-written march of the orthographic front view (rays along +y):
+    every hitting ray has L = ny * spacing_y exactly, n = ceil(L / step)."""
+    nz, ny, nx = vol.shape
+    o, d = RT.rays(cam, W, H)
+    L = ny * sp[1]
+    n = max(1, math.ceil(L / step))
+    out, counts = [], []
+    for k in range(len(o)):
+        x, z = o[k, 0], o[k, 2]
+        if not (0 <= x <= nx * sp[0] and 0 <= z <= nz * sp[2]):
+            out.append(np.array(BG))
+            counts.append(0)
+            continue
+        T, Cc, cnt = 1.0, np.zeros(3), 0
+        for i in range(n):
+            ln = step if i < n - 1 else L - (n - 1) * step
+            y = (i * step + 0.5 * ln) / sp[1] - 0.5          # voxel coordinate along y
+            s = R.density_at(vol, sp, [[x, (y + 0.5) * sp[1], z]])[0]
+            xx = min(max(s, 0.0), 1.0) * 255.0
+            kk = min(int(math.floor(xx)), 254)
+            w = xx - kk
+            q = (1 - w) * tf[kk] + w * tf[kk + 1]
+            e = math.exp(-q[3] * ln)
+            cnt += T >= ert_eps
+            Cc += T * (1 - e) * q[:3]
+            T *= e
+        out.append(np.concatenate([Cc + T * np.array(BG[:3]), [1 - T * (1 - BG[3])]]))
+        counts.append(cnt)
+    return np.array(out).reshape(H, W, 4), np.array(counts)
+
+
+@pytest.mark.parametrize("step,n_want", [(0.5, 20), (0.5 * (1 - 2.0 ** -20), 21)])
+def test_exact_multiple_step_count(step, n_want):
+    """A segment that is a whole number of steps (L = 10 along +y, step 0.5)
+    takes exactly L/step samples; a step a hair shorter gives ceil(L/step) =
+    L/step + 1 samples, the last a sliver of length L - 20 step."""
+    rng = np.random.default_rng(31)
+    nx, ny, nz = 5, 10, 6
+    vol = rng.uniform(0.0, 0.4, size=(nz, ny, nx))
+    tf = _linear_tf(np.array([0.8, 0.3, 0.6]), 0.7)
+    cam = synth.front_ortho_camera(nx, ny, nz)
+    W, H = 6, 5
+    img, cnt = R.render(vol, (1, 1, 1), tf, cam, W, H, step, ert_eps=0.0, bg=BG)
+    ref, per_ray = _front_march_brute(vol, (1, 1, 1), tf, cam, W, H, step, 0.0)
+    assert np.abs(img[0] - ref).max() < 1e-13
+    hit = per_ray > 0
+    assert hit.sum() >= 20 and (per_ray[hit] == n_want).all()
+    assert cnt[0] == per_ray.sum()
+
+
+def test_count_bounds_at_exact_multiples():
+    """On rays whose length is exactly 128 steps, a lower-precision length may
+    round up: hi allows the one extra sliver step, lo does not.  A step a hair
+    shorter (129 samples, the last a sliver) gives the opposite bounds."""
+    vol = np.zeros((64, 64, 64), dtype=np.uint16)
+    cam = synth.front_ortho_camera(64, 64, 64)
+    rays = 32 * 32
+    _, cnt, b = R.render(vol, (1, 1, 1), synth.default_tf(), cam, 32, 32, 0.5, bounds=True)
+    assert cnt[0] == rays * 128 and b[0, 0] == rays * 128 and b[0, 1] == rays * 129
+    _, cnt, b = R.render(vol, (1, 1, 1), synth.default_tf(), cam, 32, 32, 0.5 * (1 - 2.0 ** -20),
+                         bounds=True)
+    assert cnt[0] == rays * 129 and b[0, 0] == rays * 128 and b[0, 1] == rays * 129
+    # a step count far from a whole number: the bounds close on the count
+    _, cnt, b = R.render(vol, (1, 1, 1), synth.default_tf(), cam, 32, 32, 0.3, bounds=True)
+    assert cnt[0] == rays * 214 and b[0, 0] == b[0, 1] == cnt[0]
+
+
+def test_count_bounds_at_the_termination_threshold():
+    """Opaque medium, step 0.5, T_k = exp(-0.5 sigma k).  With sigma = 2 ln 2,
+    T_14 = 2^-14 up to rounding: the sample at which T falls below the
+    threshold is ambiguous, so [lo, hi] = [14, 15] per ray.  With sigma = 2 no
+    T_k lies near 2^-14 and the bounds close on the count of 1 + floor(14 ln 2)."""
+    vol = np.full((64, 64, 64), 65535, dtype=np.uint16)
+    cam = synth.front_ortho_camera(64, 64, 64)
+    rays = 32 * 32
+    _, cnt, b = R.render(vol, (1, 1, 1), _const_tf(0.5, 2.0 * math.log(2.0)), cam, 32, 32, 0.5,
+                         bounds=True)
+    assert b[0, 0] == rays * 14 and b[0, 1] == rays * 15
+    assert b[0, 0] <= cnt[0] <= b[0, 1]
+    _, cnt, b = R.render(vol, (1, 1, 1), _const_tf(0.5, 2.0), cam, 32, 32, 0.5, bounds=True)
+    per_ray = math.floor(14 * math.log(2)) + 1
+    assert cnt[0] == b[0, 0] == b[0, 1] == rays * per_ray
+
+
+def test_count_bounds_bracket_per_pixel():
+    """Per-pixel counts of a turntable scene lie within their own bounds, and
+    the bounds are at most one sample either side for each decision."""
+    rng = np.random.default_rng(4)
+    vol = rng.integers(0, 40000, size=(12, 10, 14)).astype(np.uint16)
+    cams = synth.turntable_cameras(14, 10, 12, n_views=4)
+    pix = np.array([(v, j, i) for v in range(4) for j in range(9) for i in range(11)])
+    _, tot, c = R.render_pixels(vol, (1, 1, 1), synth.default_tf(sigma_scale=8.0), cams, 11, 9, 0.5,
+                                pix, per_pixel=True)
+    assert (c[:, 1] <= c[:, 0]).all() and (c[:, 0] <= c[:, 2]).all()
+    assert (c[:, 0] - c[:, 1] <= 2).all() and (c[:, 2] - c[:, 0] <= 2).all()
+    assert tot == c[:, 0].sum()
+
+
 def test_torch_twin_matches_c_oracle():
     rng = np.random.default_rng(9)
     d = rng.uniform(0, 0.6, size=(11, 9, 10))

@@ -47,8 +47,8 @@ def _run(exe, tmp, vol, spacing, tf, cams, W, H, step, ert_eps, bg):
     raw = open(outp, "rb").read()
     n = len(cams) * H * W * 4
     rgba = np.frombuffer(raw[: 8 * n], dtype=np.float64).reshape(len(cams), H, W, 4)
-    samples = np.frombuffer(raw[8 * n:], dtype=np.int64)
-    return rgba, samples
+    rest = np.frombuffer(raw[8 * n:], dtype=np.int64)
+    return rgba, rest[: len(cams)], rest[len(cams):].reshape(len(cams), 2)
 
 
 def _cams(nx, ny, nz):
@@ -77,7 +77,8 @@ def test_sanitized_oracle_equals_plain_build(driver, tmp_path, shape, dtype, W, 
     cams = _cams(nx * spacing[0], ny * spacing[1], nz * spacing[2])
     bg = (0.1, 0.2, 0.3, 1.0)
     for ert in (0.0, 2.0 ** -14):
-        got, gs = _run(driver, str(tmp_path), vol, spacing, tf, cams, W, H, 0.37, ert, bg)
-        ref, rs = R.render(vol, spacing, tf, cams, W, H, 0.37, ert_eps=ert, bg=bg)
+        got, gs, gb = _run(driver, str(tmp_path), vol, spacing, tf, cams, W, H, 0.37, ert, bg)
+        ref, rs, rb = R.render(vol, spacing, tf, cams, W, H, 0.37, ert_eps=ert, bg=bg, bounds=True)
         assert np.array_equal(got, ref)
         assert np.array_equal(gs, rs)
+        assert np.array_equal(gb, rb)
