@@ -324,10 +324,11 @@ typedef struct {
  * u = r x f, ndc_x = (2(i+1/2)/W - 1) W/H, ndc_y = 1 - 2(j+1/2)/H:
  *   perspective: origin eye, direction normalise(f + tan(fov/2)(ndc_x r + ndc_y u));
  *   orthographic: origin eye + h (ndc_x r + ndc_y u), direction f.
- * The ray is clipped to the world box [0, n*spacing]^3 giving [t0, t1];
- * n = max(1, ceil((t1-t0)/step - 2^-10)) midpoint samples of length step, the
- * last one ending exactly at t1 (shorter than step, or longer by less than
- * step/1024 when rounding made the segment a hair over a whole number of steps).  Density = trilinear
+ * The ray is clipped to the world box [0, n*spacing]^3: t0 = max(entry, 0)
+ * and L = the distance from the entry point to the first face the ray leaves
+ * through (t1 - t0, taken from coordinates inside the box);
+ * n = max(1, ceil(L/step)) midpoint samples of length step, the last one
+ * ending exactly at t0 + L (no longer than step).  Density = trilinear
  * interpolation of cell-centred voxels with taps clamped to the volume; the
  * transfer function d_tf (256 x (r, g, b, sigma) f32, sigma = extinction per
  * world unit) is interpolated linearly at x = 255 clamp(s, 0, 1).  Front to

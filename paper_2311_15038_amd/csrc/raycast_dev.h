@@ -42,7 +42,7 @@ struct Scene {
     float aspect;
     float step, eps;
     float inv_step;         // 1 / step
-    float skip_c;           // sample-centre offset (plus the last step's excess) in skip_to
+    float skip_c;           // sample-centre offset (plus a rounding margin) in skip_to
     uint32_t row_e, slab_e; // element strides of a brick row and a brick slab (brick layouts)
     int wide;               // offsets need 64-bit addressing and full multiplies
     float bg[4];
@@ -234,7 +234,7 @@ __device__ __forceinline__ bool setup_ray(const View& v, const Scene& S, int i, 
             d[a] = v.f[a];
         }
     }
-    float tin = -INFINITY, tout = INFINITY;
+    float tin = -INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (d[a] == 0.0f) {
@@ -244,21 +244,29 @@ __device__ __forceinline__ bool setup_ray(const View& v, const Scene& S, int i, 
         const float ta = (0.0f - o[a]) / d[a];
         const float tb = (S.ext[a] - o[a]) / d[a];
         tin = fmaxf(tin, fminf(ta, tb));
-        tout = fminf(tout, fmaxf(ta, tb));
     }
     tin = fmaxf(tin, 0.0f);
-    if (!(tout > tin)) return false;
-    L = tout - tin;
 #pragma unroll
     for (int a = 0; a < 3; ++a) p[a] = fmaf(tin, d[a], o[a]);
-    return true;
+    // The clipped length is measured from the entry point to the first face
+    // the ray leaves through, not as the difference of two long distances
+    // from the eye: an axis-aligned ray across the box then has L = n *
+    // spacing exactly, a whole number of steps when the step divides it.
+    L = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) continue;
+        const float la = ((d[a] > 0.0f ? S.ext[a] : 0.0f) - p[a]) / d[a];
+        L = fminf(L, la);
+    }
+    return L > 0.0f;
 }
 
-// n = max(1, ceil(L/step - 2^-10)): a segment that is a whole number of steps
-// up to the rounding of its clipped length gets no extra sliver of a step.
+// n = max(1, ceil(L/step)) midpoint samples, the last one shorter than step
+// unless L is a whole number of steps.
 __device__ __forceinline__ int step_count(float L, float step)
 {
-    return max(1, (int)ceilf(L / step - (1.0f / 1024.0f)));
+    return max(1, (int)ceilf(L / step));
 }
 
 // Index of the first sample that may leave an empty cell (a brick, sh = 2,

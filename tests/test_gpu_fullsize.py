@@ -5,8 +5,8 @@ bricked 512^3 level, 36 x 512^2 turntable frames with empty-space skipping).
 Checked against the oracle: both histograms in full; the threshold and keep
 mask; every level on sampled 16-slice slabs (box sums never cross them) plus
 level 1 in full (built slab by slab); the atlas as the slicemap of level 2;
-and rendered RGBA on sampled pixels of all 36 views, computed one ray at a
-time by the FP64 oracle from the oracle's own level 1."""
+every pixel of the 36 rendered frames and the step's sample count against
+the FP64 oracle's render of its own level 1."""
 import numpy as np
 import pytest
 import torch
@@ -95,26 +95,40 @@ def test_level1_in_full(full, level1):
     assert np.array_equal(u16_np(pipe.levels[0]), level1)
 
 
-def test_frames_on_sampled_pixels(full, level1):
+@pytest.fixture(scope="module")
+def oracle_frames(full, level1):
     pipe, *_ = full
     c = pipe.cfg
-    banner("fullsize: sampled pixels of 36 x 512^2")
-    rng = np.random.default_rng(11)
-    n = 1536
-    pix = np.stack([rng.integers(0, len(pipe.cams), n), rng.integers(0, c.height, n),
-                    rng.integers(0, c.width, n)], axis=1)
-    # plus the centre column of every view, where rays cross the whole specimen
-    ctr = np.array([[v, j, c.width // 2] for v in range(len(pipe.cams))
-                    for j in range(0, c.height, 32)])
-    pix = np.concatenate([pix, ctr])
-    ref, _ = R.render_pixels(level1, (1, 1, 1), pipe.tf.cpu().numpy().astype(np.float64),
-                             pipe.cams, c.width, c.height, c.step, pix, c.ert_eps)
-    fr = pipe.frames.cpu().numpy()
-    got = fr[pix[:, 0], pix[:, 1], pix[:, 2]]
-    err = np.abs(got - ref).max()
+    banner(f"fullsize: FP64 oracle of all {len(pipe.cams)} x {c.width}x{c.height} frames")
+    return R.render(level1, (1, 1, 1), pipe.tf.cpu().numpy().astype(np.float64), pipe.cams,
+                    c.width, c.height, c.step, c.ert_eps, bounds=True)
+
+
+def test_frames_in_full(full, oracle_frames):
+    """Every pixel of the 36 turntable frames within 2e-4 of the FP64 oracle,
+    which renders them from its own level 1."""
+    pipe, *_ = full
+    banner("fullsize: frames in full")
+    ref, _, _ = oracle_frames
+    err = float(np.abs(pipe.frames.cpu().numpy() - ref).max())
     assert err <= 2e-4, err
-    assert ref[:, 3].max() > 0.5                          # the sample sees the specimen
-    assert int(pipe.samples[1].item()) <= int(pipe.samples[0].item())
+    assert ref[..., 3].max() > 0.5                        # the frames see the specimen
+
+
+def test_headline_sample_count(full, oracle_frames):
+    """The samples the 1024^3 step counts (the throughput's numerator) against
+    the oracle's count of samples taken before early termination: within the
+    per-ray bounds of an FP32 decision on the step count or the termination
+    sample (L/step within 2^-10 of an integer, T within a factor 1 -/+ 2^-10
+    of the threshold)."""
+    pipe, *_ = full
+    _, n_ref, lohi = oracle_frames
+    n_gpu = int(pipe.samples[0].item())
+    n_or, lo, hi = int(n_ref.sum()), int(lohi[:, 0].sum()), int(lohi[:, 1].sum())
+    banner(f"fullsize: samples gpu {n_gpu} oracle {n_or} bounds [{lo}, {hi}]")
+    assert lo <= n_gpu <= hi, (n_gpu, n_or, lo, hi)
+    assert hi - lo <= 1e-3 * n_or                         # the bounds are tight
+    assert int(pipe.samples[1].item()) <= n_gpu           # evaluated <= taken
 
 
 @pytest.mark.parametrize("shift", [8, 0])

@@ -35,13 +35,19 @@ def test_small_config_front_view(level1):
     cam = synth.front_ortho_camera(64, 64, 64)
     cnt = torch.zeros(2, dtype=torch.int64, device=dev())
     img = vr.vr_raycast(to_dev_u16(level1), _tf_dev(tf), cam, 256, 256, 0.5, samples=cnt)
-    ref, n_ref = R.render(level1, (1, 1, 1), tf.astype(np.float64), cam, 256, 256, 0.5)
+    ref, n_ref, lohi = R.render(level1, (1, 1, 1), tf.astype(np.float64), cam, 256, 256, 0.5,
+                                bounds=True)
     err = np.abs(img.cpu().numpy() - ref).max()
     assert err <= TOL, err
     assert ref[..., 3].max() > 0.5                        # the view does show the specimen
     n_gpu = int(cnt[0].item())
     assert int(cnt[1].item()) == n_gpu               # no occupancy: every sample evaluated
-    assert abs(n_gpu - int(n_ref[0])) <= 1e-3 * int(n_ref[0]), (n_gpu, n_ref)
+    # every ray crosses the box along +y with L = 64 exactly: 128 steps on both sides (the
+    # oracle's upper bound allows a 129th on each ray, since L/step is an integer) and no
+    # ray's transmittance comes near 2^-14, so the count is the oracle's exactly
+    lo, hi = int(lohi[0, 0]), int(lohi[0, 1])
+    assert lo == 256 * 256 * 128 and hi == 256 * 256 * 129, (lo, hi)
+    assert n_gpu == int(n_ref[0]) == lo, (n_gpu, int(n_ref[0]))
 
 
 def test_turntable_perspective(level1):
@@ -264,9 +270,11 @@ def test_brick_and_skip_bit_identical(level1, shape):
     assert c0[1].item() == c0[0].item() and c2[1].item() == c2[0].item()
     assert c1[1].item() <= c1[0].item()               # skipped samples are counted, not evaluated
     if shape != (64, 64, 64):
-        ref, n_ref = R.render(a, (1, 1, 1), synth.default_tf(sigma_scale=3.0).astype(np.float64),
-                              cams, 45, 38, 0.5)
+        ref, n_ref, lohi = R.render(a, (1, 1, 1), synth.default_tf(sigma_scale=3.0).astype(np.float64),
+                                    cams, 45, 38, 0.5, bounds=True)
         assert np.abs(skip.cpu().numpy() - ref).max() <= TOL
+        # the count the skipping march reports (passed-over samples included) is the oracle's
+        assert int(lohi[:, 0].sum()) <= c1[0].item() <= int(lohi[:, 1].sum()), (c1, n_ref.sum(), lohi.sum(0))
 
 
 def _grazing_cameras(nx, ny, nz):
