@@ -124,6 +124,7 @@ def run_gpu(steps, warmup):
     ms_step = total_ms / steps
     red_ms = sum(per[k] for k in pipe.REDUCTION_CALLS)
     red_bytes = pipe.reduction_bytes()
+    red_bytes_sep = pipe.reduction_bytes(separate_steps=True)
     T = int(pipe.result[0].item())
     best_view = int(pipe.best_view.item())
     best_entropy = float(pipe.view_entropy[best_view].item())
@@ -134,6 +135,7 @@ def run_gpu(steps, warmup):
         "kernel_ms": per,
         "reduction_ms": red_ms,
         "reduction_bytes": red_bytes,
+        "reduction_bytes_separate_steps": red_bytes_sep,
         "threshold": T,
         "best_view": {"view": best_view, "entropy_bits": best_entropy},
     }
@@ -693,6 +695,11 @@ def main():
         "evaluated_per_step": evaluated,
         "reduction": {"ms": res["reduction_ms"], "bytes": res["reduction_bytes"],
                       "GB_per_s": red_gbs, "frac_hbm_peak": red_gbs / HBM_PEAK_GBS,
+                      "bytes_note": "bytes the fused pass moves (the atlas comes from the pyramid's "
+                                    "pass, its level is not read again)",
+                      "bytes_separate_steps": res["reduction_bytes_separate_steps"],
+                      "frac_hbm_peak_separate_steps": res["reduction_bytes_separate_steps"]
+                      / (res["reduction_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       "threshold": res["threshold"]},
         "best_view": res["best_view"],
         "kernel_ms": res["kernel_ms"],

@@ -194,15 +194,17 @@ class PreviewPipeline:
 
     REDUCTION_CALLS = ("histograms", "select", "pyramid+atlas")
 
-    def reduction_bytes(self) -> int:
-        """Algorithmic HBM bytes of the reduction steps (histograms, pyramid, atlas), each
-        input read once and each output written once, as for separate steps."""
+    def reduction_bytes(self, separate_steps=False) -> int:
+        """Algorithmic HBM bytes of the reduction (histograms, pyramid, atlas): each
+        input read once and each output written once.  The atlas is written by the
+        pyramid's own pass, so its level is not read again; separate_steps=True
+        counts that read too, as a separate packing step would make it."""
         nz, ny, nx = self.shape
         vol = nx * ny * nz * 2
         top = nx * ny * min(self.cfg.top_slices, nz) * 2
         lv = sum(l.numel() * 2 for l in self.levels)
         at_in = at_out = 0
         if self.atlas is not None:
-            at_in = self.levels[self.cfg.atlas_level - 1].numel() * 2
+            at_in = self.levels[self.cfg.atlas_level - 1].numel() * 2 if separate_steps else 0
             at_out = self.atlas.numel() * 2
         return vol + top + vol + lv + at_in + at_out

@@ -280,3 +280,75 @@ def test_brick_layout_adjoint_matches_linear():
         assert s > 0 and np.abs(got - ref).max() <= 1e-5 * s, (occ, np.abs(got - ref).max() / s)
         st = np.abs(tl.cpu().numpy()).max()
         assert np.abs(tb.cpu().numpy() - tl.cpu().numpy()).max() <= 1e-4 * st
+
+
+def test_adjoint_at_fit_size():
+    """The fit's configuration: a 256^3 f32 grid of spacing 2 (a generated scene,
+    grey values / 65535), the default TF, 16 turntable views at 256 x 256 of its
+    world box, step 1 (half a voxel), through the differentiable render as the fit
+    calls it (bricked copy with empty-space skipping), early termination off.
+    The loss weights 256 sampled pixels only, so the FP64 autograd reference marches
+    just those rays; density and TF gradients must agree to 2e-3 of their maxima,
+    and central differences of the C oracle at 16 voxels (h = 1e-3) and the 8
+    largest TF entries (h = 1e-5)."""
+    n, W, H, step, sp, V = 256, 256, 256, 1.0, (2.0, 2.0, 2.0), 16
+    banner("backward at fit size: 256^3 f32, 16 x 256^2, 256 weighted pixels")
+    a = synth.to_numpy_u16(synth.make_volume(synth.scaled_spec(n, n, n, 2330)))
+    dens32 = a.astype(np.float32) / np.float32(65535.0)
+    tf32 = synth.default_tf().astype(np.float32)
+    cams = synth.turntable_cameras(n, n, n, spacing=sp, n_views=V)
+    rng = np.random.default_rng(31)
+    K = 256
+    pix = np.stack([rng.integers(0, V, K), rng.integers(H // 5, H - H // 5, K),
+                    rng.integers(W // 5, W - W // 5, K)], axis=1)
+    wts = rng.uniform(-1.0, 1.0, size=(K, 4))
+
+    d = torch.tensor(dens32, device=dev(), requires_grad=True)
+    t = torch.tensor(tf32, device=dev(), requires_grad=True)
+    img = VA.render(d, t, cams, W, H, step, sp, ert_eps=0.0)
+    pt = torch.from_numpy(pix).to(dev())
+    (img[pt[:, 0], pt[:, 1], pt[:, 2]] * torch.tensor(wts, dtype=torch.float32, device=dev())).sum().backward()
+    gd, gt = d.grad.cpu().numpy(), t.grad.cpu().numpy()
+
+    dref = torch.tensor(dens32.astype(np.float64), requires_grad=True)
+    tref = torch.tensor(tf32.astype(np.float64), requires_grad=True)
+    o, dd = RT.pixel_rays(cams, W, H, pix)
+    ref = RT.march_rays(dref, tref, o, dd, step, sp)
+    (ref * torch.tensor(wts)).sum().backward()
+    gd_ref, gt_ref = dref.grad.numpy(), tref.grad.numpy()
+    got = img.detach()[pt[:, 0], pt[:, 1], pt[:, 2]].cpu().numpy()
+    assert np.abs(got - ref.detach().numpy()).max() <= 2e-4
+    sd, st = np.abs(gd_ref).max(), np.abs(gt_ref).max()
+    assert sd > 0 and st > 0
+    ed, et = np.abs(gd - gd_ref).max() / sd, np.abs(gt - gt_ref).max() / st
+    banner(f"fit size: density grad rel err {ed:.2e}, tf grad rel err {et:.2e}, "
+           f"{int((gd_ref != 0).sum())} voxels touched")
+    assert ed <= 2e-3 and et <= 2e-3
+
+    d64, t64 = dens32.astype(np.float64), tf32.astype(np.float64)
+
+    def loss(dv, tv):
+        im, _ = R.render_pixels(dv, sp, tv, cams, W, H, step, pix, ert_eps=0.0)
+        return float((im * wts).sum())
+
+    h = 1e-3
+    big = np.argwhere(np.abs(gd_ref) > 0.05 * sd)
+    ok = 0
+    for z, y, x in big[rng.choice(len(big), size=16, replace=False)]:
+        dp, dm = d64.copy(), d64.copy()
+        dp[z, y, x] += h
+        dm[z, y, x] -= h
+        fd = (loss(dp, t64) - loss(dm, t64)) / (2 * h)
+        ok += abs(gd[z, y, x] - fd) <= 1e-3 * sd + 5e-2 * abs(fd)
+    assert ok >= 14, ok
+    # the 8 largest TF gradients; h = 1e-5 there, since the extinction of the air's
+    # knots multiplies path lengths of hundreds of samples and the loss curves too
+    # strongly for central differences at 1e-3
+    ht = 1e-5
+    for q in np.argsort(np.abs(gt_ref).ravel())[-8:]:
+        k, c = divmod(int(q), 4)
+        tp, tm = t64.copy(), t64.copy()
+        tp[k, c] += ht
+        tm[k, c] -= ht
+        fd = (loss(d64, tp) - loss(d64, tm)) / (2 * ht)
+        assert abs(gt[k, c] - fd) <= 1e-3 * st + 1e-3 * abs(fd), (k, c, gt[k, c], fd)

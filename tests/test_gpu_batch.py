@@ -3,7 +3,10 @@
 Reduction outputs (threshold, level 1) bit-exact; frames bit-identical to the
 single-volume ray caster on the same bricked level and within 2e-4 of the
 oracle; repeated launches and HIP graph replays give the same results; other
-launch shapes (the tuner's choices) do not change them.
+launch shapes (the tuner's choices, down to the smallest tasks, which split
+every histogram over many tasks) do not change them.  A batch of volumes at
+the extremes of the uneven-batch sizes (64 to 512 voxels per axis) is checked
+against the oracle too.
 """
 import json
 
@@ -56,10 +59,12 @@ def test_batch_matches_single_volume(volumes):
     b.close()
 
 
-def test_batch_matches_oracle(volumes):
-    banner("batch vs oracle")
+@pytest.mark.parametrize("hist_task_voxels", [4 << 20, 8192])
+def test_batch_matches_oracle(volumes, hist_task_voxels):
+    banner(f"batch vs oracle, {hist_task_voxels} voxels per histogram task")
     W = H = 24
-    b = VB.BatchPreview(volumes[:3], n_views=2, width=W, height=H)
+    b = VB.BatchPreview(volumes[:3], n_views=2, width=W, height=H,
+                        tuning=dict(hist_task_voxels=hist_task_voxels))
     b.launch()
     torch.cuda.synchronize()
     tf = synth.default_tf().astype(np.float64)
@@ -105,7 +110,8 @@ def test_launch_shape_does_not_change_results(volumes):
     ref = None
     for t in [dict(wave_w=8, wave_h=8, waves_x=4), dict(wave_w=16, wave_h=4, waves_x=2, hist_task_voxels=1 << 20,
                                                        down_tiles_per_task=3, slabs_per_task=5),
-              dict(wave_w=4, wave_h=16, waves_x=8, down_tiles_per_task=64, slabs_per_task=200)]:
+              dict(wave_w=4, wave_h=16, waves_x=8, down_tiles_per_task=64, slabs_per_task=200),
+              dict(hist_task_voxels=8192, down_tiles_per_task=1, slabs_per_task=1)]:
         b = VB.BatchPreview(volumes, n_views=2, width=35, height=29, tuning=t)
         b.launch()
         torch.cuda.synchronize()
@@ -134,3 +140,39 @@ def test_batch_rejects_bad_config(volumes):
         VB.BatchPreview(volumes[:1], n_views=2, width=8, height=8, tuning=dict(wave_w=8, wave_h=4))
     with pytest.raises(vr.VrError):
         VB.BatchPreview(volumes[:1], n_views=49, width=8, height=8)
+
+
+# (nz, ny, nx) at the extremes of 64..512 per axis, plus a ragged one
+CONFIG3_SHAPES = [(384, 64, 512), (64, 512, 512), (512, 512, 64), (64, 64, 64), (301, 77, 449)]
+
+
+def test_batch_extreme_shapes_match_oracle():
+    """Volumes at the extremes of the uneven-batch sizes: with the default task
+    sizes the larger ones take several histogram tasks each (4 Mi voxels per
+    task), whose counts are summed into one histogram.  Thresholds and level 1
+    bit-exact against the oracle, frames bit-identical to the single-volume path
+    and within 2e-4 of the oracle."""
+    vols = [synth.make_volume(synth.scaled_spec(nx, ny, nz, 4100 + k), dev())
+            for k, (nz, ny, nx) in enumerate(CONFIG3_SHAPES)]
+    W = H = 48
+    banner(f"batch of extreme shapes {CONFIG3_SHAPES}")
+    b = VB.BatchPreview(vols, n_views=3, width=W, height=H)
+    b.launch()
+    torch.cuda.synchronize()
+    assert b.status()[0] == 0
+    assert b.n_tasks() > 2 * len(vols)
+    tf = synth.default_tf().astype(np.float64)
+    for i, v in enumerate(vols):
+        banner(f"extreme shape {tuple(v.shape)}: oracle")
+        a = u16_np(v)
+        Hh, Ht = O.histogram(a), O.histogram(a, 0, 3)
+        T = O.valley_threshold(Hh)
+        L1 = O.pyramid(a, O.keep_bits(T, Ht), 1)[0]
+        assert b.result(i)[0].item() == T, (i, b.result(i)[0].item(), T)
+        assert np.array_equal(u16_np(b.level1(i)), L1), i
+        res, L1g, fr = _solo(v, b.cams[i][0], W, H, b.tf)
+        assert torch.equal(b.frames[i], fr), i
+        ref, _ = R.render(L1, (1, 1, 1), tf, b.cams[i][0], W, H, 0.5)
+        err = float(np.abs(b.frames[i].cpu().numpy() - ref).max())
+        assert err <= 2e-4, (i, err)
+    b.close()

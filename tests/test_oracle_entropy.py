@@ -75,3 +75,52 @@ def test_best_view_is_first_maximum():
     best, H = E.best_view(frames)
     assert best == 2
     assert np.allclose(H, [0.0, 1.0, 2.0, 2.0, 1.0])
+
+
+def _round_f32(x):
+    """x (a non-negative Fraction) rounded to the nearest FP32 value, ties to even:
+    the rounding of one FP32 operation, written out in exact rational arithmetic."""
+    from fractions import Fraction
+    if x == 0:
+        return Fraction(0)
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    if Fraction(2) ** e > x:
+        e -= 1                                       # 2^e <= x < 2^(e+1)
+    ulp = Fraction(2) ** (e - 23)
+    m = x / ulp
+    f = m.numerator // m.denominator
+    r = m - f
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and f % 2 == 1):
+        f += 1
+    return f * ulp
+
+
+def test_channel_codes_at_every_rounding_boundary():
+    """Around each boundary (k - 1/2)/255 of the 8-bit code, 64 FP32 values on
+    either side: the oracle's code equals floor(round32(round32(255 c) + 1/2)),
+    each FP32 operation written out as an exact rational rounding, and it equals
+    the exact floor(255 c + 1/2) except for values whose exact 255 c + 1/2 lies
+    within 2^-15 of the integer k (there the FP32 sum rounds onto k)."""
+    import math
+    from fractions import Fraction
+    flips = 0
+    for k in range(1, 256):
+        b = np.float32((k - 0.5) / 255.0)
+        vals = [b]
+        lo = hi = b
+        for _ in range(64):
+            lo = np.nextafter(lo, np.float32(0.0))
+            hi = np.nextafter(hi, np.float32(1.0))
+            vals += [lo, hi]
+        vals = np.array(vals, dtype=np.float32)
+        got = E.channel_codes(vals)
+        for c, q in zip(vals.tolist(), got.tolist()):
+            cf = Fraction(c)
+            fp32 = math.floor(_round_f32(_round_f32(255 * cf) + Fraction(1, 2)))
+            assert q == fp32, (k, c, q, fp32)
+            exact = math.floor(255 * cf + Fraction(1, 2))
+            if q != exact:
+                flips += 1
+                assert abs(255 * cf + Fraction(1, 2) - k) < Fraction(1, 2 ** 15), (k, c)
+        assert got.min() == k - 1 and got.max() == k          # both codes occur around it
+    assert flips < 255 * 8                                     # a few values per boundary at most

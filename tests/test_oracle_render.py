@@ -402,3 +402,59 @@ def test_torch_twin_gradient_analytic_single_material():
     others = torch.ones(256, dtype=torch.bool)
     others[k] = others[k + 1] = False
     assert tf.grad[others].abs().max().item() == 0.0
+
+
+def _pix(V, H, W, K, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, V, K), rng.integers(0, H, K), rng.integers(0, W, K)], axis=1)
+
+
+def test_march_rays_matches_both_oracles():
+    """The per-ray form of the torch twin against the C oracle and the step-by-step
+    twin, on sampled pixels of perspective and orthographic views (misses included)."""
+    rng = np.random.default_rng(21)
+    d = rng.uniform(0, 0.6, size=(11, 9, 10))
+    sp = (1.0, 1.3, 0.7)
+    tf = synth.random_tf(22).astype(np.float64)
+    cams = np.concatenate([synth.turntable_cameras(10, 9, 11, sp, n_views=3),
+                           synth.front_ortho_camera(10, 9, 11, sp)])
+    W, H = 13, 11
+    pix = np.concatenate([_pix(4, H, W, 60, 23), [[3, 0, 0], [0, 5, 6]]])
+    o, dd = RT.pixel_rays(cams, W, H, pix)
+    got = RT.march_rays(torch.tensor(d), torch.tensor(tf), o, dd, 0.4, sp, bg=BG).numpy()
+    ref_c, _ = R.render_pixels(d, sp, tf, cams, W, H, 0.4, pix, ert_eps=0.0, bg=BG)
+    full = RT.render(torch.tensor(d), torch.tensor(tf), cams, W, H, 0.4, sp, bg=BG).numpy()
+    assert np.abs(got - ref_c).max() < 1e-13
+    assert np.abs(got - full[pix[:, 0], pix[:, 1], pix[:, 2]]).max() < 1e-13
+    assert (np.abs(got - np.array(BG)).max(axis=1) > 0.01).sum() > 15     # a third of them show the volume
+
+
+def test_march_rays_beer_lambert():
+    nx, ny, nz = 6, 10, 8
+    vol = torch.full((nz, ny, nx), 20000 / 65535, dtype=torch.float64)
+    rgb, sig = np.array([0.7, 0.2, 0.4]), 0.13
+    cam = synth.front_ortho_camera(nx, ny, nz)
+    o, d = RT.pixel_rays(cam, 9, 7, [[0, 3, 4]])                 # the centre pixel
+    got = RT.march_rays(vol, torch.tensor(_const_tf(rgb, sig)), o, d, 0.3, bg=BG).numpy()[0]
+    e = math.exp(-sig * ny)
+    want = np.concatenate([rgb * (1 - e) + np.array(BG[:3]) * e, [1 - e * (1 - BG[3])]])
+    assert np.abs(got - want).max() < 1e-12
+
+
+def test_march_rays_gradient_matches_step_by_step_twin():
+    rng = np.random.default_rng(24)
+    d = rng.uniform(0.05, 0.5, size=(8, 9, 7))
+    tf = synth.random_tf(25).astype(np.float64)
+    cams = synth.turntable_cameras(7, 9, 8, n_views=2)
+    W = H = 10
+    pix = _pix(2, H, W, 40, 26)
+    wts = torch.tensor(rng.uniform(-1, 1, size=(len(pix), 4)))
+    d1, t1 = torch.tensor(d, requires_grad=True), torch.tensor(tf, requires_grad=True)
+    o, dd = RT.pixel_rays(cams, W, H, pix)
+    (RT.march_rays(d1, t1, o, dd, 0.5) * wts).sum().backward()
+    d2, t2 = torch.tensor(d, requires_grad=True), torch.tensor(tf, requires_grad=True)
+    img = RT.render(d2, t2, cams, W, H, 0.5)
+    (img[pix[:, 0], pix[:, 1], pix[:, 2]] * wts).sum().backward()
+    assert d1.grad.abs().max() > 0 and t1.grad.abs().max() > 0
+    assert (d1.grad - d2.grad).abs().max() < 1e-12
+    assert (t1.grad - t2.grad).abs().max() < 1e-12
