@@ -163,6 +163,30 @@ int vr_find_container(const uint16_t* d_slice, int64_t nx, int64_t ny, int r_min
                       int edge_shift, int margin, void* d_work, int64_t work_bytes,
                       int32_t* d_circle, void* stream);
 
+/*
+ * vr_find_container for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that forbid allocation): the same steps
+ * and the same record, with the workspace taken from a fixed device array of
+ * VR_CONTAINER_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of a caller's buffer.  Nothing is allocated
+ * or freed by the call.
+ *   Size limit: the slice's vr_container_workspace_size must not exceed
+ *     VR_CONTAINER_SCRATCH_BYTES (any slice of at most 1024 x 1024 pixels, for
+ *     every r_max); larger requests return VR_ERR_WORKSPACE before anything is
+ *     enqueued.
+ *   The array belongs to the device current on the calling thread, and
+ *   `stream` must belong to that device.  Every call on one GPU shares it:
+ *   calls that overlap on one GPU (on different streams, or from several host
+ *   threads) race and give undefined records; calls in one stream order are
+ *   safe, since each starts by clearing what it accumulates.  The first call
+ *   on a device looks the array's address up (hipGetSymbolAddress).
+ * Errors: as vr_find_container (VR_ERR_WORKSPACE for the size limit), and
+ * VR_ERR_UNSUPPORTED for a device index above 63.
+ */
+#define VR_CONTAINER_SCRATCH_BYTES (32ll << 20)
+int vr_find_container_noalloc(const uint16_t* d_slice, int64_t nx, int64_t ny, int r_min, int r_max,
+                              int edge_shift, int margin, int32_t* d_circle, void* stream);
+
 /* Sets every voxel outside the kept disc of d_circle to 0, in every slice of
  * d_vol [nz][ny][nx], in place (nothing changes when the circle was not
  * found).  Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_HIP. */

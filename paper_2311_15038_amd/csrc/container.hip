@@ -19,6 +19,7 @@
 //      [found, cx, cy, r, R, centre votes, radius count, edges].
 // Every decision is integer arithmetic, so the record is exact.
 #include <algorithm>
+#include <mutex>
 
 #include "disc_dev.h"
 
@@ -359,27 +360,19 @@ extern "C" int vr_container_workspace_size(int64_t nx, int64_t ny, int r_max, in
     return VR_OK;
 }
 
-extern "C" int vr_find_container(const uint16_t* d_slice, int64_t nx, int64_t ny, int r_min, int r_max,
-                                 int edge_shift, int margin, void* d_work, int64_t work_bytes,
-                                 int32_t* d_circle, void* stream)
+namespace {
+
+// The steps of vr_find_container on a carved workspace w.
+int find_on(const uint16_t* d_slice, int64_t nx, int64_t ny, int r_min, int r_max, int edge_shift, int margin,
+            const Ws& w, int32_t* d_circle, hipStream_t s)
 {
-    vr::clear_error();
-    VR_REQUIRE(d_slice && d_work && d_circle, VR_ERR_NULL, "vr_find_container: NULL pointer");
-    int rc = check_find(nx, ny, r_min, r_max, edge_shift, margin);
-    if (rc) return rc;
-    const int64_t need = carve(nullptr, nx, ny, r_max, nullptr);
-    VR_REQUIRE(work_bytes >= need, VR_ERR_WORKSPACE, "vr_find_container: workspace %lld bytes, %lld needed",
-               (long long)work_bytes, (long long)need);
-    VR_REQUIRE((reinterpret_cast<uintptr_t>(d_work) & 255u) == 0, VR_ERR_RANGE,
-               "vr_find_container: workspace not 256-byte aligned");
-    Ws w;
-    carve(d_work, nx, ny, r_max, &w);
-    hipStream_t s = vr::as_stream(stream);
+    int rc;
     const int64_t cap = (int64_t)vr::num_cus() * 8;
     const int64_t n = nx * ny, interior = (nx - 2) * (ny - 2);
     const int wb = std::max(1, r_max / 16);
     const int k0 = std::max(1, (r_min * 181) >> 8);     // below r_min / sqrt(2): no step reaches r_min
 
+    // every counter and accumulator the later steps add to starts at zero here
     clear_ws<<<grid_for(n, cap), kT, 0, s>>>(w, n, r_max + 1);
     if ((rc = vr::check_launch("vr_find_container: clear"))) return rc;
     const int64_t cap2 = (int64_t)vr::num_cus() * 2;
@@ -399,6 +392,77 @@ extern "C" int vr_find_container(const uint16_t* d_slice, int64_t nx, int64_t ny
     if ((rc = vr::check_launch("vr_find_container: radii"))) return rc;
     finish<<<1, kT, 0, s>>>(nx, r_min, r_max, margin, w, d_circle);
     return vr::check_launch("vr_find_container: record");
+}
+
+// Workspace of vr_find_container_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes its name to a
+// kernel (on the host the name is a stand-in, not a device address): the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kScratchBytes = VR_CONTAINER_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device).
+int scratch_ptr(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    VR_REQUIRE(e == hipSuccess, VR_ERR_HIP, "vr_find_container_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    VR_REQUIRE(dev >= 0 && dev < kMaxDevices, VR_ERR_UNSUPPORTED,
+               "vr_find_container_noalloc: device %d beyond the %d this build tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        VR_REQUIRE(e == hipSuccess && p != nullptr, VR_ERR_HIP,
+                   "vr_find_container_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VR_OK;
+}
+
+}  // namespace
+
+extern "C" int vr_find_container(const uint16_t* d_slice, int64_t nx, int64_t ny, int r_min, int r_max,
+                                 int edge_shift, int margin, void* d_work, int64_t work_bytes,
+                                 int32_t* d_circle, void* stream)
+{
+    vr::clear_error();
+    VR_REQUIRE(d_slice && d_work && d_circle, VR_ERR_NULL, "vr_find_container: NULL pointer");
+    int rc = check_find(nx, ny, r_min, r_max, edge_shift, margin);
+    if (rc) return rc;
+    const int64_t need = carve(nullptr, nx, ny, r_max, nullptr);
+    VR_REQUIRE(work_bytes >= need, VR_ERR_WORKSPACE, "vr_find_container: workspace %lld bytes, %lld needed",
+               (long long)work_bytes, (long long)need);
+    VR_REQUIRE((reinterpret_cast<uintptr_t>(d_work) & 255u) == 0, VR_ERR_RANGE,
+               "vr_find_container: workspace not 256-byte aligned");
+    Ws w;
+    carve(d_work, nx, ny, r_max, &w);
+    return find_on(d_slice, nx, ny, r_min, r_max, edge_shift, margin, w, d_circle, vr::as_stream(stream));
+}
+
+extern "C" int vr_find_container_noalloc(const uint16_t* d_slice, int64_t nx, int64_t ny, int r_min, int r_max,
+                                         int edge_shift, int margin, int32_t* d_circle, void* stream)
+{
+    vr::clear_error();
+    VR_REQUIRE(d_slice && d_circle, VR_ERR_NULL, "vr_find_container_noalloc: NULL pointer");
+    int rc = check_find(nx, ny, r_min, r_max, edge_shift, margin);
+    if (rc) return rc;
+    const int64_t need = carve(nullptr, nx, ny, r_max, nullptr);
+    VR_REQUIRE(need <= kScratchBytes, VR_ERR_WORKSPACE,
+               "vr_find_container_noalloc: a %lld x %lld slice needs %lld bytes of scratch, above the %lld "
+               "this build holds",
+               (long long)nx, (long long)ny, (long long)need, (long long)kScratchBytes);
+    void* base = nullptr;
+    if ((rc = scratch_ptr(&base))) return rc;
+    Ws w;
+    carve(base, nx, ny, r_max, &w);
+    return find_on(d_slice, nx, ny, r_min, r_max, edge_shift, margin, w, d_circle, vr::as_stream(stream));
 }
 
 extern "C" int vr_remove_container(uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz, const int32_t* d_circle,

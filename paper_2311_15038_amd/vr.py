@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libvr.so")
 NBINS = 65536
 KEEP_WORDS = 2048
 CIRCLE_INTS = 8
+CONTAINER_SCRATCH_BYTES = 32 << 20
 HOLLOW_MAX_THICKNESS = 8
 MAX_LEVELS = 4
 MAX_VIEWS_PER_LAUNCH = 48
@@ -90,6 +91,7 @@ def lib():
         L.vr_histogram_with_top.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
         L.vr_container_workspace_size.argtypes = [i64, i64, i32, C.POINTER(C.c_int64)]
         L.vr_find_container.argtypes = [vp, i64, i64, i32, i32, i32, i32, vp, i64, vp, vp]
+        L.vr_find_container_noalloc.argtypes = [vp, i64, i64, i32, i32, i32, i32, vp, vp]
         L.vr_remove_container.argtypes = [vp, i64, i64, i64, vp, vp]
         L.vr_hollow.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp]
         L.vr_histogram_in_disc.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp]
@@ -119,7 +121,7 @@ def lib():
         for name in ("vr_histogram", "vr_select_threshold", "vr_threshold_downsample",
                      "vr_pack_slicemap", "vr_raycast", "vr_raycast_backward", "vr_brick_volume",
                      "vr_unbrick_volume", "vr_frame_entropy", "vr_entropy_from_counts", "vr_container_workspace_size",
-                     "vr_find_container", "vr_remove_container", "vr_histogram_in_disc",
+                     "vr_find_container", "vr_find_container_noalloc", "vr_remove_container", "vr_histogram_in_disc",
                      "vr_threshold_downsample_in_disc", "vr_hollow",
                      "vr_brick_count", "vr_histogram_with_top", "vr_batch_workspace_size",
                      "vr_batch_plan_create", "vr_batch_launch", "vr_batch_capture", "vr_batch_status",
@@ -233,6 +235,22 @@ def vr_find_container(slice2d, r_min=None, r_max=None, edge_shift=4, margin=2, w
                                    int(edge_shift), int(margin), _dev(work, "work", torch.uint8, need),
                                    work.numel(), _dev(circle, "circle", torch.int32, CIRCLE_INTS),
                                    _stream(stream)))
+    return circle
+
+
+def vr_find_container_noalloc(slice2d, r_min=None, r_max=None, edge_shift=4, margin=2, circle=None,
+                              stream=None):
+    """vr_find_container with the library's fixed device scratch as its workspace
+    (the call allocates nothing; pass `circle` to allocate nothing here either)."""
+    ny, nx = slice2d.shape
+    lo, hi = container_radii(nx, ny)
+    r_min = lo if r_min is None else r_min
+    r_max = hi if r_max is None else r_max
+    if circle is None:
+        circle = torch.empty(CIRCLE_INTS, dtype=torch.int32, device=slice2d.device)
+    _check(lib().vr_find_container_noalloc(_dev(slice2d, "slice", _U16), nx, ny, int(r_min), int(r_max),
+                                           int(edge_shift), int(margin),
+                                           _dev(circle, "circle", torch.int32, CIRCLE_INTS), _stream(stream)))
     return circle
 
 

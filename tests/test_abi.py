@@ -126,6 +126,18 @@ def test_container_validation_on_the_host(lib):
     assert ok(r0=0) == -3 and ok(r0=41) == -3 and ok(sh=17) == -3 and ok(m=-1) == -3
     assert ok(wb=need - 1) == -7
     assert ok(w=C.c_void_p(128)) == -3                                           # unaligned workspace
+    # the no-allocation variant: same validation, and the scratch array's size limit
+    na = lambda **k: lib.vr_find_container_noalloc(k.get("s", p), k.get("nx", 100), k.get("ny", 80),  # noqa: E731
+                                                   k.get("r0", 10), k.get("r1", 40), 4, 2, k.get("c", p), None)
+    assert na(s=None) == -1 and na(c=None) == -1 and na(r0=0) == -3 and na(nx=2) == -2
+    assert lib.vr_container_workspace_size(1100, 1100, 550, C.byref(b)) == 0
+    assert b.value > vr.CONTAINER_SCRATCH_BYTES
+    assert na(nx=1100, ny=1100, r0=137, r1=550) == -7
+    assert "scratch" in lib.vr_last_error().decode()
+    assert lib.vr_container_workspace_size(1024, 1024, 4096, C.byref(b)) == 0
+    assert b.value <= vr.CONTAINER_SCRATCH_BYTES                                 # 1024^2 slices fit
+    m = re.search(r"#define VR_CONTAINER_SCRATCH_BYTES \((\d+)ll << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == vr.CONTAINER_SCRATCH_BYTES
     assert lib.vr_remove_container(None, 4, 4, 4, p, None) == -1
     assert lib.vr_remove_container(p, 4, 0, 4, p, None) == -2
     assert lib.vr_histogram_in_disc(p, 4, 4, 4, 5, p, p, p, None) == -3
