@@ -42,6 +42,7 @@ extern "C" {
 #define VR_KEEP_WORDS 2048        /* keep mask: bin b -> bit (b % 32) of word b / 32 */
 #define VR_MAX_LEVELS 4           /* pyramid levels produced by one call */
 #define VR_MAX_VIEWS_PER_LAUNCH 48
+#define VR_BRICK_DIST_CAP 8       /* cap of the brick distance grid, see vr_brick_volume */
 
 enum {
     VR_OK = 0,
@@ -69,7 +70,8 @@ enum { VR_U16_NORM = 0, VR_F32 = 1 };
 enum {
     VR_LAYOUT_LINEAR = 0,      /* [nz][ny][nx], x fastest */
     VR_LAYOUT_BRICK4 = 1,      /* 4x4x4 bricks, see vr_brick_volume */
-    VR_LAYOUT_BRICK4_PAIRS = 2 /* 4x4x4 bricks of x-tap pairs, see vr_brick_volume */
+    VR_LAYOUT_BRICK4_PAIRS = 2, /* 4x4x4 bricks of x-tap pairs, see vr_brick_volume */
+    VR_LAYOUT_BRICK8 = 3       /* 8x8x8 bricks, see vr_brick_volume */
 };
 
 /*
@@ -278,19 +280,31 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  * one of the 8 taps of a trilinear fetch whose base (floor, clamped) tap lies
  * in that brick, followed by one byte per 4 x 4 x 4 bricks (16^3 voxels,
  * [ceil(nbz/4)][ceil(nby/4)][ceil(nbx/4)]) that is non-zero iff any of its
- * bricks is.  The ray caster passes over samples of unoccupied bricks
- * when the transfer function's first entry has zero extinction: such samples
- * have density 0 and change neither colour nor transmittance, so the result
- * is bit-identical.
+ * bricks is, then one byte per brick (brick order) holding the Chebyshev
+ * distance in bricks, max over axes of |b - b'|, to the nearest occupied
+ * brick b', capped at VR_BRICK_DIST_CAP (0 for an occupied brick; the cap
+ * where none is nearer), then one byte per brick of working storage.  The
+ * ray caster passes over samples of unoccupied bricks when the transfer
+ * function's first entry has zero extinction: such samples have density 0
+ * and change neither colour nor transmittance, so the result is
+ * bit-identical.  From an empty brick whose distance is r it leaves in one
+ * step the cube of bricks within r - 1 of it, all of them empty.
  * Layout VR_LAYOUT_BRICK4_PAIRS orders elements the same way, but element
  * (x, y, z) holds two voxels, (x, y, z) then (min(x + 1, nx - 1), y, z)
  * (two u16 in one 32-bit word, low half first, or two f32): the two x taps
  * of a trilinear fetch come in one load, at twice the memory.
+ * Layout VR_LAYOUT_BRICK8 is the same with 8 x 8 x 8-voxel bricks: brick
+ * (bx, by, bz) at element ((bz*nby + by)*nbx + bx)*512 with nbx = ceil(nx / 8),
+ * voxel (x, y, z) at ((z&7)*64 + (y&7)*8 + (x&7)) inside it; its occupancy is
+ * the same four grids over these bricks (groups of 4 x 4 x 4 of them, 32^3
+ * voxels), sized by vr_brick_count_layout.
  *   d_src: [nz][ny][nx] of u16 (dtype VR_U16_NORM) or f32 (VR_F32).
- *   layout: VR_LAYOUT_BRICK4 or VR_LAYOUT_BRICK4_PAIRS.
- *   d_bricked: vr_brick_count(...) * 64 elements (x2 voxels for pairs),
- *     16-byte aligned, overwritten.
- *   d_occupancy: NULL or the occupancy_bytes of vr_brick_count, overwritten.
+ *   layout: VR_LAYOUT_BRICK4, VR_LAYOUT_BRICK4_PAIRS or VR_LAYOUT_BRICK8.
+ *   d_bricked: the elements of vr_brick_count_layout (for 4^3 bricks
+ *     vr_brick_count(...) * 64, x2 voxels for pairs), 16-byte aligned,
+ *     overwritten.
+ *   d_occupancy: NULL or the occupancy_bytes of vr_brick_count_layout,
+ *     overwritten.
  * Errors: VR_ERR_NULL, VR_ERR_DTYPE, VR_ERR_DIMS, VR_ERR_RANGE (layout,
  * alignment), VR_ERR_HIP.
  */
@@ -311,14 +325,23 @@ int vr_unbrick_volume(const void* d_bricked, int dtype, int64_t nx, int64_t ny, 
                       void* stream);
 
 /* Number of 4x4x4 bricks of an nx x ny x nz volume and the size of its
- * occupancy (nullable) in bytes (host only). */
+ * occupancy (nullable; the grids vr_brick_volume describes: 3 bytes per brick
+ * plus one per 4x4x4 bricks) in bytes (host only). */
 int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_t* occupancy_bytes);
+
+/* vr_brick_count for any brick layout: bricks of the layout's edge (4 for
+ * VR_LAYOUT_BRICK4 and VR_LAYOUT_BRICK4_PAIRS, 8 for VR_LAYOUT_BRICK8),
+ * elements of the bricked volume (nullable; bricks x edge^3, doubled for the
+ * pair layout), and the occupancy's bytes (nullable).
+ * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (layout). */
+int vr_brick_count_layout(int layout, int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_t* elements,
+                          int64_t* occupancy_bytes);
 
 /* A volume to render. dtype VR_U16_NORM (value / 65535) or VR_F32 (value). */
 typedef struct {
     const void* data;          /* device pointer in `layout` */
     int32_t dtype;
-    int32_t layout;            /* VR_LAYOUT_LINEAR, VR_LAYOUT_BRICK4 or VR_LAYOUT_BRICK4_PAIRS */
+    int32_t layout;            /* VR_LAYOUT_LINEAR, VR_LAYOUT_BRICK4, VR_LAYOUT_BRICK4_PAIRS or VR_LAYOUT_BRICK8 */
     int64_t nx, ny, nz;
     double spacing[3];         /* world units per voxel along x, y, z (> 0) */
     const uint8_t* occupancy;  /* NULL, or the brick occupancy (brick layouts only) */
@@ -339,7 +362,15 @@ typedef struct {
     uint32_t* view_hist;       /* NULL, or [n_views][256] device counts, overwritten by
                                   vr_raycast with the grey-value histogram of each frame
                                   as vr_frame_entropy defines it (for vr_entropy_from_counts) */
+    uint32_t flags;            /* 0, or VR_RENDER_STAGED (vr_raycast only) */
 } vr_render_opts;
+
+/* vr_render_opts.flags: march in depth windows whose voxels are staged in LDS
+ * instead of reading the taps through the caches (u16 volumes in
+ * VR_LAYOUT_BRICK4 with their occupancy, otherwise VR_ERR_UNSUPPORTED).  The
+ * frames and counts are bit-identical; on the turntable benchmark it is the
+ * slower of the two marches. */
+#define VR_RENDER_STAGED 1u
 
 /*
  * Emission-absorption ray casting (Section III-C renders the reduced data to
@@ -473,8 +504,9 @@ typedef struct {
     int32_t waves_x;           /* waves across a render task's tile (16 waves per task; divides 16) */
     int64_t hist_task_voxels;  /* voxels per histogram task (>= 8192) */
     int32_t down_tiles_per_task;   /* 64x16x16 tiles per pyramid task */
-    int32_t slabs_per_task;    /* 16-brick slabs per brick task */
+    int32_t slabs_per_task;    /* 16-brick slabs per brick task (8^3 bricks: 256 row pieces each) */
     int32_t render_tiles_per_task; /* must be 1 */
+    int32_t brick_edge;        /* level-1 bricks of 4 (or 0) or 8 voxels a side */
 } vr_batch_config;
 
 int vr_batch_workspace_size(const vr_batch_item* items, int n_items, const vr_batch_config* cfg,

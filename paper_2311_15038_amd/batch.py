@@ -6,10 +6,10 @@ every item (histograms, masks, level 1, bricks, occupancy, task table), builds
 the plan, optionally captures the launch into a HIP graph, and exposes the
 per-item outputs as tensor views of the workspace.
 
-tune() times candidate render tiles (pixels per wave, waves per task) and
-task sizes on the actual batch with HIP events and keeps the fastest; results
-are cached in a JSON file keyed by GPU architecture, a coarse size bucket of
-the batch and the frame size.
+tune() times candidate render tiles (pixels per wave, waves per task), brick
+sizes (4^3 or 8^3 voxels) and task sizes on the actual batch with HIP events
+and keeps the fastest; results are cached in a JSON file keyed by GPU
+architecture, a coarse size bucket of the batch and the frame size.
 """
 from __future__ import annotations
 
@@ -24,9 +24,10 @@ import torch
 from . import synth, vr
 
 DEFAULTS = dict(wave_w=8, wave_h=8, waves_x=4, hist_task_voxels=4 << 20, down_tiles_per_task=16,
-                slabs_per_task=32)
+                slabs_per_task=32, brick_edge=4)
 
 RENDER_TILES = [(8, 8, 4), (8, 8, 2), (8, 8, 8), (16, 4, 2), (16, 4, 4), (4, 16, 8), (4, 16, 4)]
+BRICK_EDGES = [4, 8]
 TASK_SIZES = [(4 << 20, 16, 32), (1 << 20, 8, 16), (16 << 20, 32, 64)]
 
 
@@ -35,7 +36,7 @@ def _cfg(width, height, step, ert_eps, bg, rule, rule_param, top_slices, t):
                               (C.c_float * 4)(*[float(b) for b in bg]), int(rule), int(rule_param),
                               int(top_slices), int(t["wave_w"]), int(t["wave_h"]), int(t["waves_x"]),
                               int(t["hist_task_voxels"]), int(t["down_tiles_per_task"]),
-                              int(t["slabs_per_task"]), 1)
+                              int(t["slabs_per_task"]), 1, int(t.get("brick_edge", 4)))
 
 
 class BatchPreview:
@@ -156,11 +157,15 @@ def tune(volumes, n_views=12, width=256, height=256, use_cache=True, log=None, *
     timings = {}                  # configuration -> fastest time seen (ms), status-0 runs only
     best = dict(DEFAULTS)
     ws = None
-    # stage 1: render tile shape; stage 2: task sizes with the best tile
-    for stage in range(2):
-        cands = [dict(best, wave_w=a, wave_h=b, waves_x=c) for a, b, c in RENDER_TILES] if stage == 0 else [
-            dict(best, hist_task_voxels=h, down_tiles_per_task=d, slabs_per_task=s)
-            for h, d, s in TASK_SIZES]
+    # stage 1: render tile shape; stage 2: brick size; stage 3: task sizes, each with the best so far
+    for stage in range(3):
+        if stage == 0:
+            cands = [dict(best, wave_w=a, wave_h=b, waves_x=c) for a, b, c in RENDER_TILES]
+        elif stage == 1:
+            cands = [dict(best, brick_edge=e) for e in BRICK_EDGES]
+        else:
+            cands = [dict(best, hist_task_voxels=h, down_tiles_per_task=d, slabs_per_task=s)
+                     for h, d, s in TASK_SIZES]
         for t in cands:
             b = BatchPreview(volumes, n_views, width, height, tuning=t, workspace=ws, **kw)
             ws = b.workspace

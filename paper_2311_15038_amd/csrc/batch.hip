@@ -84,6 +84,7 @@ struct BatchDev {
     int rule, rule_param, n_chunks;
     int wave_w, wave_h, waves_x;   // render tile: waves of wave_w x wave_h pixels, waves_x across
     int tiles_per_row;             // render tiles across an image
+    int brick8;                    // level 1 in 8^3 bricks (else 4^3)
 };
 
 union BatchLds {
@@ -193,8 +194,16 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
         break;
     }
     case T_BRICK: {
-        // slabs [a, b): slab s = (bz * nby + by) * nslab_x + sx
         wait_ge(B, cnt + C_DOWN, it.need[C_DOWN]);
+        if (B.brick8) {
+            // 8-voxel row pieces [a, b), one per thread
+            for (int64_t r = t.a + tid; r < t.b; r += kT)
+                vr::bk::row8_body<uint16_t>(it.level1, it.lx, it.ly, it.lz, it.nbx, it.nby, it.bricked, it.occ,
+                                            it.occ + (int64_t)it.nbx * it.nby * it.nbz, it.nmx, it.nmy, r);
+            signal(cnt + C_BRICK);
+            break;
+        }
+        // slabs [a, b): slab s = (bz * nby + by) * nslab_x + sx
         const int g = tid / vr::bk::kThreads, lt = tid % vr::bk::kThreads;
         const int groups = kT / vr::bk::kThreads;
         const int64_t n_slabs = (int64_t)it.nslab_x * it.nby * it.nbz;
@@ -260,8 +269,11 @@ __device__ void render_waves(const BatchDev& B, const BatchLds& L)
         const int j = ty * tile_h + (w / B.waves_x) * B.wave_h + lane / B.wave_w;
         uint32_t cr = 0, er = 0;
         if (i < S.W && j < S.H) {
-            const float4 rgba = vr::rc::march<uint16_t, VR_LAYOUT_BRICK4, true, false>(
-                S, it.V.v[t.a], it.bricked, L.tf, skip, i, j, cr, er);
+            const float4 rgba =
+                B.brick8 ? vr::rc::march<uint16_t, VR_LAYOUT_BRICK8, true, false, false>(
+                               S, it.V.v[t.a], it.bricked, L.tf, skip, i, j, cr, er)
+                         : vr::rc::march<uint16_t, VR_LAYOUT_BRICK4, true, false, false>(
+                               S, it.V.v[t.a], it.bricked, L.tf, skip, i, j, cr, er);
             reinterpret_cast<float4*>(it.frames)[((int64_t)t.a * S.H + j) * S.W + i] = rgba;
         }
         if (B.samples) {
@@ -364,6 +376,10 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
                (long long)cfg->hist_task_voxels);
     VR_REQUIRE(cfg->down_tiles_per_task >= 1 && cfg->slabs_per_task >= 1 && cfg->render_tiles_per_task == 1,
                VR_ERR_RANGE, "vr_batch: task sizes");
+    VR_REQUIRE(cfg->brick_edge == 0 || cfg->brick_edge == 4 || cfg->brick_edge == 8, VR_ERR_RANGE,
+               "vr_batch: brick edge %d (4 or 8)", cfg->brick_edge);
+    const bool b8 = cfg->brick_edge == 8;
+    const int be = b8 ? 8 : 4;
 
     const int bins = cfg->rule == VR_RULE_VALLEY || cfg->rule == VR_RULE_NONE ? VR_NBINS : (VR_NBINS >> cfg->rule_param);
     const int n_chunks = (bins + kT - 1) / kT;
@@ -397,16 +413,16 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
         it.level1 = static_cast<uint16_t*>(C.take((size_t)it.lx * it.ly * it.lz * 2));
         it.down_tiles_x = (it.nx + vr::ds::TX - 1) / vr::ds::TX;
         it.down_tiles_y = (it.ny + vr::ds::TY - 1) / vr::ds::TY;
-        it.nbx = (it.lx + 3) / 4;
-        it.nby = (it.ly + 3) / 4;
-        it.nbz = (it.lz + 3) / 4;
+        it.nbx = (it.lx + be - 1) / be;
+        it.nby = (it.ly + be - 1) / be;
+        it.nbz = (it.lz + be - 1) / be;
         it.nmx = (it.nbx + 3) / 4;
         it.nmy = (it.nby + 3) / 4;
         const int nmz = (it.nbz + 3) / 4;
         it.nslab_x = (it.nbx + 15) / 16;
         const int64_t nbricks = (int64_t)it.nbx * it.nby * it.nbz;
         it.occ_bytes = nbricks + (int64_t)it.nmx * it.nmy * nmz;
-        it.bricked = static_cast<uint16_t*>(C.take((size_t)nbricks * 64 * 2));
+        it.bricked = static_cast<uint16_t*>(C.take((size_t)nbricks * be * be * be * 2));
         it.occ = static_cast<uint8_t*>(C.take((size_t)it.occ_bytes));
         it.frames = in.d_frames;
         it.n_views = in.n_views;
@@ -416,7 +432,7 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
         vr_volume vol{};
         vol.data = it.bricked ? it.bricked : reinterpret_cast<const void*>(16);
         vol.dtype = VR_U16_NORM;
-        vol.layout = VR_LAYOUT_BRICK4;
+        vol.layout = b8 ? VR_LAYOUT_BRICK8 : VR_LAYOUT_BRICK4;
         vol.nx = it.lx;
         vol.ny = it.ly;
         vol.nz = it.lz;
@@ -434,6 +450,7 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
                    "vr_batch_plan_create: item %d has a level of more than 2^24 bricks", v);
         it.S.data = it.bricked;
         it.S.occ = it.occ;
+        it.S.dist = nullptr;     // the batch keeps the marks and the group marks only
         it.S.view0 = 0;
         rc = vr::rc::build_views(in.h_cams, in.n_views, it.V);
         if (rc) return rc;
@@ -461,10 +478,13 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
         for (int64_t a = 0; a < n_tiles; a += cfg->down_tiles_per_task, ++n_down)
             phase[T_DOWN].push_back({T_DOWN, v, a, std::min<int64_t>(n_tiles, a + cfg->down_tiles_per_task)});
         it.need[C_DOWN] = n_down;
-        const int64_t n_slabs = (int64_t)it.nslab_x * it.nby * it.nbz;
+        // 4^3: slabs of 16 bricks along x; 8^3: 8-voxel row pieces, 256 per slab's worth
+        const int64_t n_units = b8 ? (int64_t)it.nbx * (it.nby * 8) * (it.nbz * 8)
+                                   : (int64_t)it.nslab_x * it.nby * it.nbz;
+        const int64_t per_task = b8 ? (int64_t)cfg->slabs_per_task * 256 : (int64_t)cfg->slabs_per_task;
         int n_brick = 0;
-        for (int64_t a = 0; a < n_slabs; a += cfg->slabs_per_task, ++n_brick)
-            phase[T_BRICK].push_back({T_BRICK, v, a, std::min<int64_t>(n_slabs, a + cfg->slabs_per_task)});
+        for (int64_t a = 0; a < n_units; a += per_task, ++n_brick)
+            phase[T_BRICK].push_back({T_BRICK, v, a, std::min<int64_t>(n_units, a + per_task)});
         it.need[C_BRICK] = n_brick;
         for (int view = 0; view < in.n_views; ++view)
             for (int tt = 0; tt < tiles_per_row * tiles_per_col; ++tt)
@@ -490,6 +510,7 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
     B.wave_h = wh;
     B.waves_x = wx;
     B.tiles_per_row = tiles_per_row;
+    B.brick8 = b8 ? 1 : 0;
     B.items = static_cast<const ItemDev*>(C.take(sizeof(ItemDev) * n_items));
     B.tasks = static_cast<const Task*>(C.take(sizeof(Task) * tasks->size()));
     B.counters = static_cast<uint32_t*>(C.take(sizeof(uint32_t) * (C_COUNT * n_items + 4)));

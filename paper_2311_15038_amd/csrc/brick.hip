@@ -24,6 +24,60 @@ brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby
                         blockIdx.z, true, threadIdx.x, G);
 }
 
+// One separable pass of the capped Chebyshev distance over the brick grid:
+// out[b] = min over |t| < kDistCap of max(|t|, in(b + t e_axis)), where in(i)
+// is 0 for a marked brick and kDistCap otherwise (FROM_OCC, the first pass),
+// or the previous pass's value.  Taken over x, then y, then z this is the
+// distance min over marked b' of max_a |b_a - b'_a|, capped.  A workgroup is
+// 64 x 4 bricks of a z-slice.  Every offset is read (no early exit), so the
+// 2 (kDistCap - 1) loads of a brick are in flight together; an offset past
+// the grid's edge reads the edge brick instead, whose own term, at a smaller
+// offset, is already in the minimum and no smaller than this one.
+template <bool FROM_OCC>
+__device__ __forceinline__ int dist_in(const uint8_t* __restrict__ in, int64_t i)
+{
+    return FROM_OCC ? (in[i] != 0 ? 0 : kDistCap) : (int)in[i];
+}
+
+template <bool FROM_OCC>
+__global__ void __launch_bounds__(256)
+dist_pass(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, int nbx, int nby, int nbz, int axis)
+{
+    const int x = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int y = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6), z = (int)blockIdx.z;
+    if (x >= nbx || y >= nby) return;
+    const int64_t b = ((int64_t)z * nby + y) * nbx + x;
+    const int c = axis == 0 ? x : axis == 1 ? y : z;
+    const int na = axis == 0 ? nbx : axis == 1 ? nby : nbz;
+    const int64_t st = axis == 0 ? 1 : axis == 1 ? (int64_t)nbx : (int64_t)nbx * nby;
+    int best = dist_in<FROM_OCC>(in, b);
+#pragma unroll
+    for (int t = 1; t < kDistCap; ++t) {
+        const int up = min(c + t, na - 1) - c, dn = c - max(c - t, 0);
+        best = min(best, max(t, dist_in<FROM_OCC>(in, b + up * st)));
+        best = min(best, max(t, dist_in<FROM_OCC>(in, b - dn * st)));
+    }
+    out[b] = (uint8_t)best;
+}
+
+template <bool FROM_OCC>
+void launch_dist(hipStream_t s, const uint8_t* in, uint8_t* out, int nbx, int nby, int nbz, int axis)
+{
+    const dim3 g((unsigned)vr::ceil_div(nbx, 64), (unsigned)vr::ceil_div(nby, 4), (unsigned)nbz);
+    dist_pass<FROM_OCC><<<g, 256, 0, s>>>(in, out, nbx, nby, nbz, axis);
+}
+
+// 8^3 bricks: one thread per 8-voxel row piece (grid-stride).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+brick8_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby, T* __restrict__ dst,
+              uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx, int nmy)
+{
+    const int64_t n = (int64_t)nbx * (nby * 8) * ((nz + 7) / 8 * 8);
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads)
+        row8_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, r);
+}
+
 // Rows load four voxels at a time when nx is a multiple of 4 and src is
 // aligned to four voxels.
 template <typename T, bool PAIRS>
@@ -51,7 +105,25 @@ extern "C" int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bri
                (long long)nz);
     const int64_t bx = (nx + 3) / 4, by = (ny + 3) / 4, bz = (nz + 3) / 4;
     *n_bricks = bx * by * bz;
-    if (occupancy_bytes) *occupancy_bytes = bx * by * bz + ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 3) / 4);
+    if (occupancy_bytes) *occupancy_bytes = 3 * bx * by * bz + ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 3) / 4);
+    return VR_OK;
+}
+
+extern "C" int vr_brick_count_layout(int layout, int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks,
+                                     int64_t* elements, int64_t* occupancy_bytes)
+{
+    vr::clear_error();
+    VR_REQUIRE(n_bricks != nullptr, VR_ERR_NULL, "vr_brick_count_layout: n_bricks is NULL");
+    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS || layout == VR_LAYOUT_BRICK8,
+               VR_ERR_RANGE, "vr_brick_count_layout: layout %d is not a brick layout", layout);
+    VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
+               VR_ERR_DIMS, "vr_brick_count_layout: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
+               (long long)nz);
+    const int e = layout == VR_LAYOUT_BRICK8 ? 8 : 4;
+    const int64_t bx = (nx + e - 1) / e, by = (ny + e - 1) / e, bz = (nz + e - 1) / e;
+    *n_bricks = bx * by * bz;
+    if (elements) *elements = bx * by * bz * e * e * e * (layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
+    if (occupancy_bytes) *occupancy_bytes = 3 * bx * by * bz + ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 3) / 4);
     return VR_OK;
 }
 
@@ -62,15 +134,17 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
     VR_REQUIRE(d_src && d_bricked, VR_ERR_NULL, "vr_brick_volume: NULL pointer");
     VR_REQUIRE(dtype == VR_U16_NORM || dtype == VR_F32, VR_ERR_DTYPE, "vr_brick_volume: dtype %d",
                dtype);
-    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS, VR_ERR_RANGE,
-               "vr_brick_volume: layout %d is not a brick layout", layout);
+    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS || layout == VR_LAYOUT_BRICK8,
+               VR_ERR_RANGE, "vr_brick_volume: layout %d is not a brick layout", layout);
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
                VR_ERR_DIMS, "vr_brick_volume: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
                (long long)nz);
-    const int nbx = (int)((nx + 3) / 4), nby = (int)((ny + 3) / 4), nbz = (int)((nz + 3) / 4);
+    const int be = layout == VR_LAYOUT_BRICK8 ? 8 : 4;
+    const int nbx = (int)((nx + be - 1) / be), nby = (int)((ny + be - 1) / be), nbz = (int)((nz + be - 1) / be);
     const int nmx = (nbx + 3) / 4, nmy = (nby + 3) / 4, nmz = (nbz + 3) / 4;
     const int64_t bricks = (int64_t)nbx * nby * nbz;
-    const int64_t occ_bytes = bricks + (int64_t)nmx * nmy * nmz;
+    const int64_t groups = (int64_t)nmx * nmy * nmz;
+    const int64_t occ_bytes = bricks + groups;           // marks and group marks (cleared first)
     VR_REQUIRE(nby < 65536 && nbz < 65536, VR_ERR_DIMS, "vr_brick_volume: volume too large");
     VR_REQUIRE((reinterpret_cast<uintptr_t>(d_bricked) & 15u) == 0, VR_ERR_RANGE,
                "vr_brick_volume: d_bricked must be 16-byte aligned");
@@ -86,14 +160,33 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
     uint8_t* macro = d_occupancy ? d_occupancy + bricks : nullptr;
     const bool pairs = layout == VR_LAYOUT_BRICK4_PAIRS;
     const int inx = (int)nx, iny = (int)ny, inz = (int)nz;
-    if (dtype == VR_U16_NORM) {
+    if (layout == VR_LAYOUT_BRICK8) {
+        const int64_t pieces = (int64_t)nbx * (nby * 8) * (nbz * 8);
+        const unsigned g8 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap * 4, vr::ceil_div<int64_t>(pieces, kThreads)));
+        if (dtype == VR_U16_NORM)
+            brick8_kernel<uint16_t><<<g8, kThreads, 0, s>>>(static_cast<const uint16_t*>(d_src), inx, iny, inz, nbx,
+                                                            nby, static_cast<uint16_t*>(d_bricked), d_occupancy, macro,
+                                                            nmx, nmy);
+        else
+            brick8_kernel<float><<<g8, kThreads, 0, s>>>(static_cast<const float*>(d_src), inx, iny, inz, nbx, nby,
+                                                         static_cast<float*>(d_bricked), d_occupancy, macro, nmx,
+                                                         nmy);
+    } else if (dtype == VR_U16_NORM) {
         if (pairs) launch_brick<uint16_t, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
         else launch_brick<uint16_t, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
     } else {
         if (pairs) launch_brick<float, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
         else launch_brick<float, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
     }
-    return vr::check_launch("vr_brick_volume");
+    int rc = vr::check_launch("vr_brick_volume");
+    if (rc || !d_occupancy) return rc;
+    // the distance grid: x from the marks, y into the working bytes, z back
+    uint8_t* dist = d_occupancy + bricks + groups;
+    uint8_t* work = dist + bricks;
+    launch_dist<true>(s, d_occupancy, dist, nbx, nby, nbz, 0);
+    launch_dist<false>(s, dist, work, nbx, nby, nbz, 1);
+    launch_dist<false>(s, work, dist, nbx, nby, nbz, 2);
+    return vr::check_launch("vr_brick_volume: distance grid");
 }
 
 namespace {

@@ -10,8 +10,11 @@
 // lies in brick b; a voxel at (x, y, z) is a tap for base taps
 // (x - {0,1}, y - {0,1}, z - {0,1}), so it marks up to eight bricks.  A second
 // grid follows the first: one byte per 4 x 4 x 4 bricks (16^3 voxels), set
-// when any of its bricks is marked, so a ray can cross large empty regions in
-// long steps.
+// when any of its bricks is marked.  Then one byte per brick: the Chebyshev
+// distance, in bricks, to the nearest marked brick, capped at kDistCap (0 for
+// a marked brick): every brick within distance r - 1 of a brick whose byte is
+// r is empty, so a ray can leave that whole cube of bricks in one step.  A
+// last byte per brick is working storage of the distance passes.
 //
 // Pair variant: the same brick order, but element (x, y, z) holds the two x
 // taps (voxel x and voxel min(x + 1, nx - 1)), so a trilinear fetch reads
@@ -26,6 +29,7 @@ namespace vr {
 namespace bk {
 
 constexpr int kThreads = 256;      // threads of one slab group
+constexpr int kDistCap = VR_BRICK_DIST_CAP;   // cap of the brick distance grid (bricks)
 
 template <typename T>
 __device__ __forceinline__ bool nonzero(T v) { return v != (T)0; }
@@ -154,6 +158,63 @@ __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int 
             macro[((int64_t)(bzz >> 2) * nmy + (byy >> 2)) * nmx + (bx >> 2)] = 1;
         }
     }
+}
+
+// 8^3 bricks: row piece r = ((z * 8 nby) + y) * nbx + bx holds the 8 voxels
+// [8 bx, 8 bx + 8) of row (y, z) of the volume padded to whole bricks (0 past
+// its end), one brick row, stored with 16-byte vectors at element
+// ((z & 7) * 8 + (y & 7)) * 8 of brick (bx, y >> 3, z >> 3); the pieces
+// r < nbx * 8 nby * 8 nbz cover every brick.  Marks (bytes of 1, written by every piece that sees
+// a non-zero voxel, so overlapping writes agree): the piece's own brick, and
+// the brick below in x, y or z when the piece's first voxel, first row of a
+// brick or first slice of a brick reaches back into it, with the group marks
+// of each (4^3 bricks).
+template <typename T>
+__device__ inline void row8_body(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
+                                 T* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro,
+                                 int nmx, int nmy, int64_t r)
+{
+    const int bx = (int)(r % nbx);
+    const int64_t yz = r / nbx;
+    const int py = nby * 8;
+    const int y = (int)(yz % py), z = (int)(yz / py);
+    const bool rowok = y < ny && z < nz;
+    const T* row = src + ((int64_t)(rowok ? z : 0) * ny + (rowok ? y : 0)) * nx;
+    const int x0 = bx * 8;
+    T v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (rowok && x0 + e < nx) ? row[x0 + e] : (T)0;
+    const int64_t brick = ((int64_t)(z >> 3) * nby + (y >> 3)) * nbx + bx;
+    T* out = dst + (brick << 9) + (((z & 7) << 6) | ((y & 7) << 3));
+    using V = typename std::conditional<sizeof(T) == 2, uint4, float4>::type;
+    constexpr int kPerVec = 16 / (int)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < 8 / kPerVec; ++q) {
+        V w;
+        T* wt = reinterpret_cast<T*>(&w);
+#pragma unroll
+        for (int e = 0; e < kPerVec; ++e) wt[e] = v[q * kPerVec + e];
+        *reinterpret_cast<V*>(out + q * kPerVec) = w;
+    }
+    if (occ == nullptr) return;
+    bool any = false;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) any |= nonzero(v[e]);
+    if (!any) return;
+    const int by = y >> 3, bz = z >> 3;
+    const int xs[2] = {bx, (nonzero(v[0]) && bx > 0) ? bx - 1 : -1};
+    const int ys[2] = {by, ((y & 7) == 0 && by > 0) ? by - 1 : -1};
+    const int zs[2] = {bz, ((z & 7) == 0 && bz > 0) ? bz - 1 : -1};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (xs[a] >= 0 && ys[b] >= 0 && zs[c] >= 0) {
+                    occ[((int64_t)zs[c] * nby + ys[b]) * nbx + xs[a]] = 1;
+                    macro[((int64_t)(zs[c] >> 2) * nmy + (ys[b] >> 2)) * nmx + (xs[a] >> 2)] = 1;
+                }
 }
 
 }  // namespace bk

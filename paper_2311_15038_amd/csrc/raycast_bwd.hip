@@ -129,7 +129,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                 ig[a] = gr[a] != 0.0f ? 1.0f / gr[a] : 0.0f;
             }
             uint32_t cur_b = 0xFFFFFFFFu;
-            bool cur_full = true;
+            uint32_t cur_r = 0u;     // distance byte of brick cur_b (0: occupied)
             for (int k = 0; k < n;) {
                 const float len = (k < n - 1) ? S.step : last;
                 const float off = fmaf(0.5f, len, (float)k * S.step);
@@ -138,24 +138,16 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                     const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
                     if (b != cur_b) {
                         cur_b = b;
-                        cur_full = S.occ[b] != 0;
+                        cur_r = S.dist[b];
                     }
-                    if (!cur_full) {
+                    if (cur_r != 0u) {
                         // a run of samples whose eight taps are all 0: density 0, zero
                         // extinction and colour weight, so the colour, the transmittance and
                         // the density gradient are unchanged; each sample's only gradient is
                         // len * q to the first knot's extinction, added for the whole run
-                        const uint32_t m[3] = {c.x0 >> 4, c.y0 >> 4, c.z0 >> 4};
-                        const uint32_t mi = (m[2] * (uint32_t)S.nmy + m[1]) * (uint32_t)S.nmx + m[0];
-                        int next;
-                        if (S.occ[S.macro_off + mi] == 0) {
-                            const int nm[3] = {S.nmx, S.nmy, S.nmz};
-                            next = skip_to(S, u0, gr, ig, m, nm, 4, k, n);
-                        } else {
-                            const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                            const int nb[3] = {S.nbx, S.nby, S.nbz};
-                            next = skip_to(S, u0, gr, ig, bb, nb, 2, k, n);
-                        }
+                        // (the run leaves the cube of empty bricks the distance grid gives)
+                        const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
+                        const int next = skip_cube(S, u0, gr, ig, bb, cur_r, 2, k, n);
                         const float lsum = next < n ? (float)(next - k) * S.step
                                                     : fmaf((float)(n - 1 - k), S.step, last);
                         const float q = g.x * (Tr * tf_s[0].x - (I.x - Pr)) + g.y * (Tr * tf_s[0].y - (I.y - Pg)) +
@@ -273,6 +265,8 @@ extern "C" int vr_raycast_backward(const vr_volume* vol, const float* d_tf, cons
     // the occupancy of vr_brick_volume on the same grid, if given, lets the adjoint
     // pass over empty bricks (build_scene keeps it for the brick layouts only)
     S.occ = vol->occupancy;
+    S.dist = vol->occupancy ? vol->occupancy + (int64_t)S.nbx * S.nby * S.nbz + (int64_t)S.nmx * S.nmy * S.nmz
+                            : nullptr;
     VR_REQUIRE(d_rgba_fwd && d_grad_rgba && d_grad_density && d_grad_tf, VR_ERR_NULL,
                "vr_raycast_backward: NULL buffer");
     hipStream_t s = vr::as_stream(stream);

@@ -17,6 +17,16 @@ namespace rc {
 
 constexpr int kMaxViews = VR_MAX_VIEWS_PER_LAUNCH;
 
+// Brick layouts: log2 of the brick edge (4 or 8 voxels); the linear layout has none.
+template <int LAYOUT>
+struct Lay {
+    static constexpr bool bricked = LAYOUT != VR_LAYOUT_LINEAR;
+    static constexpr int bs = LAYOUT == VR_LAYOUT_BRICK8 ? 3 : 2;
+    static constexpr uint32_t edge = 1u << bs;
+    static constexpr uint32_t mask = edge - 1u;
+};
+inline int brick_shift(int layout) { return layout == VR_LAYOUT_BRICK8 ? 3 : 2; }
+
 struct View {
     float eye[3];   // perspective origin, or centre of the orthographic view
     float f[3];     // unit forward
@@ -32,11 +42,13 @@ struct Views {
 struct Scene {
     const void* data;
     const uint8_t* occ;     // brick occupancy or NULL
+    const uint8_t* dist;    // brick distance grid (with occ), or NULL: skip by 16^3 groups instead
     int nx, ny, nz;
-    int nbx, nby, nbz;      // 4^3 bricks per axis
-    int nmx, nmy, nmz;      // 16^3 groups of bricks per axis
+    int nbx, nby, nbz;      // bricks per axis (4^3 or 8^3 voxels)
+    int nmx, nmy, nmz;      // groups of 4^3 bricks per axis
     uint32_t macro_off;     // byte offset of the group occupancy
     float inv_sp[3];
+    float umax[3];          // n - 1 per axis: the last voxel centre in voxel coordinates
     float ext[3];
     int W, H;
     float aspect;
@@ -118,7 +130,7 @@ __device__ __forceinline__ float voxel<float>(const float* p, uint32_t i) { retu
 __device__ __forceinline__ float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
 
 // Offsets of the eight taps (x fastest: 000 100 010 110 001 101 011 111) of
-// the clamped tap corners, in the linear or the 4^3-brick layout.
+// the clamped tap corners, in the linear or a brick layout.
 template <int LAYOUT>
 __device__ __forceinline__ void tap_offsets(const Scene& S, uint32_t x0, uint32_t x1, uint32_t y0,
                                             uint32_t y1, uint32_t z0, uint32_t z1, uint32_t off[8])
@@ -130,10 +142,12 @@ __device__ __forceinline__ void tap_offsets(const Scene& S, uint32_t x0, uint32_
         ay0 = y0 * nx; ay1 = y1 * nx;
         az0 = z0 * nxy; az1 = z1 * nxy;
     } else {
-        const uint32_t row = (uint32_t)S.nbx << 6, slab = row * (uint32_t)S.nby;
-        ax0 = ((x0 >> 2) << 6) | (x0 & 3u); ax1 = ((x1 >> 2) << 6) | (x1 & 3u);
-        ay0 = (y0 >> 2) * row + ((y0 & 3u) << 2); ay1 = (y1 >> 2) * row + ((y1 & 3u) << 2);
-        az0 = (z0 >> 2) * slab + ((z0 & 3u) << 4); az1 = (z1 >> 2) * slab + ((z1 & 3u) << 4);
+        constexpr int B = Lay<LAYOUT>::bs;
+        constexpr uint32_t M = Lay<LAYOUT>::mask;
+        const uint32_t row = (uint32_t)S.nbx << (3 * B), slab = row * (uint32_t)S.nby;
+        ax0 = ((x0 >> B) << (3 * B)) | (x0 & M); ax1 = ((x1 >> B) << (3 * B)) | (x1 & M);
+        ay0 = (y0 >> B) * row + ((y0 & M) << B); ay1 = (y1 >> B) * row + ((y1 & M) << B);
+        az0 = (z0 >> B) * slab + ((z0 & M) << (2 * B)); az1 = (z1 >> B) * slab + ((z1 & M) << (2 * B));
     }
     off[0] = az0 + ay0 + ax0; off[1] = az0 + ay0 + ax1;
     off[2] = az0 + ay1 + ax0; off[3] = az0 + ay1 + ax1;
@@ -150,17 +164,16 @@ struct Cell {
 __device__ __forceinline__ Cell cell_at(const Scene& S, float px, float py, float pz)
 {
     Cell c;
-    const float ux = fmaf(px, S.inv_sp[0], -0.5f);
-    const float uy = fmaf(py, S.inv_sp[1], -0.5f);
-    const float uz = fmaf(pz, S.inv_sp[2], -0.5f);
+    const float ux = __builtin_amdgcn_fmed3f(fmaf(px, S.inv_sp[0], -0.5f), 0.0f, S.umax[0]);
+    const float uy = __builtin_amdgcn_fmed3f(fmaf(py, S.inv_sp[1], -0.5f), 0.0f, S.umax[1]);
+    const float uz = __builtin_amdgcn_fmed3f(fmaf(pz, S.inv_sp[2], -0.5f), 0.0f, S.umax[2]);
     const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
     c.wx = ux - fx;
     c.wy = uy - fy;
     c.wz = uz - fz;
-    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    c.x0 = (uint32_t)min(max(ix, 0), S.nx - 1); c.x1 = (uint32_t)min(max(ix + 1, 0), S.nx - 1);
-    c.y0 = (uint32_t)min(max(iy, 0), S.ny - 1); c.y1 = (uint32_t)min(max(iy + 1, 0), S.ny - 1);
-    c.z0 = (uint32_t)min(max(iz, 0), S.nz - 1); c.z1 = (uint32_t)min(max(iz + 1, 0), S.nz - 1);
+    c.x0 = (uint32_t)(int)fx; c.x1 = (uint32_t)min((int)c.x0 + 1, S.nx - 1);
+    c.y0 = (uint32_t)(int)fy; c.y1 = (uint32_t)min((int)c.y0 + 1, S.ny - 1);
+    c.z0 = (uint32_t)(int)fz; c.z1 = (uint32_t)min((int)c.z0 + 1, S.nz - 1);
     return c;
 }
 
@@ -269,25 +282,29 @@ __device__ __forceinline__ int step_count(float L, float step)
     return max(1, (int)ceilf(L / step));
 }
 
-// Index of the first sample that may leave an empty cell (a brick, sh = 2,
-// or a 16^3 group of bricks, sh = 4).  The base tap stays in cell (cx, cy,
-// cz) while u = u0 + s g lies in [cell << sh, (cell + 1) << sh) on every
-// axis; the first and last cells of an axis extend to infinity, since taps
-// are clamped.  Each bound is moved kSkipMarginVox into the cell, which
-// covers the rounding of the sample positions, and the sample-centre offset
-// is taken off in ray distance; ig holds 1/g (0 where g = 0).  Samples below
-// the returned index are in the cell; the sample at it is checked again.
-__device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const float g[3],
-                                       const float ig[3], const uint32_t cell[3], const int ncell[3],
-                                       int sh, int k, int n)
+// Index of the first sample that may leave an empty box of cells (cells of
+// 2^sh voxels: bricks, sh = 2, or 16^3 groups of bricks, sh = 4), cells lo..hi
+// per axis.  The base tap stays in the box while u = u0 + s g lies in
+// [lo << sh, (hi + 1) << sh) on every axis; a box that reaches the first or
+// last cell of an axis extends to infinity there, since taps are clamped.
+// Each bound is moved kSkipMarginVox into the box, which covers the rounding
+// of the sample positions, and the sample-centre offset is taken off in ray
+// distance; ig holds 1/g (0 where g = 0).  Samples below the returned index
+// are in the box; the sample at it is checked again.
+__device__ __forceinline__ int skip_span(const Scene& S, const float u0[3], const float g[3],
+                                         const float ig[3], const uint32_t lo[3], const uint32_t hi[3],
+                                         const int ncell[3], int sh, int k, int n)
 {
     float s_exit = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const bool up = g[a] > 0.0f;
-        const bool open = up ? ((int)cell[a] < ncell[a] - 1) : (g[a] < 0.0f && cell[a] > 0u);
-        const float bound = up ? (float)((cell[a] + 1u) << sh) - kSkipMarginVox
-                               : (float)(cell[a] << sh) + kSkipMarginVox;
+        const bool dn = g[a] < 0.0f;
+        const uint32_t c1 = up ? hi[a] + 1u : lo[a];
+        const float edge = (float)(c1 << sh);
+        const float bound = edge + (up ? -kSkipMarginVox : kSkipMarginVox);
+        const uint32_t open = ((uint32_t)up & (uint32_t)((int)hi[a] < ncell[a] - 1)) |
+                              ((uint32_t)dn & (uint32_t)(lo[a] > 0u));
         const float sa = (bound - u0[a]) * ig[a];
         s_exit = open ? fminf(s_exit, sa) : s_exit;
     }
@@ -295,6 +312,31 @@ __device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const 
     int next = n;
     if (lim < (float)n) next = (int)ceilf(lim);
     return min(max(next, k + 1), n);
+}
+
+// skip_span for a single cell.
+__device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const float g[3],
+                                       const float ig[3], const uint32_t cell[3], const int ncell[3],
+                                       int sh, int k, int n)
+{
+    return skip_span(S, u0, g, ig, cell, cell, ncell, sh, k, n);
+}
+
+// skip_span for the empty cube of bricks (of 2^sh voxels) around brick bb whose
+// distance byte is r >= 1: bricks within r - 1 of bb on every axis (clipped to
+// the grid).
+__device__ __forceinline__ int skip_cube(const Scene& S, const float u0[3], const float g[3],
+                                         const float ig[3], const uint32_t bb[3], uint32_t r, int sh, int k,
+                                         int n)
+{
+    const int nb[3] = {S.nbx, S.nby, S.nbz};
+    uint32_t lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = bb[a] >= r - 1u ? bb[a] - (r - 1u) : 0u;
+        hi[a] = bb[a] + (r - 1u);
+    }
+    return skip_span(S, u0, g, ig, lo, hi, nb, sh, k, n);
 }
 
 // Whether samples of empty bricks may be passed over: the volume is in the
@@ -332,12 +374,13 @@ struct Corners {
     uint32_t key_o, key_f;
 };
 
-template <bool WIDE, typename P>
+template <bool WIDE, typename P, int B = 2>
 __device__ __forceinline__ uint32_t base_offset(const Cell& c, uint32_t b)
 {
     constexpr uint32_t E = WIDE ? 1u : (uint32_t)sizeof(P);   // offsets in elements or bytes
-    const uint32_t in0 = ((c.z0 & 3u) << 4) | ((c.y0 & 3u) << 2) | (c.x0 & 3u);
-    return ((b << 6) | in0) * E;
+    constexpr uint32_t M = (1u << B) - 1u;
+    const uint32_t in0 = ((c.z0 & M) << (2 * B)) | ((c.y0 & M) << B) | (c.x0 & M);
+    return ((b << (3 * B)) | in0) * E;
 }
 
 // Element of a pair-layout volume at offset o (bytes, or elements when
@@ -388,14 +431,18 @@ __device__ __forceinline__ uint32_t clamp_flags(const Cell& c)
     return (c.x1 == c.x0 ? 1u : 0u) | (c.y1 == c.y0 ? 2u : 0u) | (c.z1 == c.z0 ? 4u : 0u);
 }
 
-template <typename T, bool WIDE>
+// Tap steps: one voxel inside a brick of edge e = 2^B; from a brick's last
+// layer to the next brick, e^3 - (e - 1) in x, a brick row less (e - 1) e in y,
+// a brick slab less (e - 1) e^2 in z.
+template <typename T, bool WIDE, int B = 2>
 __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict__ vol, const Cell& c,
                                              uint32_t o0, Corners& k)
 {
     constexpr uint32_t E = WIDE ? 1u : (uint32_t)sizeof(T);
-    const uint32_t dx = (c.x1 == c.x0) ? 0u : ((c.x0 & 3u) == 3u ? 61u * E : E);
-    const uint32_t dy = (c.y1 == c.y0) ? 0u : ((c.y0 & 3u) == 3u ? (S.row_e - 12u) * E : 4u * E);
-    const uint32_t dz = (c.z1 == c.z0) ? 0u : ((c.z0 & 3u) == 3u ? (S.slab_e - 48u) * E : 16u * E);
+    constexpr uint32_t e = 1u << B, M = e - 1u;
+    const uint32_t dx = (c.x1 == c.x0) ? 0u : ((c.x0 & M) == M ? (e * e * e - M) * E : E);
+    const uint32_t dy = (c.y1 == c.y0) ? 0u : ((c.y0 & M) == M ? (S.row_e - M * e) * E : e * E);
+    const uint32_t dz = (c.z1 == c.z0) ? 0u : ((c.z0 & M) == M ? (S.slab_e - M * e * e) * E : e * e * E);
     const uint32_t o2 = o0 + dy, o4 = o0 + dz, o6 = o4 + dy;
     k.v[0] = tap<T, WIDE>(vol, o0);
     k.v[1] = tap<T, WIDE>(vol, o0 + dx);
@@ -420,8 +467,10 @@ __device__ __forceinline__ float interp_corners(const Corners& k, const Cell& c)
 // Front-to-back march of the ray through pixel (i, j): returns its RGBA and,
 // with COUNT, adds to the counts of samples taken (cnt) and evaluated
 // (evals).  WIDE selects 64-bit addressing and full multiplies for volumes
-// of more than 2^24 bricks.
-template <typename T, int LAYOUT, bool COUNT, bool WIDE>
+// of more than 2^24 bricks.  Empty bricks are left by the cube of empty
+// bricks the distance grid gives (DIST, S.dist set), or else by their 16^3
+// group when that is empty too.
+template <typename T, int LAYOUT, bool COUNT, bool WIDE, bool DIST = true>
 __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* __restrict__ vol,
                                         const TfLds& tf, bool skip, int i, int j, uint32_t& cnt,
                                         uint32_t& evals)
@@ -437,10 +486,10 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
         g[a] = d[a] * S.inv_sp[a];
         ig[a] = g[a] != 0.0f ? 1.0f / g[a] : 0.0f;
     }
-    const bool skipping = skip && (LAYOUT == VR_LAYOUT_BRICK4 || LAYOUT == VR_LAYOUT_BRICK4_PAIRS);
+    const bool skipping = skip && Lay<LAYOUT>::bricked;
     float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t cur_b = 0xFFFFFFFFu;
-    bool cur_full = true;
+    uint32_t cur_r = 0u;         // distance byte of brick cur_b (0: occupied)
     Corners kc;                  // corners of the last sampled cell (consecutive samples share
     kc.key_o = 0xFFFFFFFFu;      // a cell about half the time at half-voxel steps)
     kc.key_f = 0xFFFFFFFFu;
@@ -450,27 +499,34 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
         const float off = fmaf(0.5f, len, (float)k * S.step);
         const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
         float sv;
-        if constexpr (LAYOUT == VR_LAYOUT_BRICK4 || LAYOUT == VR_LAYOUT_BRICK4_PAIRS) {
-            const uint32_t b = mul_idx<WIDE>(mul_idx<WIDE>(c.z0 >> 2, (uint32_t)S.nby) + (c.y0 >> 2),
-                                             (uint32_t)S.nbx) + (c.x0 >> 2);
+        if constexpr (Lay<LAYOUT>::bricked) {
+            constexpr int B = Lay<LAYOUT>::bs;
+            const uint32_t b = mul_idx<WIDE>(mul_idx<WIDE>(c.z0 >> B, (uint32_t)S.nby) + (c.y0 >> B),
+                                             (uint32_t)S.nbx) + (c.x0 >> B);
             if (skipping) {
                 if (b != cur_b) {
                     cur_b = b;
-                    cur_full = S.occ[b] != 0;
+                    cur_r = DIST ? (uint32_t)S.dist[b] : (S.occ[b] != 0 ? 0u : 1u);
                 }
-                if (!cur_full) {
-                    // empty brick: leave its 16^3 group if that is empty too, else the brick
-                    const uint32_t m[3] = {c.x0 >> 4, c.y0 >> 4, c.z0 >> 4};
-                    const uint32_t mi = mul_idx<WIDE>(mul_idx<WIDE>(m[2], (uint32_t)S.nmy) + m[1],
-                                                      (uint32_t)S.nmx) + m[0];
+                if (cur_r != 0u) {
                     int next;
-                    if (S.occ[S.macro_off + mi] == 0) {
-                        const int nm[3] = {S.nmx, S.nmy, S.nmz};
-                        next = skip_to(S, u0, g, ig, m, nm, 4, k, n);
+                    if constexpr (DIST) {
+                        // empty brick: leave the cube of empty bricks around it
+                        const uint32_t bb[3] = {c.x0 >> B, c.y0 >> B, c.z0 >> B};
+                        next = skip_cube(S, u0, g, ig, bb, cur_r, B, k, n);
                     } else {
-                        const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                        const int nb[3] = {S.nbx, S.nby, S.nbz};
-                        next = skip_to(S, u0, g, ig, bb, nb, 2, k, n);
+                        // empty brick: leave its group of 4^3 bricks if that is empty too, else the brick
+                        const uint32_t m[3] = {c.x0 >> (B + 2), c.y0 >> (B + 2), c.z0 >> (B + 2)};
+                        const uint32_t mi = mul_idx<WIDE>(mul_idx<WIDE>(m[2], (uint32_t)S.nmy) + m[1],
+                                                          (uint32_t)S.nmx) + m[0];
+                        if (S.occ[S.macro_off + mi] == 0) {
+                            const int nm[3] = {S.nmx, S.nmy, S.nmz};
+                            next = skip_to(S, u0, g, ig, m, nm, B + 2, k, n);
+                        } else {
+                            const uint32_t bb[3] = {c.x0 >> B, c.y0 >> B, c.z0 >> B};
+                            const int nb[3] = {S.nbx, S.nby, S.nbz};
+                            next = skip_to(S, u0, g, ig, bb, nb, B, k, n);
+                        }
                     }
                     if (COUNT) cnt += (uint32_t)(next - k);
                     k = next;
@@ -479,11 +535,11 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
             }
             constexpr bool PAIRS = LAYOUT == VR_LAYOUT_BRICK4_PAIRS;
             const uint32_t o0 = PAIRS ? base_offset<WIDE, typename vr::bk::PairOf<T>::type>(c, b)
-                                      : base_offset<WIDE, T>(c, b);
+                                      : base_offset<WIDE, T, B>(c, b);
             const uint32_t f = clamp_flags(c);
             if (o0 != kc.key_o || f != kc.key_f) {
                 if (PAIRS) load_corners_pairs<T, WIDE>(S, vol, c, o0, kc);
-                else load_corners<T, WIDE>(S, vol, c, o0, kc);
+                else load_corners<T, WIDE, B>(S, vol, c, o0, kc);
                 kc.key_o = o0;
                 kc.key_f = f;
             }
@@ -524,15 +580,17 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
     VR_REQUIRE(vol->dtype == VR_U16_NORM || vol->dtype == VR_F32, VR_ERR_DTYPE,
                "raycast: unknown dtype %d", vol->dtype);
     VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4 ||
-                   vol->layout == VR_LAYOUT_BRICK4_PAIRS,
+                   vol->layout == VR_LAYOUT_BRICK4_PAIRS || vol->layout == VR_LAYOUT_BRICK8,
                VR_ERR_RANGE, "raycast: unknown layout %d", vol->layout);
     VR_REQUIRE(vol->nx >= 1 && vol->ny >= 1 && vol->nz >= 1 && vol->nx < (1 << 30) &&
                    vol->ny < (1 << 30) && vol->nz < (1 << 30),
                VR_ERR_DIMS, "raycast: volume dims %lld x %lld x %lld", (long long)vol->nx,
                (long long)vol->ny, (long long)vol->nz);
-    const int64_t nb[3] = {(vol->nx + 3) / 4, (vol->ny + 3) / 4, (vol->nz + 3) / 4};
+    const int bs = brick_shift(vol->layout);
+    const int64_t be = int64_t(1) << bs, bvox = int64_t(1) << (3 * bs);   // brick edge and voxels
+    const int64_t nb[3] = {(vol->nx + be - 1) >> bs, (vol->ny + be - 1) >> bs, (vol->nz + be - 1) >> bs};
     const bool bricked = vol->layout != VR_LAYOUT_LINEAR;
-    const int64_t elems = bricked ? nb[0] * nb[1] * nb[2] * 64 : vol->nx * vol->ny * vol->nz;
+    const int64_t elems = bricked ? nb[0] * nb[1] * nb[2] * bvox : vol->nx * vol->ny * vol->nz;
     VR_REQUIRE(elems <= (int64_t)0xFFFFFFFFu, VR_ERR_DIMS,
                "raycast: volume of %lld elements exceeds 32-bit offsets", (long long)elems);
     for (int a = 0; a < 3; ++a)
@@ -570,23 +628,29 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
     S.nmy = (S.nby + 3) / 4;
     S.nmz = (S.nbz + 3) / 4;
     S.macro_off = (uint32_t)(nb[0] * nb[1] * nb[2]);
+    // the distance grid follows the bricks' and the groups' marks
+    S.dist = vol->occupancy ? vol->occupancy + nb[0] * nb[1] * nb[2] + (int64_t)S.nmx * S.nmy * S.nmz : nullptr;
     S.nx = (int)vol->nx;
     S.ny = (int)vol->ny;
     S.nz = (int)vol->nz;
     const int64_t n[3] = {vol->nx, vol->ny, vol->nz};
     for (int a = 0; a < 3; ++a) {
         S.inv_sp[a] = (float)(1.0 / vol->spacing[a]);
+        S.umax[a] = (float)(n[a] - 1);
         S.ext[a] = (float)((double)n[a] * vol->spacing[a]);
     }
-    S.row_e = (uint32_t)(nb[0] * 64);
-    S.slab_e = (uint32_t)(nb[0] * nb[1] * 64);
+    S.row_e = (uint32_t)(nb[0] * bvox);
+    S.slab_e = (uint32_t)(nb[0] * nb[1] * bvox);
     S.inv_step = 1.0f / o->step;
     S.skip_c = 0.5f * o->step + o->step * (1.0f / 512.0f);
-    if (!bricked) S.occ = nullptr;   // occupancy belongs to the brick layouts
+    if (!bricked) {                  // occupancy belongs to the brick layouts
+        S.occ = nullptr;
+        S.dist = nullptr;
+    }
     {   // 32-bit byte offsets and 24-bit brick-index products, unless the volume is too large
         const int64_t bricks = nb[0] * nb[1] * nb[2];
         const int64_t elem_bytes = (vol->dtype == VR_U16_NORM ? 2 : 4) * (vol->layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
-        S.wide = (bricks > (int64_t(1) << 24) || bricks * 64 * elem_bytes > (int64_t(1) << 32)) ? 1 : 0;
+        S.wide = (bricks > (int64_t(1) << 24) || bricks * bvox * elem_bytes > (int64_t(1) << 32)) ? 1 : 0;
     }
     S.view_hist = o->view_hist;
     S.W = o->width;

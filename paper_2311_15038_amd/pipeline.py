@@ -36,8 +36,9 @@ class PreviewConfig:
     fov_deg: float = 60.0
     ortho: bool = False
     ert_eps: float = 2.0 ** -14
-    bricked: bool = True            # render from the 4^3-brick layout
-    pairs: bool = False             # ... of x-tap pairs (two voxels per load, twice the memory)
+    bricked: bool = True            # render from a brick layout
+    brick_edge: int = 4             # ... of 4^3 or 8^3 voxels (see tune_brick_edge)
+    pairs: bool = False             # ... of x-tap pairs (4^3 only; two voxels per load, twice the memory)
     skip_empty: bool = True         # with the brick occupancy (exact)
     container: bool = False         # remove the sample container (Section III-B)
     container_radii: tuple | None = None   # (r_min, r_max); None: [min side / 8, min side / 2]
@@ -99,12 +100,12 @@ class PreviewPipeline:
             self.hollow_kept = torch.zeros(1, dtype=torch.int64, device=dev)
         self.render_vol = None
         if cfg.bricked:
-            nb, nocc = vr.vr_brick_count(rx, ry, rz)
+            layout = (vr.LAYOUT_BRICK4_PAIRS if cfg.pairs else
+                      vr.LAYOUT_BRICK8 if cfg.brick_edge == 8 else vr.LAYOUT_BRICK4)
+            nb, nel, nocc = vr.vr_brick_count_layout(layout, rx, ry, rz)
             occ = torch.empty(nocc, dtype=torch.uint8, device=dev) if cfg.skip_empty else None
-            per = 128 if cfg.pairs else 64
-            self.render_vol = vr.BrickedVolume(torch.empty(nb * per, dtype=torch.uint16, device=dev),
-                                               (rz, ry, rx), occ,
-                                               vr.LAYOUT_BRICK4_PAIRS if cfg.pairs else vr.LAYOUT_BRICK4)
+            self.render_vol = vr.BrickedVolume(torch.empty(nel, dtype=torch.uint16, device=dev),
+                                               (rz, ry, rx), occ, layout)
 
     def _atlas_arg(self):
         if self.atlas is None:
@@ -152,7 +153,8 @@ class PreviewPipeline:
             self.hollow(stream)
             src = self.hollow_level
         if self.render_vol is not None:
-            vr.vr_brick_volume(src, out=self.render_vol, stream=stream, pairs=self.cfg.pairs)
+            vr.vr_brick_volume(src, out=self.render_vol, stream=stream, pairs=self.cfg.pairs,
+                               edge=self.cfg.brick_edge)
             src = self.render_vol
         vr.vr_raycast(src, self.tf, self.cams, c.width, c.height, c.step,
                       ert_eps=c.ert_eps, out=self.frames, samples=self.samples if count else None,
@@ -184,7 +186,7 @@ class PreviewPipeline:
         src = level
         if self.render_vol is not None:
             out.append(("bricks", lambda: vr.vr_brick_volume(level, out=self.render_vol, stream=stream,
-                                                             pairs=c.pairs)))
+                                                             pairs=c.pairs, edge=c.brick_edge)))
             src = self.render_vol
         out.append(("raycast", lambda src=src: vr.vr_raycast(src, self.tf, self.cams, c.width, c.height,
                                                              c.step, ert_eps=c.ert_eps, out=self.frames,
@@ -208,3 +210,63 @@ class PreviewPipeline:
             at_in = self.levels[self.cfg.atlas_level - 1].numel() * 2 if separate_steps else 0
             at_out = self.atlas.numel() * 2
         return vol + top + vol + lv + at_in + at_out
+
+
+def tune_brick_edge(pipe: PreviewPipeline, reps: int = 3, use_cache: bool = True, log=None):
+    """Pick the brick size (4 or 8 voxels a side) of the rendered level for this
+    pipeline: times the brick copy plus the frames for each on the pipeline's own
+    level (run a step or `reduce` first) with HIP events, and keeps the faster.
+    Results are cached beside the batch tuner's, keyed by GPU architecture, level
+    shape, frame size and views.  Returns (edge, {edge: ms})."""
+    import json
+    import os
+
+    from . import batch as _batch
+
+    c = pipe.cfg
+    level = pipe.levels[c.render_level - 1]
+    arch = torch.cuda.get_device_properties(level.device).gcnArchName.split(":")[0]
+    key = f"{arch}|single|{'x'.join(map(str, level.shape))}|{c.width}x{c.height}x{len(pipe.cams)}"
+    path = _batch._cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        return int(cache[key]), {}
+    times = {}
+    for edge in (4, 8):
+        bv = vr.vr_brick_volume(level, edge=edge)
+        out = torch.empty_like(pipe.frames)
+
+        def run():
+            vr.vr_brick_volume(level, out=bv, edge=edge)
+            vr.vr_raycast(bv, pipe.tf, pipe.cams, c.width, c.height, c.step, ert_eps=c.ert_eps, out=out)
+
+        run()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        times[edge] = best
+        if log:
+            log(f"brick edge {edge}: {best:.3f} ms")
+        del bv, out
+    edge = min(times, key=times.get)
+    if use_cache:
+        cache[key] = edge
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return edge, times

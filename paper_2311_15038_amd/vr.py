@@ -23,9 +23,10 @@ CONTAINER_SCRATCH_BYTES = 32 << 20
 HOLLOW_MAX_THICKNESS = 8
 MAX_LEVELS = 4
 MAX_VIEWS_PER_LAUNCH = 48
+BRICK_DIST_CAP = 8
 RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
 U16_NORM, F32 = 0, 1
-LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_BRICK4_PAIRS = 0, 1, 2
+LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_BRICK4_PAIRS, LAYOUT_BRICK8 = 0, 1, 2, 3
 ERRORS = {-1: "VR_ERR_NULL", -2: "VR_ERR_DIMS", -3: "VR_ERR_RANGE", -4: "VR_ERR_DTYPE",
           -5: "VR_ERR_HIP", -6: "VR_ERR_UNSUPPORTED", -7: "VR_ERR_WORKSPACE"}
 
@@ -64,12 +65,16 @@ class vr_batch_config(C.Structure):
                 ("rule_param", C.c_int32), ("top_slices", C.c_int32), ("wave_w", C.c_int32),
                 ("wave_h", C.c_int32), ("waves_x", C.c_int32), ("hist_task_voxels", C.c_int64),
                 ("down_tiles_per_task", C.c_int32), ("slabs_per_task", C.c_int32),
-                ("render_tiles_per_task", C.c_int32)]
+                ("render_tiles_per_task", C.c_int32), ("brick_edge", C.c_int32)]
 
 
 class vr_render_opts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("step", C.c_float),
-                ("ert_eps", C.c_float), ("bg", C.c_float * 4), ("view_hist", C.c_void_p)]
+                ("ert_eps", C.c_float), ("bg", C.c_float * 4), ("view_hist", C.c_void_p),
+                ("flags", C.c_uint32)]
+
+
+RENDER_STAGED = 1
 
 
 _lib = None
@@ -107,6 +112,8 @@ def lib():
         L.vr_frame_entropy.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.vr_entropy_from_counts.argtypes = [vp, i32, i64, vp, vp, vp]
         L.vr_brick_count.argtypes = [i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.vr_brick_count_layout.argtypes = [i32, i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                            C.POINTER(C.c_int64)]
         PB = C.POINTER(vr_batch_item)
         PC = C.POINTER(vr_batch_config)
         L.vr_batch_workspace_size.argtypes = [PB, i32, PC, C.POINTER(C.c_int64)]
@@ -123,7 +130,7 @@ def lib():
                      "vr_unbrick_volume", "vr_frame_entropy", "vr_entropy_from_counts", "vr_container_workspace_size",
                      "vr_find_container", "vr_find_container_noalloc", "vr_remove_container", "vr_histogram_in_disc",
                      "vr_threshold_downsample_in_disc", "vr_hollow",
-                     "vr_brick_count", "vr_histogram_with_top", "vr_batch_workspace_size",
+                     "vr_brick_count", "vr_brick_count_layout", "vr_histogram_with_top", "vr_batch_workspace_size",
                      "vr_batch_plan_create", "vr_batch_launch", "vr_batch_capture", "vr_batch_status",
                      "vr_batch_item_outputs", "vr_batch_plan_destroy"):
             getattr(L, name).restype = C.c_int
@@ -349,6 +356,13 @@ def vr_pack_slicemap(level, tiles_x, tiles_y, out_bits=16, out=None, stream=None
 
 
 # ------------------------------------------------------------------ rendering
+def vr_brick_count_layout(layout, nx, ny, nz):
+    """-> (bricks, elements of the bricked volume, bytes of the occupancy grids) of a brick layout."""
+    n, e, o = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    _check(lib().vr_brick_count_layout(int(layout), nx, ny, nz, C.byref(n), C.byref(e), C.byref(o)))
+    return int(n.value), int(e.value), int(o.value)
+
+
 def vr_brick_count(nx, ny, nz):
     """-> (number of 4^3 bricks, bytes of the occupancy grids)."""
     n, o = C.c_int64(0), C.c_int64(0)
@@ -357,8 +371,8 @@ def vr_brick_count(nx, ny, nz):
 
 
 class BrickedVolume:
-    """A volume in a brick render layout (4^3 bricks, or 4^3 bricks of x-tap
-    pairs), with its occupancy grid (or None)."""
+    """A volume in a brick render layout (4^3 bricks, 4^3 bricks of x-tap pairs,
+    or 8^3 bricks), with its occupancy grid (or None)."""
 
     def __init__(self, data, shape, occupancy=None, layout=None):
         self.data, self.shape, self.occupancy = data, tuple(shape), occupancy
@@ -367,23 +381,25 @@ class BrickedVolume:
         self.device = data.device
 
 
-def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False) -> BrickedVolume:
-    """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy);
-    with pairs, into the layout of x-tap pairs (twice the memory)."""
+def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False, edge=4) -> BrickedVolume:
+    """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy):
+    bricks of `edge` (4 or 8) voxels; with pairs, the 4^3 layout of x-tap pairs
+    (twice the memory)."""
     nz, ny, nx = src.shape
-    nb, nocc = vr_brick_count(nx, ny, nz)
     dt = U16_NORM if src.dtype in _U16 else F32
-    layout = LAYOUT_BRICK4_PAIRS if pairs else LAYOUT_BRICK4
-    per = 128 if pairs else 64                      # voxels stored per brick
+    if edge not in (4, 8) or (pairs and edge != 4):
+        raise ValueError("bricks are 4^3 (plain or pairs) or 8^3")
+    layout = LAYOUT_BRICK4_PAIRS if pairs else (LAYOUT_BRICK8 if edge == 8 else LAYOUT_BRICK4)
+    nb, nel, nocc = vr_brick_count_layout(layout, nx, ny, nz)
     if out is None:
-        data = torch.empty(nb * per, dtype=src.dtype, device=src.device)
+        data = torch.empty(nel, dtype=src.dtype, device=src.device)
         occ = torch.empty(nocc, dtype=torch.uint8, device=src.device) if with_occupancy else None
         out = BrickedVolume(data, (nz, ny, nx), occ, layout)
     if out.layout != layout:
         raise ValueError("out has a different brick layout")
     occp = None if out.occupancy is None else _dev(out.occupancy, "occupancy", torch.uint8, nocc)
     _check(lib().vr_brick_volume(_dev(src, "src", (*_U16, torch.float32)), dt, layout, nx, ny, nz,
-                                 _dev(out.data, "bricked", src.dtype, nb * per), occp,
+                                 _dev(out.data, "bricked", src.dtype, nel), occp,
                                  _stream(stream)))
     return out
 
@@ -408,7 +424,8 @@ def make_volume(data, spacing=(1.0, 1.0, 1.0)):
     """vr_volume for a uint16 (normalised) or float32 tensor [nz][ny][nx], or a BrickedVolume."""
     if isinstance(data, BrickedVolume):
         t, layout, shape = data.data, data.layout, data.shape
-        occ = None if data.occupancy is None else _dev(data.occupancy, "occupancy").value
+        occ = None if data.occupancy is None else _dev(
+            data.occupancy, "occupancy", torch.uint8, vr_brick_count_layout(layout, *shape[::-1])[2]).value
     else:
         t, layout, shape, occ = data, LAYOUT_LINEAR, data.shape, None
     if t.dtype in _U16:
@@ -438,20 +455,21 @@ def make_cameras(cams):
     return arr, len(cams)
 
 
-def make_opts(width, height, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0), view_hist=None):
+def make_opts(width, height, step, ert_eps=2.0 ** -14, bg=(0.0, 0.0, 0.0, 0.0), view_hist=None, flags=0):
     return vr_render_opts(int(width), int(height), float(step), float(ert_eps),
-                          (C.c_float * 4)(*[float(b) for b in bg]), view_hist)
+                          (C.c_float * 4)(*[float(b) for b in bg]), view_hist, int(flags))
 
 
 def vr_raycast(data, tf, cams, width, height, step, spacing=(1.0, 1.0, 1.0), ert_eps=2.0 ** -14,
-               bg=(0.0, 0.0, 0.0, 0.0), out=None, samples=None, stream=None, view_hist=None):
+               bg=(0.0, 0.0, 0.0, 0.0), out=None, samples=None, stream=None, view_hist=None, staged=False):
     """RGBA frames [V][H][W][4] float32; `samples` (int64[2]) accumulates the sample
     counts: [0] samples taken before early termination, [1] samples evaluated;
-    `view_hist` (int32 [V][256]) receives the grey-value counts of the frames."""
+    `view_hist` (int32 [V][256]) receives the grey-value counts of the frames;
+    `staged` selects the depth-window march with LDS staging (VR_RENDER_STAGED)."""
     vol = make_volume(data, spacing)
     ca, nv = make_cameras(cams)
     vh = None if view_hist is None else _dev(view_hist, "view_hist", torch.int32, nv * 256).value
-    opts = make_opts(width, height, step, ert_eps, bg, vh)
+    opts = make_opts(width, height, step, ert_eps, bg, vh, RENDER_STAGED if staged else 0)
     if out is None:
         out = torch.empty((nv, height, width, 4), dtype=torch.float32, device=data.device)
     sp = None if samples is None else _dev(samples, "samples", torch.int64, 2)
@@ -503,7 +521,7 @@ def vr_raycast_backward(data, tf, cams, width, height, step, rgba_fwd, grad_rgba
     (with it, runs of samples in empty bricks are not marched)."""
     vol = make_volume(data, spacing)
     if occupancy is not None:
-        vol.occupancy = _dev(occupancy, "occupancy", torch.uint8).value
+        vol.occupancy = _dev(occupancy, "occupancy", torch.uint8, vr_brick_count(*vol_shape(data)[::-1])[1]).value
     ca, nv = make_cameras(cams)
     opts = make_opts(width, height, step, ert_eps, bg)
     n = nv * height * width * 4

@@ -106,7 +106,15 @@ def test_brick_validation_on_the_host(lib):
     assert lib.vr_unbrick_volume(p, vr.U16_NORM, 8, 0, 8, p, None) == -2
     n, o = C.c_int64(0), C.c_int64(0)
     assert lib.vr_brick_count(9, 5, 4, C.byref(n), C.byref(o)) == 0
-    assert n.value == 3 * 2 * 1 and o.value == 6 + 1
+    # marks, group marks, distance grid and its working bytes
+    assert n.value == 3 * 2 * 1 and o.value == 6 + 1 + 6 + 6
+    e = C.c_int64(0)
+    assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK8, 9, 5, 17, C.byref(n), C.byref(e), C.byref(o)) == 0
+    assert n.value == 2 * 1 * 3 and e.value == 6 * 512 and o.value == 3 * 6 + 1
+    assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK4_PAIRS, 9, 5, 4, C.byref(n), C.byref(e), None) == 0
+    assert n.value == 6 and e.value == 6 * 128
+    assert lib.vr_brick_count_layout(vr.LAYOUT_LINEAR, 9, 5, 4, C.byref(n), None, None) == -3
+    assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK8, 0, 5, 4, C.byref(n), None, None) == -2
 
 
 def test_container_validation_on_the_host(lib):
@@ -138,6 +146,8 @@ def test_container_validation_on_the_host(lib):
     assert b.value <= vr.CONTAINER_SCRATCH_BYTES                                 # 1024^2 slices fit
     m = re.search(r"#define VR_CONTAINER_SCRATCH_BYTES \((\d+)ll << (\d+)\)", open(HEADER).read())
     assert m and int(m.group(1)) << int(m.group(2)) == vr.CONTAINER_SCRATCH_BYTES
+    m = re.search(r"#define VR_BRICK_DIST_CAP (\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == vr.BRICK_DIST_CAP
     assert lib.vr_remove_container(None, 4, 4, 4, p, None) == -1
     assert lib.vr_remove_container(p, 4, 0, 4, p, None) == -2
     assert lib.vr_histogram_in_disc(p, 4, 4, 4, 5, p, p, p, None) == -3

@@ -59,12 +59,12 @@ def test_batch_matches_single_volume(volumes):
     b.close()
 
 
-@pytest.mark.parametrize("hist_task_voxels", [4 << 20, 8192])
-def test_batch_matches_oracle(volumes, hist_task_voxels):
-    banner(f"batch vs oracle, {hist_task_voxels} voxels per histogram task")
+@pytest.mark.parametrize("hist_task_voxels,brick_edge", [(4 << 20, 4), (8192, 4), (4 << 20, 8)])
+def test_batch_matches_oracle(volumes, hist_task_voxels, brick_edge):
+    banner(f"batch vs oracle, {hist_task_voxels} voxels per histogram task, {brick_edge}^3 bricks")
     W = H = 24
     b = VB.BatchPreview(volumes[:3], n_views=2, width=W, height=H,
-                        tuning=dict(hist_task_voxels=hist_task_voxels))
+                        tuning=dict(hist_task_voxels=hist_task_voxels, brick_edge=brick_edge))
     b.launch()
     torch.cuda.synchronize()
     tf = synth.default_tf().astype(np.float64)
@@ -111,7 +111,8 @@ def test_launch_shape_does_not_change_results(volumes):
     for t in [dict(wave_w=8, wave_h=8, waves_x=4), dict(wave_w=16, wave_h=4, waves_x=2, hist_task_voxels=1 << 20,
                                                        down_tiles_per_task=3, slabs_per_task=5),
               dict(wave_w=4, wave_h=16, waves_x=8, down_tiles_per_task=64, slabs_per_task=200),
-              dict(hist_task_voxels=8192, down_tiles_per_task=1, slabs_per_task=1)]:
+              dict(hist_task_voxels=8192, down_tiles_per_task=1, slabs_per_task=1),
+              dict(brick_edge=8), dict(brick_edge=8, slabs_per_task=1, wave_w=16, wave_h=4, waves_x=2)]:
         b = VB.BatchPreview(volumes, n_views=2, width=35, height=29, tuning=t)
         b.launch()
         torch.cuda.synchronize()
@@ -128,8 +129,10 @@ def test_tuner_runs(volumes, tmp_path, monkeypatch):
     banner("tuner")
     monkeypatch.setenv("VR_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
     best, timings = VB.tune(volumes[:2], n_views=2, width=32, height=32)
-    # every render tile is timed; task sizes too (a repeat of a timed configuration counts once)
-    assert len(VB.RENDER_TILES) <= len(timings) <= len(VB.RENDER_TILES) + len(VB.TASK_SIZES)
+    # every render tile is timed; brick sizes and task sizes too (a repeat of a timed
+    # configuration counts once)
+    assert len(VB.RENDER_TILES) <= len(timings) <= len(VB.RENDER_TILES) + len(VB.BRICK_EDGES) + len(VB.TASK_SIZES)
+    assert best["brick_edge"] in VB.BRICK_EDGES
     assert json.loads(min(timings, key=timings.get)) == best
     again, t2 = VB.tune(volumes[:2], n_views=2, width=32, height=32)
     assert again == best and t2 == {}              # served from the cache

@@ -131,6 +131,20 @@ def test_headline_sample_count(full, oracle_frames):
     assert int(pipe.samples[1].item()) <= n_gpu           # evaluated <= taken
 
 
+def test_staged_march_at_full_size(full):
+    """The depth-window march with LDS staging renders the step's 36 frames bit for
+    bit like the gather march the step uses."""
+    from paper_2311_15038_amd import vr
+    pipe, *_ = full
+    c = pipe.cfg
+    banner("fullsize: staged march")
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev())
+    img = vr.vr_raycast(pipe.render_vol, pipe.tf, pipe.cams, c.width, c.height, c.step, ert_eps=c.ert_eps,
+                        samples=cnt, staged=True)
+    assert torch.equal(img, pipe.frames)
+    assert torch.equal(cnt, pipe.samples)
+
+
 @pytest.mark.parametrize("shift", [8, 0])
 def test_otsu_and_its_full_histogram(full, shift):
     """Algorithms 1 and 2 on the full volume's histogram, on 256 (8-bit) and 65536 bins."""

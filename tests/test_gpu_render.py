@@ -135,25 +135,44 @@ def test_raycast_rejects_bad_args(level1):
 
 
 # ------------------------------------------------------------ brick render layout
-def _brick_ref(a):
-    """The 4^3 brick layout and the dilated occupancy, written out with NumPy."""
+def _brick_ref(a, e=4):
+    """The brick layout (bricks of e^3 voxels) and the dilated occupancy, written out
+    with NumPy."""
     nz, ny, nx = a.shape
-    nbz, nby, nbx = (nz + 3) // 4, (ny + 3) // 4, (nx + 3) // 4
-    pad = np.zeros((nbz * 4, nby * 4, nbx * 4), dtype=a.dtype)
+    nbz, nby, nbx = (nz + e - 1) // e, (ny + e - 1) // e, (nx + e - 1) // e
+    pad = np.zeros((nbz * e, nby * e, nbx * e), dtype=a.dtype)
     pad[:nz, :ny, :nx] = a
-    br = pad.reshape(nbz, 4, nby, 4, nbx, 4).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
+    br = pad.reshape(nbz, e, nby, e, nbx, e).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
     occ = np.zeros((nbz, nby, nbx), dtype=np.uint8)
     for z, y, x in np.argwhere(a != 0):
         for zz in (z - 1, z):
             for yy in (y - 1, y):
                 for xx in (x - 1, x):
                     if zz >= 0 and yy >= 0 and xx >= 0:
-                        occ[zz // 4, yy // 4, xx // 4] = 1
+                        occ[zz // e, yy // e, xx // e] = 1
     mz, my, mx = (nbz + 3) // 4, (nby + 3) // 4, (nbx + 3) // 4
     pad = np.zeros((mz * 4, my * 4, mx * 4), dtype=np.uint8)
     pad[:nbz, :nby, :nbx] = occ
     macro = pad.reshape(mz, 4, my, 4, mx, 4).max(axis=(1, 3, 5))
-    return br, np.concatenate([occ.reshape(-1), macro.reshape(-1)])
+    # Chebyshev distance over bricks to the nearest marked brick, capped (brute force)
+    cap = vr.BRICK_DIST_CAP
+    marked = np.argwhere(occ != 0)
+    grid = np.indices(occ.shape).reshape(3, -1).T
+    if len(marked):
+        dist = np.abs(grid[:, None, :] - marked[None, :, :]).max(axis=2).min(axis=1)
+    else:
+        dist = np.full(len(grid), cap)
+    dist = np.minimum(dist, cap).astype(np.uint8)
+    return br, np.concatenate([occ.reshape(-1), macro.reshape(-1), dist])
+
+
+def _occ_parts(occ_t, shape, layout=vr.LAYOUT_BRICK4):
+    """The marks, group marks and distance grid of an occupancy tensor (the working
+    bytes after them are left out)."""
+    nz, ny, nx = shape
+    nb, _, nocc = vr.vr_brick_count_layout(layout, nx, ny, nz)
+    assert occ_t.numel() == nocc
+    return occ_t.cpu().numpy()[:nocc - nb]
 
 
 # nx a multiple of 4 takes whole-row vector loads: (8, 8, 8), (7, 5, 12), (13, 30, 64)
@@ -171,11 +190,50 @@ def test_brick_layout_and_occupancy(shape):
     br, occ = _brick_ref(a)
     got = bv.data.cpu().view(torch.int16).numpy().view(np.uint16)
     assert (got == br).all()
-    assert (bv.occupancy.cpu().numpy() == occ).all()
+    assert (_occ_parts(bv.occupancy, shape) == occ).all()
     f = a.astype(np.float32) / 7.0
     bf = vr.vr_brick_volume(torch.from_numpy(f).to(dev()))
     assert (bf.data.cpu().numpy() == _brick_ref(f)[0]).all()
-    assert (bf.occupancy.cpu().numpy() == occ).all()
+    assert (_occ_parts(bf.occupancy, shape) == occ).all()
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 120), (9, 70, 33)])
+def test_brick_distance_grid_far_from_anything(shape):
+    """Two non-zero voxels in a large empty volume: distances from 0 up to the cap,
+    against brute force (and an empty volume, all at the cap)."""
+    banner(f"brick distance grid {shape}")
+    a = np.zeros(shape, dtype=np.uint16)
+    a[1, 2, 3] = 500
+    a[-2, -3, -5] = 65535
+    bv = vr.vr_brick_volume(to_dev_u16(a))
+    ref = _brick_ref(a)[1]
+    got = _occ_parts(bv.occupancy, shape)
+    assert (got == ref).all()
+    nb = vr.vr_brick_count(*shape[::-1])[0]
+    assert got[-nb:].max() == vr.BRICK_DIST_CAP and (got[-nb:] == 0).sum() >= 2
+    e = vr.vr_brick_volume(to_dev_u16(np.zeros(shape, dtype=np.uint16)))
+    assert (_occ_parts(e.occupancy, shape)[-nb:] == vr.BRICK_DIST_CAP).all()
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (17, 40, 70)])
+def test_brick8_layout_and_occupancy(shape):
+    """8^3 bricks: layout, marks, group marks and distance grid against NumPy."""
+    banner(f"brick8 layout {shape}")
+    rng = np.random.default_rng(35)
+    a = np.zeros(shape, dtype=np.uint16)
+    m = rng.random(shape) < 0.005
+    a[m] = rng.integers(1, 65536, size=int(m.sum()))
+    a[0, 0, 0] = 7
+    a[-1, -1, -1] = 9
+    bv = vr.vr_brick_volume(to_dev_u16(a), edge=8)
+    assert bv.layout == vr.LAYOUT_BRICK8
+    br, occ = _brick_ref(a, 8)
+    assert (bv.data.cpu().view(torch.int16).numpy().view(np.uint16) == br).all()
+    assert (_occ_parts(bv.occupancy, shape, vr.LAYOUT_BRICK8) == occ).all()
+    f = a.astype(np.float32) / 7.0
+    bf = vr.vr_brick_volume(torch.from_numpy(f).to(dev()), edge=8)
+    assert (bf.data.cpu().numpy() == _brick_ref(f, 8)[0]).all()
+    assert (_occ_parts(bf.occupancy, shape, vr.LAYOUT_BRICK8) == occ).all()
 
 
 def test_brick_layout_from_unaligned_source():
@@ -192,7 +250,7 @@ def test_brick_layout_from_unaligned_source():
     bv = vr.vr_brick_volume(src)
     br, occ = _brick_ref(a)
     assert (bv.data.cpu().view(torch.int16).numpy().view(np.uint16) == br).all()
-    assert (bv.occupancy.cpu().numpy() == occ).all()
+    assert (_occ_parts(bv.occupancy, shape) == occ).all()
     f = torch.zeros(a.size + 8, dtype=torch.float32, device=dev())
     f[2:2 + a.size] = torch.from_numpy(a.reshape(-1).astype(np.float32) / 5.0).to(dev())
     fs = f[2:2 + a.size].view(shape)
@@ -222,7 +280,7 @@ def test_pair_layout(shape):
     bv = vr.vr_brick_volume(to_dev_u16(a), pairs=True)
     got = bv.data.cpu().view(torch.int16).numpy().view(np.uint16)
     assert (got == _pairs_ref(a)).all()
-    assert (bv.occupancy.cpu().numpy() == _brick_ref(a)[1]).all()
+    assert (_occ_parts(bv.occupancy, shape) == _brick_ref(a)[1]).all()
     f = a.astype(np.float32) / 3.0
     bf = vr.vr_brick_volume(torch.from_numpy(f).to(dev()), pairs=True)
     assert (bf.data.cpu().numpy() == _pairs_ref(f)).all()
@@ -260,6 +318,12 @@ def test_brick_and_skip_bit_identical(level1, shape):
     bv.occupancy = None
     noskip = vr.vr_raycast(bv, tf, cams, 45, 38, 0.5, samples=c2)
     assert torch.equal(lin, noskip) and torch.equal(lin, skip)
+    b8 = vr.vr_brick_volume(v, edge=8)
+    c8 = torch.zeros(2, dtype=torch.int64, device=dev())
+    assert torch.equal(lin, vr.vr_raycast(b8, tf, cams, 45, 38, 0.5, samples=c8))
+    assert c8[0].item() == c0[0].item() and c8[1].item() <= c8[0].item()
+    b8.occupancy = None
+    assert torch.equal(lin, vr.vr_raycast(b8, tf, cams, 45, 38, 0.5))
     pv = vr.vr_brick_volume(v, pairs=True)
     c3 = torch.zeros(2, dtype=torch.int64, device=dev())
     assert torch.equal(lin, vr.vr_raycast(pv, tf, cams, 45, 38, 0.5, samples=c3))
@@ -324,3 +388,39 @@ def test_skip_disabled_when_density_zero_is_not_empty(level1):
     assert torch.equal(lin, br)
     ref, _ = R.render(level1, (1, 1, 1), tf.astype(np.float64), cams, 32, 32, 0.5)
     assert np.abs(br.cpu().numpy() - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (37, 60, 83), (70, 33, 81)])
+def test_staged_march_bit_identical(level1, shape):
+    """The depth-window march with LDS staging gives the gather march's frames, sample
+    counts and grey-value counts bit for bit (perspective and orthographic views, a
+    sparse volume with empty space, odd shapes, background)."""
+    banner(f"staged march == gather march {shape}")
+    a = level1 if shape == (64, 64, 64) else _sparse_volume(shape, 7)
+    nz, ny, nx = a.shape
+    tf = _tf_dev(synth.default_tf(sigma_scale=3.0))
+    cams = np.concatenate([synth.turntable_cameras(nx, ny, nz, n_views=9),
+                           synth.front_ortho_camera(nx, ny, nz)])
+    bv = vr.vr_brick_volume(to_dev_u16(a))
+    outs = []
+    for staged in (False, True):
+        cnt = torch.zeros(2, dtype=torch.int64, device=dev())
+        vh = torch.zeros((len(cams), 256), dtype=torch.int32, device=dev())
+        img = vr.vr_raycast(bv, tf, cams, 45, 38, 0.5, bg=BG, samples=cnt, view_hist=vh, staged=staged)
+        outs.append((img, cnt, vh))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][2], outs[1][2])
+
+
+def test_staged_march_rejects_other_volumes(level1):
+    v = to_dev_u16(level1)
+    tf = _tf_dev(synth.default_tf())
+    cam = synth.front_ortho_camera(64, 64, 64)
+    with pytest.raises(vr.VrError):
+        vr.vr_raycast(v, tf, cam, 8, 8, 0.5, staged=True)                 # linear layout
+    with pytest.raises(vr.VrError):
+        vr.vr_raycast(vr.vr_brick_volume(v, with_occupancy=False), tf, cam, 8, 8, 0.5, staged=True)
+    f = torch.from_numpy(level1.astype(np.float32) / 65535.0).to(dev())
+    with pytest.raises(vr.VrError):
+        vr.vr_raycast(vr.vr_brick_volume(f), tf, cam, 8, 8, 0.5, staged=True)
