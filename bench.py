@@ -33,6 +33,15 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32, published
 # index 2, four TF lerps 12, extinction + exp + alpha 3, compositing 8.
 FLOPS_PER_SAMPLE = 62
 METRIC = "Gsamples/s ray casting + GB/s reduction vs HBM peak; fwd+bwd, batched vs plain"
+# FP32 operations of one evaluated sample of the adjoint (FMA = 2): the forward
+# sample again (62); the colour and extinction gradients of the sample, T_{i+1} and
+# len (g . (T_{i+1} rgb - (I - P_i)) + g_a (1 - I_a)) and g T_i alpha (20); the two
+# TF knots' shares (17); the density gradient through the TF slope (12); the
+# trilinear weights of the eight taps and their running sums (31).
+ADJ_FLOPS_PER_SAMPLE = 142
+# Memory-side atomic requests of one adjoint launch on the fit's 256^3 grid, per
+# evaluated sample, from rocprofv3 counters (see profiles/); None until measured.
+ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": None}
 
 # HBM bytes of one launch of the dominant kernel (raycast_fwd on this step),
 # FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of
@@ -44,7 +53,7 @@ RAYCAST_TRAFFIC = {"fetch_kib": 2249506, "write_kib": 156652, "fetch_scale": 104
                    "write_scale": 1048576 / 1048576, "sources_sha256_16": "733e972dd5099254"}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
-RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "brick_dev.h", "common.h", "entropy_dev.h")
+RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "raycast_staged.h", "brick_dev.h", "common.h", "entropy_dev.h")
 
 
 # The paper's own timings (other hardware, other workloads): context beside
@@ -94,6 +103,11 @@ def run_gpu(steps, warmup):
     torch.cuda.synchronize()
     log(f"generated 1024^3 volume in {time.time() - t0:.1f} s")
     pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=dev)
+    # the brick size of the rendered level, picked by timing both on this step's level
+    pipe.step(vol)
+    edge, edge_ms = P.tune_brick_edge(pipe, use_cache=False, log=log)
+    if edge != pipe.cfg.brick_edge:
+        pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(brick_edge=edge), device=dev)
 
     # sample count of one step (same every step: deterministic)
     pipe.samples.zero_()
@@ -128,7 +142,17 @@ def run_gpu(steps, warmup):
     T = int(pipe.result[0].item())
     best_view = int(pipe.best_view.item())
     best_entropy = float(pipe.view_entropy[best_view].item())
+    # the depth-window march with LDS staging, on a 4^3-brick copy of the same level
+    from paper_2311_15038_amd import vr
+    c = pipe.cfg
+    b4 = pipe.render_vol if pipe.render_vol.layout == vr.LAYOUT_BRICK4 else vr.vr_brick_volume(pipe.levels[0])
+    staged_out = torch.empty_like(pipe.frames)
+    staged_ms = _median_ms(lambda: vr.vr_raycast(b4, pipe.tf, pipe.cams, c.width, c.height, c.step,
+                                                 ert_eps=c.ert_eps, out=staged_out, staged=True), 3)
+    staged_same = bool(torch.equal(staged_out, pipe.frames))
     out = {
+        "render_tuning": {"brick_edge": edge, "ms_bricks_plus_frames": {str(k): v for k, v in edge_ms.items()}},
+        "raycast_staged": {"ms": staged_ms, "frames_identical": staged_same},
         "samples_per_step": samples,
         "evaluated_per_step": evaluated,
         "ms_per_step": ms_step,
@@ -202,7 +226,31 @@ def run_fwd_bwd(pipe, steps=200):
         torch.cuda.synchronize()
         fwd_ms = fe[0].elapsed_time(fe[1]) / 5
     n_fwd = int(cnt[0].item())
-    return {"ms_per_iter": it_ms, "fwd_ms": fwd_ms, "iter_over_fwd": it_ms / fwd_ms,
+    n_eval = int(cnt[1].item())
+    # the adjoint alone (one vr_raycast_backward on the forward's bricked copy), against the
+    # FP32 ALU peak (ADJ_FLOPS_PER_SAMPLE per evaluated sample) and the HBM peak (its
+    # algorithmic bytes: the grid, its occupancy, the frames and their gradient read once,
+    # the density gradient read and written once)
+    with torch.no_grad():
+        fwd_out, src = VA.render_forward(dens.detach(), tfp.detach(), cams, 256, 256, 1.0, (2.0, 2.0, 2.0),
+                                         with_source=True)
+        grad_out = torch.full_like(fwd_out, 1e-3)
+        g_b = torch.zeros_like(src.data)
+        g_tf = torch.zeros_like(tfp)
+        bwd_ms = _median_ms(lambda: vr.vr_raycast_backward(src, tfp.detach(), cams, 256, 256, 1.0, fwd_out, grad_out,
+                                                           g_b, g_tf, (2.0, 2.0, 2.0), occupancy=src.occupancy), 5)
+    grid_b = src.data.numel() * 4
+    adj_bytes = grid_b + src.occupancy.numel() + 2 * fwd_out.numel() * 4 + 2 * grid_b
+    adj_tflops = n_eval * ADJ_FLOPS_PER_SAMPLE / (bwd_ms * 1e-3) / 1e12
+    adjoint = {"ms": bwd_ms, "evaluated_samples": n_eval,
+               "evaluated_Gsamples_per_s": n_eval / (bwd_ms * 1e-3) / 1e9,
+               "flops_per_sample": ADJ_FLOPS_PER_SAMPLE, "TFLOP_per_s": adj_tflops,
+               "frac_fp32_peak": adj_tflops / FP32_PEAK_TFLOPS,
+               "algorithmic_bytes": adj_bytes, "bytes_per_evaluated_sample": adj_bytes / max(n_eval, 1),
+               "GB_per_s": adj_bytes / (bwd_ms * 1e-3) / 1e9,
+               "frac_hbm_peak": adj_bytes / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    adjoint.update(ADJOINT_COUNTERS)
+    return {"ms_per_iter": it_ms, "fwd_ms": fwd_ms, "iter_over_fwd": it_ms / fwd_ms, "adjoint": adjoint,
             "samples_fwd": n_fwd, "evaluated_fwd": int(cnt[1].item()), "fwd_Gsamples_per_s": n_fwd / (fwd_ms * 1e-3) / 1e9,
             "iter_Gsamples_per_s": n_fwd / (it_ms * 1e-3) / 1e9,
             "steps": steps, "loss_first": lo[0], "loss_last": lo[-1],
@@ -510,6 +558,23 @@ def run_served(seconds=20.0, warmup_s=5.0, rate=50.0, slots=4, budget_gib=64.0, 
                        "one_slot_views_per_s": one_s["views_per_s"],
                        "served_loads": cap_s["loads"], "one_slot_loads": one_s["loads"]}
     log(f"capacity: {out['capacity']}")
+    # Poisson arrivals above what one slot can serve (twice its request rate in the burst),
+    # on the same resident volumes: the continuous-batching loop against one request at a time
+    one_rps = one_s["requests"] / max(one_s["wall_s"], 1e-9)
+    rate_hi = 2.0 * one_rps
+    trace_hi, _ = S.make_trace(rate=rate_hi, duration=min(4.0, 600.0 / rate_hi), pool=64, seed=5000)
+    hi = S.Server(served_ex, budget, slots=slots)
+    hi.resident.update(srv.resident)
+    hi_s = hi.run(trace_hi).summary()
+    hi1 = S.Server(served_ex, budget, slots=1)
+    hi1.resident.update(srv.resident)
+    hi1_s = hi1.run(S.copy_trace(trace_hi)).summary()
+    out["above_one_slot_capacity"] = {
+        "rate_per_s": rate_hi, "one_slot_capacity_requests_per_s": one_rps, "requests": len(trace_hi),
+        "served": hi_s, "one_slot": hi1_s,
+        "views_per_s_ratio": hi_s["views_per_s"] / max(hi1_s["views_per_s"], 1e-9),
+        "p99_ratio": hi_s["p99_ms"] / max(hi1_s["p99_ms"], 1e-9)}
+    log(f"above one-slot capacity: {out['above_one_slot_capacity']}")
     out["views_per_s_vs_plain"] = out["served"]["views_per_s"] / max(out["plain"]["views_per_s"], 1e-9)
     out["p99_vs_plain"] = out["served"]["p99_ms"] / max(out["plain"]["p99_ms"], 1e-9)
     served_ex.vols.clear()
@@ -593,6 +658,39 @@ def traffic_probe():
                       "calibration_bytes_written": dst.numel() * 4}), flush=True)
 
 
+def adjoint_probe():
+    """One launch of the adjoint in the fit's configuration (the 256^3 f32 grid of
+    spacing 2 from the 1024^3 step's 256^3 level, 16 turntable views at 256^2, step
+    1) after its forward, for kernel counters."""
+    import torch
+
+    from paper_2311_15038_amd import autograd as VA
+    from paper_2311_15038_amd import pipeline as P
+    from paper_2311_15038_amd import synth, vr
+
+    dev = torch.device("cuda:0")
+    vol = synth.make_volume(synth.FULL, dev)
+    pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=dev)
+    pipe.reduce(vol)
+    del vol
+    L1 = pipe.levels[0]
+    rz, ry, rx = L1.shape
+    cams = synth.turntable_cameras(rx, ry, rz, n_views=16)
+    dens = pipe.levels[1].to(torch.float32) / 65535.0
+    fwd, src = VA.render_forward(dens, pipe.tf, cams, 256, 256, 1.0, (2.0, 2.0, 2.0), with_source=True)
+    grad = torch.full_like(fwd, 1e-3)
+    g_b = torch.zeros_like(src.data)
+    g_tf = torch.zeros_like(pipe.tf)
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev)
+    VA.render_forward(dens, pipe.tf, cams, 256, 256, 1.0, (2.0, 2.0, 2.0), samples=cnt)
+    torch.cuda.synchronize()
+    vr.vr_raycast_backward(src, pipe.tf, cams, 256, 256, 1.0, fwd, grad, g_b, g_tf, (2.0, 2.0, 2.0),
+                           occupancy=src.occupancy)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "adjoint", "samples": int(cnt[0].item()), "evaluated": int(cnt[1].item())}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -602,6 +700,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one step plus a 1 GiB-in, 1 GiB-out elementwise kernel, for HBM counter runs")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="one forward and one adjoint launch of the fit's configuration (for counters)")
     ap.add_argument("--container-only", action="store_true",
                     help="only the container-removal leg (for kernel profiles)")
     ap.add_argument("--fit-only", action="store_true",
@@ -625,6 +725,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
 
+    if args.adjoint_probe:
+        adjoint_probe()
+        return
     if args.traffic_probe:
         traffic_probe()
         return
@@ -683,12 +786,15 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": raycast_traffic(),
                      "traffic_unit": "B per launch (HBM read + write, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "algorithmic_bytes": res["raycast_alg_bytes"],
-                     "kernel": "raycast_fwd<u16,brick4>", "flops_per_sample": FLOPS_PER_SAMPLE,
+                     "kernel": f"raycast_fwd<u16,brick{res['render_tuning']['brick_edge']}>",
+                     "flops_per_sample": FLOPS_PER_SAMPLE,
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
                                  "TD_busy": 0.85, "TA_busy": 0.65, "VALU_busy": 0.80,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
+        "render_tuning": res["render_tuning"],
+        "raycast_staged": res["raycast_staged"],
         "raycast_Gsamples_per_s": samples / (rc_ms * 1e-3) / 1e9,
         "raycast_evaluated_Gsamples_per_s": evaluated / (rc_ms * 1e-3) / 1e9,
         "samples_per_step": samples,
