@@ -39,18 +39,25 @@ METRIC = "Gsamples/s ray casting + GB/s reduction vs HBM peak; fwd+bwd, batched 
 # TF knots' shares (17); the density gradient through the TF slope (12); the
 # trilinear weights of the eight taps and their running sums (31).
 ADJ_FLOPS_PER_SAMPLE = 142
-# Memory-side atomic requests of one adjoint launch on the fit's 256^3 grid, per
-# evaluated sample, from rocprofv3 counters (see profiles/); None until measured.
-ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": None}
+# One adjoint launch in the fit's configuration (bench.py --adjoint-probe: the
+# 256^3 f32 grid before fitting, 16 x 256^2 views, 19,674,760 evaluated samples),
+# from rocprofv3 counters: memory-side atomic requests (TCC_EA0_ATOMIC_sum, equal
+# to TCC_ATOMIC_sum: every density-gradient atomic goes beyond the L2) and HBM
+# bytes (FETCH_SIZE x 1.9999 + WRITE_SIZE, the bitwise-NOT calibration of the
+# forward's traffic figure), per evaluated sample.
+ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539723 / 19674760,
+                    "hbm_bytes_per_evaluated_sample": (70913.375 * 1048576 / 524316.625 + 653105.03125) * 1024
+                    / 19674760,
+                    "source": "profiles/raycast_bwd_fit_256_counters.md"}
 
 # HBM bytes of one launch of the dominant kernel (raycast_fwd on this step),
 # FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of
 # --traffic-probe, each scaled by what the same counter reads for a kernel of
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
-# 524307 KiB for it (scale 2.000), WRITE_SIZE 1048576 KiB (scale 1.000).
+# 524316.6 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 2249506, "write_kib": 156652, "fetch_scale": 1048576 / 524307,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "733e972dd5099254"}
+RAYCAST_TRAFFIC = {"fetch_kib": 2741695.25, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.625,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "c18719a037a7e599"}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
 RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "raycast_staged.h", "brick_dev.h", "common.h", "entropy_dev.h")
@@ -250,6 +257,25 @@ def run_fwd_bwd(pipe, steps=200):
                "GB_per_s": adj_bytes / (bwd_ms * 1e-3) / 1e9,
                "frac_hbm_peak": adj_bytes / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     adjoint.update(ADJOINT_COUNTERS)
+    # the atomics against a measured ceiling of scattered f32 atomic adds on this
+    # device: torch's index_add_ of as many adds at random offsets of a grid of
+    # the same size (one request per add: 64 lanes meet 64 different lines)
+    n_atom = int(round(ADJOINT_COUNTERS["atomic_requests_per_evaluated_sample"] * n_eval))
+    if n_atom > 0:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(11)
+        idx = torch.randint(0, src.data.numel(), (n_atom,), device=dev, generator=gen)
+        vals = torch.full((n_atom,), 1e-3, dtype=torch.float32, device=dev)
+        tgt = torch.zeros(src.data.numel(), dtype=torch.float32, device=dev)
+        atom_ms = _median_ms(lambda: tgt.index_add_(0, idx, vals), 5)
+        rate = n_atom / (bwd_ms * 1e-3)
+        ceiling = n_atom / (atom_ms * 1e-3)
+        adjoint.update({"atomic_requests": n_atom, "atomic_requests_per_s": rate,
+                        "scattered_atomic_ceiling_per_s": ceiling,
+                        "scattered_atomic_ceiling_note": "torch index_add_ of the same number of f32 adds at "
+                                                         "seeded random offsets of the 256^3 grid",
+                        "frac_atomic_ceiling": rate / ceiling})
+        del idx, vals, tgt
     return {"ms_per_iter": it_ms, "fwd_ms": fwd_ms, "iter_over_fwd": it_ms / fwd_ms, "adjoint": adjoint,
             "samples_fwd": n_fwd, "evaluated_fwd": int(cnt[1].item()), "fwd_Gsamples_per_s": n_fwd / (fwd_ms * 1e-3) / 1e9,
             "iter_Gsamples_per_s": n_fwd / (it_ms * 1e-3) / 1e9,
@@ -791,7 +817,7 @@ def main():
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
-                                 "TD_busy": 0.85, "TA_busy": 0.65, "VALU_busy": 0.80,
+                                 "TD_busy": 0.86, "TA_busy": 0.70, "VALU_busy": 0.75,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "render_tuning": res["render_tuning"],
         "raycast_staged": res["raycast_staged"],
