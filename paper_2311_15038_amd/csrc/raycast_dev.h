@@ -431,9 +431,27 @@ __device__ __forceinline__ uint32_t clamp_flags(const Cell& c)
     return (c.x1 == c.x0 ? 1u : 0u) | (c.y1 == c.y0 ? 2u : 0u) | (c.z1 == c.z0 ? 4u : 0u);
 }
 
+// A 32-bit word of the volume at byte offset o, which need only be 2-byte
+// aligned (the device runs with unaligned access enabled: one load, whose word
+// never crosses the 8- or 16-byte brick row it starts in, see load_corners).
+__device__ __forceinline__ uint32_t word_at(const uint16_t* vol, uint32_t o)
+{
+    typedef uint32_t u32_a2 __attribute__((aligned(2)));
+    return *reinterpret_cast<const u32_a2*>(reinterpret_cast<const char*>(vol) + o);
+}
+
 // Tap steps: one voxel inside a brick of edge e = 2^B; from a brick's last
 // layer to the next brick, e^3 - (e - 1) in x, a brick row less (e - 1) e in y,
 // a brick slab less (e - 1) e^2 in z.
+//
+// u16 volumes with 32-bit byte offsets take both x taps of a corner row in one
+// 32-bit load where they lie in one brick row (x0 not on the brick's last
+// layer): four loads per cell instead of eight, with the same lines touched.
+// The texture path's time follows the 32-bit words it returns per lane, and a
+// 16-bit load costs a whole word.  Where x0 is on the last layer, the word
+// before it is loaded (x0 in its high half, inside the row) and the x1 taps,
+// in the next brick, one by one; where x is clamped (x1 == x0) the x0 tap
+// serves for both.
 template <typename T, bool WIDE, int B = 2>
 __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict__ vol, const Cell& c,
                                              uint32_t o0, Corners& k)
@@ -444,6 +462,28 @@ __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict
     const uint32_t dy = (c.y1 == c.y0) ? 0u : ((c.y0 & M) == M ? (S.row_e - M * e) * E : e * E);
     const uint32_t dz = (c.z1 == c.z0) ? 0u : ((c.z0 & M) == M ? (S.slab_e - M * e * e) * E : e * e * E);
     const uint32_t o2 = o0 + dy, o4 = o0 + dz, o6 = o4 + dy;
+    if constexpr (sizeof(T) == 2 && !WIDE) {
+        const bool last = (c.x0 & M) == M;
+        const uint32_t back = last ? 2u : 0u;
+        const uint32_t w0 = word_at(vol, o0 - back), w2 = word_at(vol, o2 - back);
+        const uint32_t w4 = word_at(vol, o4 - back), w6 = word_at(vol, o6 - back);
+        k.v[0] = (float)(last ? (w0 >> 16) : (w0 & 0xFFFFu));
+        k.v[2] = (float)(last ? (w2 >> 16) : (w2 & 0xFFFFu));
+        k.v[4] = (float)(last ? (w4 >> 16) : (w4 & 0xFFFFu));
+        k.v[6] = (float)(last ? (w6 >> 16) : (w6 & 0xFFFFu));
+        if (last && dx != 0u) {
+            k.v[1] = tap<T, WIDE>(vol, o0 + dx);
+            k.v[3] = tap<T, WIDE>(vol, o2 + dx);
+            k.v[5] = tap<T, WIDE>(vol, o4 + dx);
+            k.v[7] = tap<T, WIDE>(vol, o6 + dx);
+        } else {
+            k.v[1] = dx == 0u ? k.v[0] : (float)(w0 >> 16);
+            k.v[3] = dx == 0u ? k.v[2] : (float)(w2 >> 16);
+            k.v[5] = dx == 0u ? k.v[4] : (float)(w4 >> 16);
+            k.v[7] = dx == 0u ? k.v[6] : (float)(w6 >> 16);
+        }
+        return;
+    }
     k.v[0] = tap<T, WIDE>(vol, o0);
     k.v[1] = tap<T, WIDE>(vol, o0 + dx);
     k.v[2] = tap<T, WIDE>(vol, o2);
