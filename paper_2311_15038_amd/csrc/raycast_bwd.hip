@@ -133,7 +133,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
             for (int k = 0; k < n;) {
                 const float len = (k < n - 1) ? S.step : last;
                 const float off = fmaf(0.5f, len, (float)k * S.step);
-                const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
+                const Cell c = cell_at(S, u0, gr, off);
                 if (skipping) {
                     const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
                     if (b != cur_b) {

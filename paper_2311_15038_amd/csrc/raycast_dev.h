@@ -45,6 +45,7 @@ struct Scene {
     const uint8_t* dist;    // brick distance grid (with occ), or NULL: skip by 16^3 groups instead
     int nx, ny, nz;
     int nbx, nby, nbz;      // bricks per axis (4^3 or 8^3 voxels)
+    uint32_t nbxy;          // bricks per brick layer, nbx * nby
     int nmx, nmy, nmz;      // groups of 4^3 bricks per axis
     uint32_t macro_off;     // byte offset of the group occupancy
     float inv_sp[3];
@@ -161,19 +162,24 @@ struct Cell {
     float wx, wy, wz;
 };
 
-__device__ __forceinline__ Cell cell_at(const Scene& S, float px, float py, float pz)
+// The sample at ray distance off, in voxel coordinates u = u0 + off g (u0 the
+// ray's start and g its direction, both divided by the spacing, u0 less half a
+// voxel: voxel centres at integers), clamped to the volume's voxel centres.
+__device__ __forceinline__ Cell cell_at(const Scene& S, const float u0[3], const float g[3], float off)
 {
     Cell c;
-    const float ux = __builtin_amdgcn_fmed3f(fmaf(px, S.inv_sp[0], -0.5f), 0.0f, S.umax[0]);
-    const float uy = __builtin_amdgcn_fmed3f(fmaf(py, S.inv_sp[1], -0.5f), 0.0f, S.umax[1]);
-    const float uz = __builtin_amdgcn_fmed3f(fmaf(pz, S.inv_sp[2], -0.5f), 0.0f, S.umax[2]);
-    const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
-    c.wx = ux - fx;
-    c.wy = uy - fy;
-    c.wz = uz - fz;
-    c.x0 = (uint32_t)(int)fx; c.x1 = (uint32_t)min((int)c.x0 + 1, S.nx - 1);
-    c.y0 = (uint32_t)(int)fy; c.y1 = (uint32_t)min((int)c.y0 + 1, S.ny - 1);
-    c.z0 = (uint32_t)(int)fz; c.z1 = (uint32_t)min((int)c.z0 + 1, S.nz - 1);
+    const float ux = __builtin_amdgcn_fmed3f(fmaf(off, g[0], u0[0]), 0.0f, S.umax[0]);
+    const float uy = __builtin_amdgcn_fmed3f(fmaf(off, g[1], u0[1]), 0.0f, S.umax[1]);
+    const float uz = __builtin_amdgcn_fmed3f(fmaf(off, g[2], u0[2]), 0.0f, S.umax[2]);
+    // u >= 0 after the clamp: truncation is the floor, and the fraction
+    // u - floor(u) is exact (one instruction each instead of floor, convert
+    // and subtract)
+    c.wx = __builtin_amdgcn_fractf(ux);
+    c.wy = __builtin_amdgcn_fractf(uy);
+    c.wz = __builtin_amdgcn_fractf(uz);
+    c.x0 = (uint32_t)ux; c.x1 = (uint32_t)min((int)c.x0 + 1, S.nx - 1);
+    c.y0 = (uint32_t)uy; c.y1 = (uint32_t)min((int)c.y0 + 1, S.ny - 1);
+    c.z0 = (uint32_t)uz; c.z1 = (uint32_t)min((int)c.z0 + 1, S.nz - 1);
     return c;
 }
 
@@ -366,12 +372,12 @@ __device__ __forceinline__ float tap(const T* vol, uint32_t o)
 
 // The eight corner voxels of a cell of a volume in the 4^3-brick layout
 // whose base-tap brick is b, and the key that identifies them (the base
-// offset and which axes are clamped).  Tap offsets are the base offset plus
+// offset, one per cell).  Tap offsets are the base offset plus
 // per-axis steps: one voxel inside a brick, or into the next brick when the
 // base tap is on a brick's last layer, or zero where the taps are clamped.
 struct Corners {
     float v[8];   // x fastest: 000 100 010 110 001 101 011 111
-    uint32_t key_o, key_f;
+    uint32_t key_o;   // base offset: one per cell, which also fixes the clamped axes
 };
 
 template <bool WIDE, typename P, int B = 2>
@@ -426,11 +432,6 @@ __device__ __forceinline__ void load_corners_pairs(const Scene& S, const T* __re
     }
 }
 
-__device__ __forceinline__ uint32_t clamp_flags(const Cell& c)
-{
-    return (c.x1 == c.x0 ? 1u : 0u) | (c.y1 == c.y0 ? 2u : 0u) | (c.z1 == c.z0 ? 4u : 0u);
-}
-
 // A 32-bit word of the volume at byte offset o, which need only be 2-byte
 // aligned (the device runs with unaligned access enabled: one load, whose word
 // never crosses the 8- or 16-byte brick row it starts in, see load_corners).
@@ -464,9 +465,9 @@ __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict
     const uint32_t o2 = o0 + dy, o4 = o0 + dz, o6 = o4 + dy;
     if constexpr (sizeof(T) == 2 && !WIDE) {
         const bool last = (c.x0 & M) == M;
-        const uint32_t back = last ? 2u : 0u;
-        const uint32_t w0 = word_at(vol, o0 - back), w2 = word_at(vol, o2 - back);
-        const uint32_t w4 = word_at(vol, o4 - back), w6 = word_at(vol, o6 - back);
+        const uint32_t ob = last ? o0 - 2u : o0;   // start of the word of each row
+        const uint32_t w0 = word_at(vol, ob), w2 = word_at(vol, ob + dy);
+        const uint32_t w4 = word_at(vol, ob + dz), w6 = word_at(vol, ob + dz + dy);
         k.v[0] = (float)(last ? (w0 >> 16) : (w0 & 0xFFFFu));
         k.v[2] = (float)(last ? (w2 >> 16) : (w2 & 0xFFFFu));
         k.v[4] = (float)(last ? (w4 >> 16) : (w4 & 0xFFFFu));
@@ -532,17 +533,19 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
     uint32_t cur_r = 0u;         // distance byte of brick cur_b (0: occupied)
     Corners kc;                  // corners of the last sampled cell (consecutive samples share
     kc.key_o = 0xFFFFFFFFu;      // a cell about half the time at half-voxel steps)
-    kc.key_f = 0xFFFFFFFFu;
     int k = 0;
     while (k < n) {
         const float len = (k < n - 1) ? S.step : last;
         const float off = fmaf(0.5f, len, (float)k * S.step);
-        const Cell c = cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
+        const Cell c = cell_at(S, u0, g, off);
         float sv;
         if constexpr (Lay<LAYOUT>::bricked) {
             constexpr int B = Lay<LAYOUT>::bs;
-            const uint32_t b = mul_idx<WIDE>(mul_idx<WIDE>(c.z0 >> B, (uint32_t)S.nby) + (c.y0 >> B),
-                                             (uint32_t)S.nbx) + (c.x0 >> B);
+            // brick index: full multiplies when WIDE, else two 24-bit products (fewer
+            // than 2^24 bricks) summed at once
+            const uint32_t b = WIDE ? ((c.z0 >> B) * (uint32_t)S.nby + (c.y0 >> B)) * (uint32_t)S.nbx + (c.x0 >> B)
+                                    : __umul24(c.z0 >> B, S.nbxy) + __umul24(c.y0 >> B, (uint32_t)S.nbx) +
+                                          (c.x0 >> B);
             if (skipping) {
                 if (b != cur_b) {
                     cur_b = b;
@@ -576,12 +579,10 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
             constexpr bool PAIRS = LAYOUT == VR_LAYOUT_BRICK4_PAIRS;
             const uint32_t o0 = PAIRS ? base_offset<WIDE, typename vr::bk::PairOf<T>::type>(c, b)
                                       : base_offset<WIDE, T, B>(c, b);
-            const uint32_t f = clamp_flags(c);
-            if (o0 != kc.key_o || f != kc.key_f) {
+            if (o0 != kc.key_o) {
                 if (PAIRS) load_corners_pairs<T, WIDE>(S, vol, c, o0, kc);
                 else load_corners<T, WIDE, B>(S, vol, c, o0, kc);
                 kc.key_o = o0;
-                kc.key_f = f;
             }
             sv = interp_corners<T>(kc, c);
         } else {
@@ -664,6 +665,7 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
     S.nbx = (int)nb[0];
     S.nby = (int)nb[1];
     S.nbz = (int)nb[2];
+    S.nbxy = (uint32_t)(nb[0] * nb[1]);
     S.nmx = (S.nbx + 3) / 4;
     S.nmy = (S.nby + 3) / 4;
     S.nmz = (S.nbz + 3) / 4;

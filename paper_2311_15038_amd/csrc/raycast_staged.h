@@ -53,12 +53,12 @@ __device__ __forceinline__ float wave_max_f(float v)
 __device__ __forceinline__ uint32_t cell_axis(const Cell& c, int a) { return a == 0 ? c.x0 : a == 1 ? c.y0 : c.z0; }
 
 // The ray's cell at sample k (the march's own arithmetic).
-__device__ __forceinline__ Cell cell_of(const Scene& S, const float p[3], const float d[3], int k, int n, float last,
+__device__ __forceinline__ Cell cell_of(const Scene& S, const float u0[3], const float g[3], int k, int n, float last,
                                         float& len)
 {
     len = (k < n - 1) ? S.step : last;
     const float off = fmaf(0.5f, len, (float)k * S.step);
-    return cell_at(S, fmaf(off, d[0], p[0]), fmaf(off, d[1], p[1]), fmaf(off, d[2], p[2]));
+    return cell_at(S, u0, g, off);
 }
 
 template <bool COUNT>
@@ -108,7 +108,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
         int cm = 0;
         while (k < n) {
             float len;
-            const Cell c = cell_of(S, p, d, k, n, last, len);
+            const Cell c = cell_of(S, u0, g, k, n, last, len);
             const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
             if (skip) {
                 if (b != cur_b) {
@@ -202,7 +202,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
         const int wcut_lo = wlo, wcut_hi = sgn > 0 ? min(wfirst + D - 1, nM - 1) : wfirst;
         while (k < n) {
             float len;
-            const Cell c = cell_of(S, p, d, k, n, last, len);
+            const Cell c = cell_of(S, u0, g, k, n, last, len);
             const int cmv = (int)cell_axis(c, M);
             if (cmv < wcut_lo || cmv > wcut_hi) break;
             const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
