@@ -470,10 +470,12 @@ int vr_raycast_backward(const vr_volume* vol, const float* d_tf, const vr_camera
  * histograms (vr_histogram_with_top), threshold selection, the fused level-1
  * pyramid step, the brick layout with occupancy of level 1, and n_views
  * frames ray cast from level 1 (vr_raycast semantics; the cameras are in the
- * level-1 volume's world frame, whose voxel size is `spacing`).  One launch
- * of a persistent kernel (one workgroup per compute unit) runs a device task
- * queue with per-item dependency counters; the launch can be captured into a
- * HIP graph (vr_batch_capture) and replayed.  Results equal those of the
+ * level-1 volume's world frame, whose voxel size is `spacing`).  A launch is
+ * a persistent kernel (one workgroup per compute unit) running a device task
+ * queue with per-item dependency counters for the reduction and brick phases,
+ * then, on the same stream, one kernel that renders every item's tiles in
+ * one-wave workgroups; the launch can be captured into a HIP graph
+ * (vr_batch_capture, both kernels in one graph) and replayed.  Results equal those of the
  * single-volume calls (bit-identical reduction, and bit-identical frames for
  * the same bricked level).
  *
@@ -514,7 +516,8 @@ int vr_batch_workspace_size(const vr_batch_item* items, int n_items, const vr_ba
 int vr_batch_plan_create(const vr_batch_item* items, int n_items, const vr_batch_config* cfg,
                          const float* d_tf, void* d_workspace, int64_t workspace_bytes,
                          vr_batch_plan** plan);
-/* One persistent launch on `stream` (the captured graph once vr_batch_capture ran). */
+/* One launch on `stream`: the persistent kernel, then the render kernel (the
+ * captured graph once vr_batch_capture ran). */
 int vr_batch_launch(vr_batch_plan* plan, void* stream);
 /* Capture the launch into a HIP graph; later vr_batch_launch calls replay it. */
 int vr_batch_capture(vr_batch_plan* plan, void* stream);

@@ -1,5 +1,6 @@
-"""Many volumes x many views in one persistent launch, with a tuner for its
-launch shape.
+"""Many volumes x many views in one launch (a persistent kernel for the
+reduction and brick phases, then one render kernel for every item's views),
+with a tuner for its launch shape.
 
 BatchPreview wraps the vr_batch_* entry points: it lays out one workspace for
 every item (histograms, masks, level 1, bricks, occupancy, task table), builds
@@ -76,7 +77,7 @@ class BatchPreview:
         self.stream = torch.cuda.Stream(device=dev)
 
     def capture(self):
-        """Capture the persistent launch into a HIP graph (replayed by launch())."""
+        """Capture the launch (both kernels) into a HIP graph (replayed by launch())."""
         with torch.cuda.stream(self.stream):
             vr.vr_batch_capture(self.plan, self.stream)
         self.captured = True

@@ -11,10 +11,12 @@
 //   DOWN   fused threshold + level-1 tiles                 (after SEL3)
 //   BRICK  level 1 to the brick layout + occupancy         (after all DOWN)
 //   RENDER one ray tile of one view                        (after all BRICK)
-// RENDER tiles are not run as workgroup tasks: once the queue of the other
-// tasks is empty, each wave takes wave-sized pieces of them (16 per tile) from
-// a render queue of its own and waits, alone, for its item's bricks.  A
-// workgroup barrier per tile would hold 16 waves for the slowest ray.
+// RENDER tiles are not run by the persistent kernel: its 128 KiB LDS union
+// (sized by the histogram) and 128 registers leave four waves per SIMD,
+// half of what the ray caster runs at.  A second kernel, launched behind it
+// on the same stream (and captured into the same graph), renders every tile
+// of every item in one-wave workgroups, 16 per tile, with the TF knots in
+// 4 KiB of LDS; stream order makes every brick complete before it starts.
 // A task waits (thread 0 spins with agent-scope acquire loads) until the
 // counters of the phase it depends on reach their totals; a finished task
 // bumps its phase counter with a release.  Tasks are claimed in table order
@@ -75,9 +77,8 @@ struct BatchDev {
     uint32_t* head;          // queue position
     uint32_t* finished;      // workgroups done
     uint32_t* status;        // non-zero after a spin time-out
-    uint32_t* render_head;   // render queue position (in wave pieces)
     int64_t n_pre;           // tasks before the render phase (the workgroup queue)
-    int64_t n_render_waves;  // render pieces: 16 waves per render tile
+    int64_t n_render_waves;  // render pieces: 16 waves per render tile (the render launch)
     unsigned long long* samples;   // [2] samples taken / evaluated (accumulated)
     const float4* tf;
     int n_items;
@@ -96,7 +97,6 @@ union BatchLds {
         uint32_t first, bad;
     } down;
     vr::bk::SlabLds<uint16_t> brick[kT / vr::bk::kThreads];
-    vr::rc::TfLds tf;
 };
 
 __device__ inline void wait_ge(const BatchDev& B, const uint32_t* c, uint32_t need)
@@ -226,66 +226,44 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
     }
 }
 
-// wait_ge for one wave: every lane reads the counter with acquire (no barrier)
-__device__ inline void wave_wait_ge(const BatchDev& B, const uint32_t* c, uint32_t need)
+// The render launch: workgroup b (in XCD-aware order, so that an XCD renders
+// consecutive pieces) is wave r % 16 of render tile r / 16 (the render tasks
+// at the end of the table), the pieces of one tile being consecutive so that
+// neighbouring waves render neighbouring pixels.
+__global__ void __launch_bounds__(64) batch_render_kernel(const BatchDev B)
 {
-    uint64_t spins = 0;
-    for (;;) {
-        const uint32_t v = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-        if (v >= need) break;
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > kSpinLimit) {
-            if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_or(B.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
-    }
-}
-
-// The render phase, one wave at a time: piece r is wave r % 16 of render tile
-// r / 16 (the render tasks at the end of the table), pieces of one tile being
-// consecutive so that neighbouring waves render neighbouring pixels.
-__device__ void render_waves(const BatchDev& B, const BatchLds& L)
-{
+    __shared__ vr::rc::TfLds tf;
+    vr::rc::stage_tf(tf, B.tf, (int)threadIdx.x, 64);
+    __syncthreads();
+    const uint32_t r = (uint32_t)vr::rc::xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int lane = threadIdx.x & 63;
     const int tile_w = B.wave_w * B.waves_x, tile_h = B.wave_h * (16 / B.waves_x);
-    int ready = -1;   // item whose bricks this wave has seen complete
-    for (;;) {
-        uint32_t r = 0;
-        if (lane == 0) r = __hip_atomic_fetch_add(B.render_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        r = __builtin_amdgcn_readfirstlane(r);
-        if ((int64_t)r >= B.n_render_waves) break;
-        const Task t = B.tasks[B.n_pre + r / 16];
-        const int w = (int)(r % 16);
-        const ItemDev& it = B.items[t.item];
-        if (t.item != ready) {
-            wave_wait_ge(B, B.counters + (int64_t)t.item * C_COUNT + C_BRICK, it.need[C_BRICK]);
-            ready = t.item;
-        }
-        const vr::rc::Scene& S = it.S;
-        const bool skip = vr::rc::can_skip(S, L.tf);
-        const int tx = (int)(t.b % B.tiles_per_row), ty = (int)(t.b / B.tiles_per_row);
-        const int i = tx * tile_w + (w % B.waves_x) * B.wave_w + lane % B.wave_w;
-        const int j = ty * tile_h + (w / B.waves_x) * B.wave_h + lane / B.wave_w;
-        uint32_t cr = 0, er = 0;
-        if (i < S.W && j < S.H) {
-            const float4 rgba =
-                B.brick8 ? vr::rc::march<uint16_t, VR_LAYOUT_BRICK8, true, false, false>(
-                               S, it.V.v[t.a], it.bricked, L.tf, skip, i, j, cr, er)
-                         : vr::rc::march<uint16_t, VR_LAYOUT_BRICK4, true, false, false>(
-                               S, it.V.v[t.a], it.bricked, L.tf, skip, i, j, cr, er);
-            reinterpret_cast<float4*>(it.frames)[((int64_t)t.a * S.H + j) * S.W + i] = rgba;
-        }
-        if (B.samples) {
-            unsigned long long c = cr, e = er;
+    const Task t = B.tasks[B.n_pre + r / 16];
+    const int w = (int)(r % 16);
+    const ItemDev& it = B.items[t.item];
+    const vr::rc::Scene& S = it.S;
+    const bool skip = vr::rc::can_skip(S, tf);
+    const int tx = (int)(t.b % B.tiles_per_row), ty = (int)(t.b / B.tiles_per_row);
+    const int i = tx * tile_w + (w % B.waves_x) * B.wave_w + lane % B.wave_w;
+    const int j = ty * tile_h + (w / B.waves_x) * B.wave_h + lane / B.wave_w;
+    uint32_t cr = 0, er = 0;
+    if (i < S.W && j < S.H) {
+        const float4 rgba =
+            B.brick8 ? vr::rc::march<uint16_t, VR_LAYOUT_BRICK8, true, false, false>(
+                           S, it.V.v[t.a], it.bricked, tf, skip, i, j, cr, er)
+                     : vr::rc::march<uint16_t, VR_LAYOUT_BRICK4, true, false, false>(
+                           S, it.V.v[t.a], it.bricked, tf, skip, i, j, cr, er);
+        reinterpret_cast<float4*>(it.frames)[((int64_t)t.a * S.H + j) * S.W + i] = rgba;
+    }
+    if (B.samples) {
+        unsigned long long c = cr, e = er;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                c += __shfl_xor(c, off);
-                e += __shfl_xor(e, off);
-            }
-            if (lane == 0 && c) atomicAdd(B.samples, c);
-            if (lane == 0 && e) atomicAdd(B.samples + 1, e);
+        for (int off = 32; off > 0; off >>= 1) {
+            c += __shfl_xor(c, off);
+            e += __shfl_xor(e, off);
         }
+        if (lane == 0 && c) atomicAdd(B.samples, c);
+        if (lane == 0 && e) atomicAdd(B.samples + 1, e);
     }
 }
 
@@ -308,12 +286,6 @@ __global__ void __launch_bounds__(kT) batch_kernel(const BatchDev B)
         if (threadIdx.x == 0) s_task[0] = s_task[1];
         __syncthreads();
     }
-    // every other task is claimed: render, one wave at a time (the TF is staged once)
-    if (B.n_render_waves > 0) {
-        vr::rc::stage_tf(L.tf, B.tf, (int)threadIdx.x, kT);
-        __syncthreads();
-        render_waves(B, L);
-    }
     __syncthreads();
     // the last workgroup out resets the queues for the next launch
     if (threadIdx.x == 0) {
@@ -322,7 +294,6 @@ __global__ void __launch_bounds__(kT) batch_kernel(const BatchDev B)
         if (done == gridDim.x - 1) {
             for (int64_t i = 0; i < (int64_t)B.n_items * C_COUNT; ++i) B.counters[i] = 0;
             *B.head = 0;
-            *B.render_head = 0;
             __threadfence();
             __hip_atomic_store(B.finished, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -513,11 +484,10 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
     B.brick8 = b8 ? 1 : 0;
     B.items = static_cast<const ItemDev*>(C.take(sizeof(ItemDev) * n_items));
     B.tasks = static_cast<const Task*>(C.take(sizeof(Task) * tasks->size()));
-    B.counters = static_cast<uint32_t*>(C.take(sizeof(uint32_t) * (C_COUNT * n_items + 4)));
+    B.counters = static_cast<uint32_t*>(C.take(sizeof(uint32_t) * (C_COUNT * n_items + 3)));
     B.head = B.counters ? B.counters + C_COUNT * n_items : nullptr;
     B.finished = B.head ? B.head + 1 : nullptr;
     B.status = B.head ? B.head + 2 : nullptr;
-    B.render_head = B.head ? B.head + 3 : nullptr;
     B.samples = static_cast<unsigned long long*>(C.take(16));
     return VR_OK;
 }
@@ -565,7 +535,7 @@ extern "C" int vr_batch_plan_create(const vr_batch_item* items, int n_items, con
     if (e == hipSuccess)
         e = hipMemcpy(const_cast<Task*>(P->dev.tasks), tasks.data(), sizeof(Task) * tasks.size(),
                       hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(P->dev.counters, 0, sizeof(uint32_t) * (C_COUNT * n_items + 4));
+    if (e == hipSuccess) e = hipMemset(P->dev.counters, 0, sizeof(uint32_t) * (C_COUNT * n_items + 3));
     if (e == hipSuccess) e = hipMemset(P->dev.samples, 0, 16);
     for (int v = 0; e == hipSuccess && v < n_items; ++v) {
         e = hipMemset(P->items[v].H, 0, VR_NBINS * 8);
@@ -593,6 +563,8 @@ extern "C" int vr_batch_launch(vr_batch_plan* plan, void* stream)
         return VR_OK;
     }
     batch_kernel<<<plan->grid, kT, 0, s>>>(plan->dev);
+    if (plan->dev.n_render_waves > 0)
+        batch_render_kernel<<<(unsigned)plan->dev.n_render_waves, 64, 0, s>>>(plan->dev);
     return vr::check_launch("vr_batch_launch");
 }
 
@@ -605,6 +577,8 @@ extern "C" int vr_batch_capture(vr_batch_plan* plan, void* stream)
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     VR_REQUIRE(e == hipSuccess, VR_ERR_HIP, "vr_batch_capture: begin: %s", hipGetErrorString(e));
     batch_kernel<<<plan->grid, kT, 0, s>>>(plan->dev);
+    if (plan->dev.n_render_waves > 0)
+        batch_render_kernel<<<(unsigned)plan->dev.n_render_waves, 64, 0, s>>>(plan->dev);
     hipError_t le = hipGetLastError();
     e = hipStreamEndCapture(s, &plan->graph);
     VR_REQUIRE(le == hipSuccess && e == hipSuccess, VR_ERR_HIP, "vr_batch_capture: %s",
