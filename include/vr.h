@@ -40,7 +40,7 @@ extern "C" {
 
 #define VR_NBINS 65536            /* 16-bit grey values */
 #define VR_KEEP_WORDS 2048        /* keep mask: bin b -> bit (b % 32) of word b / 32 */
-#define VR_MAX_LEVELS 4           /* pyramid levels produced by one call */
+#define VR_MAX_LEVELS 8           /* pyramid levels produced by one call */
 #define VR_MAX_VIEWS_PER_LAUNCH 48
 #define VR_BRICK_DIST_CAP 8       /* cap of the brick distance grid, see vr_brick_volume */
 
@@ -218,17 +218,25 @@ typedef struct {
  *   L_k = (S_k + 2^(3k-1)) >> 3k,
  * S_k the exact integer sum of f over the 2^k cube at 2^k*(x, y, z), with
  * voxels past the volume's end counted as 0 (round-half-up mean over the
- * full cube, each level from its own exact sum).  One pass over the volume.
+ * full cube, each level from its own exact sum).  One pass over the volume
+ * writes levels 1..4; levels 5..n_levels are then summed, exactly, from the
+ * level-4 sums by a second, small launch.
  *   h_levels: host array of n_levels device pointers, level k at
  *     h_levels[k-1], each [nz_k][ny_k][nx_k] u16, overwritten.
  *   n_levels: 1..VR_MAX_LEVELS.
+ *   h_level_sums: NULL, or a host array of n_levels device pointers, each
+ *     NULL or [nz_k][ny_k][nx_k] u64 receiving the exact S_k (overwritten;
+ *     for verification).  With n_levels > 4, h_level_sums[3] is required:
+ *     the levels past the fourth are formed from it.
  *   atlas: NULL, or a slicemap atlas of one of the levels to write in the
- *     same pass (the layout and values of vr_pack_slicemap, overwritten).
- * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (n_levels, atlas), VR_ERR_HIP.
+ *     same call (the layout and values of vr_pack_slicemap, overwritten).
+ * Errors: VR_ERR_NULL (incl. a missing level-4 sums buffer when n_levels > 4),
+ * VR_ERR_DIMS, VR_ERR_RANGE (n_levels, atlas), VR_ERR_HIP.
  */
 int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
                             const uint32_t* d_keep_bits, int n_levels,
-                            uint16_t* const* h_levels, const vr_atlas_spec* atlas, void* stream);
+                            uint16_t* const* h_levels, uint64_t* const* h_level_sums,
+                            const vr_atlas_spec* atlas, void* stream);
 
 /* vr_threshold_downsample with every voxel outside the kept disc of d_circle
  * (see vr_find_container) counted as removed, so the levels equal those of
@@ -237,7 +245,8 @@ int vr_threshold_downsample(const uint16_t* d_vol, int64_t nx, int64_t ny, int64
  * d_circle. */
 int vr_threshold_downsample_in_disc(const uint16_t* d_vol, int64_t nx, int64_t ny, int64_t nz,
                                     const uint32_t* d_keep_bits, const int32_t* d_circle, int n_levels,
-                                    uint16_t* const* h_levels, const vr_atlas_spec* atlas, void* stream);
+                                    uint16_t* const* h_levels, uint64_t* const* h_level_sums,
+                                    const vr_atlas_spec* atlas, void* stream);
 
 /*
  * Hollow data preview (Section II: a preview that keeps the object's outer

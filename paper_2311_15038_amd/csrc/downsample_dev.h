@@ -10,10 +10,12 @@ namespace ds {
 
 constexpr int kThreads = 256;      // threads of one tile group
 constexpr int TX = 64, TY = 16, TZ = 16;
+constexpr int kFusedLevels = 4;    // levels the streaming pass writes itself
 
 struct LevelOut {
-    uint16_t* p[VR_MAX_LEVELS];
-    int nx[VR_MAX_LEVELS], ny[VR_MAX_LEVELS], nz[VR_MAX_LEVELS];
+    uint16_t* p[kFusedLevels];
+    int nx[kFusedLevels], ny[kFusedLevels], nz[kFusedLevels];
+    uint64_t* sums[kFusedLevels];   // exact level sums (NULL: not written)
     // optional slicemap atlas of one level, written beside it
     void* atlas;
     int atlas_level, atlas_tiles_x, atlas_bits;

@@ -67,6 +67,11 @@ class PreviewPipeline:
         self.keep = torch.empty(vr.KEEP_WORDS, dtype=torch.int32, device=dev)
         self.levels = [torch.empty(vr.level_shape(self.shape, k), dtype=torch.uint16, device=dev)
                        for k in range(1, cfg.n_levels + 1)]
+        # levels past the fourth are summed from the exact level-4 sums: their buffer
+        self._sums = None
+        if cfg.n_levels > 4:
+            self._sums = [None] * cfg.n_levels
+            self._sums[3] = torch.empty(vr.level_shape(self.shape, 4), dtype=torch.int64, device=dev)
         self.tiles, self.atlas = None, None
         if cfg.atlas_level > 0:
             az, ay, ax = self.levels[cfg.atlas_level - 1].shape
@@ -131,7 +136,7 @@ class PreviewPipeline:
 
     def pyramid(self, vol, stream=None):
         vr.vr_threshold_downsample(vol, self.keep, self.cfg.n_levels, self.levels, self._atlas_arg(),
-                                   stream, circle=self.circle)
+                                   stream, circle=self.circle, sums=self._sums)
 
     # the reduction half: (the container's circle,) histograms, selection, pyramid
     # with its atlas written in the same pass

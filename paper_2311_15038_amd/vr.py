@@ -21,7 +21,7 @@ KEEP_WORDS = 2048
 CIRCLE_INTS = 8
 CONTAINER_SCRATCH_BYTES = 32 << 20
 HOLLOW_MAX_THICKNESS = 8
-MAX_LEVELS = 4
+MAX_LEVELS = 8
 MAX_VIEWS_PER_LAUNCH = 48
 BRICK_DIST_CAP = 8
 RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
@@ -91,7 +91,7 @@ def lib():
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
         L.vr_histogram.argtypes = [vp, i64, i64, i64, i64, i64, vp, vp]
         L.vr_select_threshold.argtypes = [vp, vp, i32, i32, vp, vp, vp]
-        L.vr_threshold_downsample.argtypes = [vp, i64, i64, i64, vp, i32, C.POINTER(vp),
+        L.vr_threshold_downsample.argtypes = [vp, i64, i64, i64, vp, i32, C.POINTER(vp), C.POINTER(vp),
                                               C.POINTER(vr_atlas_spec), vp]
         L.vr_histogram_with_top.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
         L.vr_container_workspace_size.argtypes = [i64, i64, i32, C.POINTER(C.c_int64)]
@@ -101,7 +101,7 @@ def lib():
         L.vr_hollow.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp]
         L.vr_histogram_in_disc.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp]
         L.vr_threshold_downsample_in_disc.argtypes = [vp, i64, i64, i64, vp, vp, i32, C.POINTER(vp),
-                                                      C.POINTER(vr_atlas_spec), vp]
+                                                      C.POINTER(vp), C.POINTER(vr_atlas_spec), vp]
         L.vr_pack_slicemap.argtypes = [vp, i64, i64, i64, i32, i32, i32, vp, vp]
         L.vr_raycast.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                  C.POINTER(vr_render_opts), vp, vp, vp]
@@ -304,13 +304,19 @@ def level_shape(shape, k):
     return tuple(-(-n // d) for n in shape)
 
 
-def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, stream=None, circle=None):
-    """Filtered pyramid levels 1..n_levels (list of uint16 tensors).
+def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, stream=None, circle=None,
+                            sums=None):
+    """Filtered pyramid levels 1..n_levels (list of uint16 tensors), or
+    (levels, sums) when sums is given.
 
     atlas: None or (level, tiles_x, tiles_y, out_bits, tensor): the slicemap
     atlas of that level, written in the same pass.
     circle: None, or a container circle record (vr_find_container): voxels
     outside its kept disc count as removed (vr_threshold_downsample_in_disc).
+    sums: None, True (one new int64 tensor of exact level sums per level), or a
+    list of n_levels tensors (or None entries).  With more than four levels
+    the level-4 sums are needed by the call: a buffer for them is made here
+    when the caller does not ask for it.
     """
     nz, ny, nx = vol.shape
     if levels is None:
@@ -325,6 +331,25 @@ def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, s
             raise ValueError(f"level {k + 1} has shape {tuple(levels[k].shape)}, expected {want}")
         ptrs[k] = _dev(levels[k], f"levels[{k}]", _U16).value
     kb = None if keep_bits is None else _dev(keep_bits, "keep_bits", torch.int32, KEEP_WORDS)
+    want_sums = sums is not None
+    if sums is True:
+        sums = [torch.empty(level_shape((nz, ny, nx), k), dtype=torch.int64, device=vol.device)
+                for k in range(1, n_levels + 1)]
+    elif sums is None:
+        sums = [None] * max(n_levels, 0)
+    if len(sums) < n_levels:
+        raise ValueError("need one sums entry per level")
+    if n_levels > 4 and sums[3] is None:
+        sums = list(sums)
+        sums[3] = torch.empty(level_shape((nz, ny, nx), 4), dtype=torch.int64, device=vol.device)
+    sptrs = None
+    if any(t is not None for t in sums[:n_levels]):
+        sptrs = (C.c_void_p * max(1, n_levels))()
+        for k in range(n_levels):
+            if sums[k] is not None:
+                if tuple(sums[k].shape) != level_shape((nz, ny, nx), k + 1):
+                    raise ValueError(f"sums {k + 1} has shape {tuple(sums[k].shape)}")
+                sptrs[k] = _dev(sums[k], f"sums[{k}]", torch.int64).value
     spec = None
     if atlas is not None:
         lvl, tx, ty, bits, t = atlas
@@ -334,12 +359,12 @@ def vr_threshold_downsample(vol, keep_bits, n_levels, levels=None, atlas=None, s
                                      _dev(t, "atlas", dt, tx * ty * lx * ly).value))
     if circle is None:
         _check(lib().vr_threshold_downsample(_dev(vol, "vol", _U16), nx, ny, nz, kb, int(n_levels),
-                                             ptrs, spec, _stream(stream)))
+                                             ptrs, sptrs, spec, _stream(stream)))
     else:
         _check(lib().vr_threshold_downsample_in_disc(
             _dev(vol, "vol", _U16), nx, ny, nz, kb, _dev(circle, "circle", torch.int32, CIRCLE_INTS),
-            int(n_levels), ptrs, spec, _stream(stream)))
-    return levels
+            int(n_levels), ptrs, sptrs, spec, _stream(stream)))
+    return (levels, sums[:n_levels]) if want_sums else levels
 
 
 def vr_pack_slicemap(level, tiles_x, tiles_y, out_bits=16, out=None, stream=None):

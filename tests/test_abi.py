@@ -51,14 +51,19 @@ def test_validation_happens_on_the_host(lib):
     assert lib.vr_histogram(C.c_void_p(16), 4, 4, 4, 3, 2, C.c_void_p(16), None) == -3
     assert lib.vr_select_threshold(C.c_void_p(16), None, 9, 0, C.c_void_p(16), C.c_void_p(16), None) == -3
     assert lib.vr_select_threshold(C.c_void_p(16), None, 0, 0, C.c_void_p(16), C.c_void_p(16), None) == -3
-    ptrs = (C.c_void_p * 5)(*([16] * 5))
-    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 5, ptrs, None, None) == -3
-    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 0, ptrs, None, None) == -3
+    ptrs = (C.c_void_p * 9)(*([16] * 9))
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 9, ptrs, None, None, None) == -3
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 0, ptrs, None, None, None) == -3
+    # levels past the fourth are formed from the level-4 sums: that buffer is required
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 5, ptrs, None, None, None) == -1
+    assert "h_level_sums[3]" in lib.vr_last_error().decode()
+    no_s4 = (C.c_void_p * 5)(16, 16, 16, None, 16)
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 5, ptrs, no_s4, None, None) == -1
     from paper_2311_15038_amd import vr
     spec = vr.vr_atlas_spec(2, 1, 1, 16, 16)       # 1 x 1 tiles cannot hold the 2 slices of level 2
-    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 2, ptrs, C.byref(spec), None) == -3
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 2, ptrs, None, C.byref(spec), None) == -3
     spec = vr.vr_atlas_spec(3, 4, 4, 16, 16)       # level 3 is not produced
-    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 2, ptrs, C.byref(spec), None) == -3
+    assert lib.vr_threshold_downsample(C.c_void_p(16), 8, 8, 8, None, 2, ptrs, None, C.byref(spec), None) == -3
     assert lib.vr_histogram_with_top(C.c_void_p(16), 4, 4, 4, 5, C.c_void_p(16), C.c_void_p(16), None) == -3
     assert lib.vr_histogram_with_top(C.c_void_p(16), 4, 4, 4, 3, None, C.c_void_p(16), None) == -1
     assert lib.vr_pack_slicemap(C.c_void_p(16), 4, 4, 10, 3, 3, 16, C.c_void_p(16), None) == -3
@@ -153,5 +158,5 @@ def test_container_validation_on_the_host(lib):
     assert lib.vr_histogram_in_disc(p, 4, 4, 4, 5, p, p, p, None) == -3
     assert lib.vr_histogram_in_disc(p, 4, 4, 4, 3, None, p, p, None) == -1
     ptrs = (C.c_void_p * 1)(16)
-    assert lib.vr_threshold_downsample_in_disc(p, 8, 8, 8, None, None, 1, ptrs, None, None) == -1
-    assert lib.vr_threshold_downsample_in_disc(p, 8193, 8, 8, None, p, 1, ptrs, None, None) == -2
+    assert lib.vr_threshold_downsample_in_disc(p, 8, 8, 8, None, None, 1, ptrs, None, None, None) == -1
+    assert lib.vr_threshold_downsample_in_disc(p, 8193, 8, 8, None, p, 1, ptrs, None, None, None) == -2

@@ -1,6 +1,7 @@
 """An odd, anisotropic volume (x 511, y 257, z 129: no side a multiple of 2,
 4, 16 or 32) through the whole preview step, against the oracle: histograms,
-threshold, keep mask, four pyramid levels and the atlas bit-exact, frames
+threshold, keep mask, eight pyramid levels (the last four summed from the
+exact level-4 sums after the pass) and the atlas bit-exact, frames
 within 2e-4 of the FP64 ray caster.  The step then runs again on the same
 input and every output must come out bit for bit the same (the integer
 outputs are deterministic, so a race in an LDS pass would show here)."""
@@ -25,7 +26,7 @@ def odd():
     nz, ny, nx = SHAPE
     banner(f"odd shape {SHAPE}: preview step")
     vol = synth.make_volume(synth.VolumeSpec(nx, ny, nz, seed=4242), dev())
-    cfg = P.PreviewConfig(n_levels=4, atlas_level=2, render_level=1, n_views=2, width=72, height=40)
+    cfg = P.PreviewConfig(n_levels=8, atlas_level=2, render_level=1, n_views=2, width=72, height=40)
     pipe = P.PreviewPipeline(vol.shape, cfg, device=dev())
     pipe.step(vol)
     torch.cuda.synchronize()
@@ -39,8 +40,8 @@ def test_reduction_bit_exact(odd):
     T = O.valley_threshold(H)
     bits = O.keep_bits(T, Ht)
     assert int(pipe.result[0].item()) == T and np.array_equal(u32_np(pipe.keep), bits)
-    ref = O.pyramid(a, bits, 4)
-    for k in range(4):
+    ref = O.pyramid(a, bits, 8)
+    for k in range(8):
         assert np.array_equal(u16_np(pipe.levels[k]), ref[k]), k + 1
     tx, ty = pipe.tiles
     assert np.array_equal(u16_np(pipe.atlas), O.slicemap(ref[1], tx, ty, 16))

@@ -206,8 +206,56 @@ def test_pyramid_extreme_values():
 def test_pyramid_rejects_bad_levels():
     v = to_dev_u16(_rand_vol((8, 8, 8), 6))
     with pytest.raises(vr.VrError) as e:
-        vr.vr_threshold_downsample(v, None, 5)
+        vr.vr_threshold_downsample(v, None, 9)
     assert e.value.code == -3
+
+
+# shapes (nz, ny, nx) whose level-4 grid is ragged, so that the level-5..8 boxes are clipped
+DEEP_SHAPES = [(37, 50, 29), (96, 17, 260), (129, 64, 33), (16, 16, 16)]
+
+
+@pytest.mark.parametrize("shape", DEEP_SHAPES)
+@pytest.mark.parametrize("n_levels", [5, 8])
+def test_pyramid_eight_levels_and_exact_sums(shape, n_levels):
+    """Levels past the fourth are summed from the exact level-4 sums after the
+    pass: every level bit-exact against the oracle's own box sums, and every
+    exact sum (u64) equal to the oracle's."""
+    banner(f"pyramid {shape} K={n_levels} with sums")
+    a = _rand_vol(shape, 7)
+    keep = np.random.default_rng(8).random(65536) < 0.6
+    bits = O.pack_bits(keep)
+    v = to_dev_u16(a)
+    levels, sums = vr.vr_threshold_downsample(v, bits_to_dev(bits), n_levels, sums=True)
+    f = O.apply_keep(a, bits)
+    for k in range(1, n_levels + 1):
+        S = O.box_sums(f, k)
+        assert np.array_equal(sums[k - 1].cpu().numpy(), S), k
+        assert np.array_equal(u16_np(levels[k - 1]), O.level_from_sums(S, k)), k
+    # without asking for the sums (the binding then passes a level-4 buffer of its own),
+    # and the fused levels unchanged by the deeper call
+    plain = vr.vr_threshold_downsample(v, bits_to_dev(bits), n_levels)
+    four = vr.vr_threshold_downsample(v, bits_to_dev(bits), 4)
+    for k in range(n_levels):
+        assert torch.equal(plain[k], levels[k]), k
+    for k in range(4):
+        assert torch.equal(four[k], levels[k]), k
+
+
+def test_pyramid_atlas_of_a_deep_level():
+    banner("atlas of level 6")
+    a = _rand_vol((200, 130, 300), 9)
+    v = to_dev_u16(a)
+    want = O.pyramid(a, None, 6)
+    lz, ly, lx = want[5].shape
+    tx, ty = 2, 2
+    for bits_out in (16, 8):
+        atl = torch.full((ty * ly * tx * lx,), 77, dtype=torch.uint16 if bits_out == 16 else torch.uint8,
+                         device=v.device)
+        got = vr.vr_threshold_downsample(v, None, 6, atlas=(6, tx, ty, bits_out, atl))
+        assert np.array_equal(u16_np(got[5]), want[5])
+        ref = O.slicemap(want[5], tx, ty, bits_out)
+        got_atl = u16_np(atl) if bits_out == 16 else atl.cpu().numpy()
+        assert np.array_equal(got_atl.reshape(ref.shape), ref)
 
 
 # ------------------------------------------------------------ slicemap
