@@ -29,7 +29,7 @@ DEFAULTS = dict(wave_w=8, wave_h=8, waves_x=4, hist_task_voxels=4 << 20, down_ti
 
 RENDER_TILES = [(8, 8, 4), (8, 8, 2), (8, 8, 8), (16, 4, 2), (16, 4, 4), (4, 16, 8), (4, 16, 4)]
 BRICK_EDGES = [4, 8]
-TASK_SIZES = [(4 << 20, 16, 32), (1 << 20, 8, 16), (16 << 20, 32, 64)]
+TASK_SIZES = [(4 << 20, 16, 32), (1 << 20, 8, 16), (16 << 20, 32, 64), (4 << 20, 32, 32), (4 << 20, 64, 64)]
 
 
 def _cfg(width, height, step, ert_eps, bg, rule, rule_param, top_slices, t):
