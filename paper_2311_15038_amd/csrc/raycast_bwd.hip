@@ -128,6 +128,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                 gr[a] = d[a] * S.inv_sp[a];
                 ig[a] = gr[a] != 0.0f ? 1.0f / gr[a] : 0.0f;
             }
+            const SkipRay SR = skip_ray(S, u0, gr, ig);
             uint32_t cur_b = 0xFFFFFFFFu;
             uint32_t cur_r = 0u;     // distance byte of brick cur_b (0: occupied)
             for (int k = 0; k < n;) {
@@ -147,7 +148,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                         // len * q to the first knot's extinction, added for the whole run
                         // (the run leaves the cube of empty bricks the distance grid gives)
                         const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                        const int next = skip_cube(S, u0, gr, ig, bb, cur_r, 2, k, n);
+                        const int next = skip_cube_ray(S, SR, gr, ig, bb, cur_r, 2, k, n);
                         const float lsum = next < n ? (float)(next - k) * S.step
                                                     : fmaf((float)(n - 1 - k), S.step, last);
                         const float q = g.x * (Tr * tf_s[0].x - (I.x - Pr)) + g.y * (Tr * tf_s[0].y - (I.y - Pg)) +

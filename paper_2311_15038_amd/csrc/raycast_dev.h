@@ -328,21 +328,47 @@ __device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const 
     return skip_span(S, u0, g, ig, cell, cell, ncell, sh, k, n);
 }
 
-// skip_span for the empty cube of bricks (of 2^sh voxels) around brick bb whose
-// distance byte is r >= 1: bricks within r - 1 of bb on every axis (clipped to
-// the grid).
-__device__ __forceinline__ int skip_cube(const Scene& S, const float u0[3], const float g[3],
-                                         const float ig[3], const uint32_t bb[3], uint32_t r, int sh, int k,
-                                         int n)
+// Per-ray constants of skip_cube_ray: for each axis the exit bound of the
+// cells below (or above) c1 is s = (c1 << sh) ig + kb, kb = (-+margin - u0) ig,
+// and nopen is the axis's cell count less one (0 where g = 0: never left).
+struct SkipRay {
+    float kb[3];
+    uint32_t nopen[3];
+};
+
+__device__ __forceinline__ SkipRay skip_ray(const Scene& S, const float u0[3], const float g[3], const float ig[3])
 {
+    SkipRay R;
     const int nb[3] = {S.nbx, S.nby, S.nbz};
-    uint32_t lo[3], hi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        lo[a] = bb[a] >= r - 1u ? bb[a] - (r - 1u) : 0u;
-        hi[a] = bb[a] + (r - 1u);
+        R.kb[a] = ((g[a] > 0.0f ? -kSkipMarginVox : kSkipMarginVox) - u0[a]) * ig[a];
+        R.nopen[a] = g[a] != 0.0f ? (uint32_t)(nb[a] - 1) : 0u;
     }
-    return skip_span(S, u0, g, ig, lo, hi, nb, sh, k, n);
+    return R;
+}
+
+// The first sample that may leave the empty cube of bricks (of 2^sh voxels)
+// around brick bb whose distance byte is r >= 1 (bricks within r - 1 of bb on
+// every axis, clipped to the grid), as skip_span computes it for a box, with
+// the per-ray constants: the cube's exit face on an axis the ray climbs is
+// c1 = bb + r, on one it descends c1 = bb + 1 - r; the face is open (not the
+// grid's edge) when 1 <= c1 <= n - 1, and its bound is one fma.
+__device__ __forceinline__ int skip_cube_ray(const Scene& S, const SkipRay& R, const float g[3], const float ig[3],
+                                             const uint32_t bb[3], uint32_t r, int sh, int k, int n)
+{
+    float s_exit = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int c1 = g[a] > 0.0f ? (int)(bb[a] + r) : (int)bb[a] + 1 - (int)r;
+        const bool open = (uint32_t)(c1 - 1) < R.nopen[a];
+        const float sa = fmaf((float)(c1 << sh), ig[a], R.kb[a]);
+        s_exit = open ? fminf(s_exit, sa) : s_exit;
+    }
+    const float lim = (s_exit - S.skip_c) * S.inv_step;
+    int next = n;
+    if (lim < (float)n) next = (int)ceilf(lim);
+    return min(max(next, k + 1), n);
 }
 
 // Whether samples of empty bricks may be passed over: the volume is in the
@@ -528,6 +554,7 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
         ig[a] = g[a] != 0.0f ? 1.0f / g[a] : 0.0f;
     }
     const bool skipping = skip && Lay<LAYOUT>::bricked;
+    const SkipRay SR = skip_ray(S, u0, g, ig);
     float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t cur_b = 0xFFFFFFFFu;
     uint32_t cur_r = 0u;         // distance byte of brick cur_b (0: occupied)
@@ -556,7 +583,7 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
                     if constexpr (DIST) {
                         // empty brick: leave the cube of empty bricks around it
                         const uint32_t bb[3] = {c.x0 >> B, c.y0 >> B, c.z0 >> B};
-                        next = skip_cube(S, u0, g, ig, bb, cur_r, B, k, n);
+                        next = skip_cube_ray(S, SR, g, ig, bb, cur_r, B, k, n);
                     } else {
                         // empty brick: leave its group of 4^3 bricks if that is empty too, else the brick
                         const uint32_t m[3] = {c.x0 >> (B + 2), c.y0 >> (B + 2), c.z0 >> (B + 2)};

@@ -77,6 +77,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
         g[a] = d[a] * S.inv_sp[a];
         ig[a] = g[a] != 0.0f ? 1.0f / g[a] : 0.0f;
     }
+    const SkipRay SR = skip_ray(S, u0, g, ig);
     // the wave's march axis: the largest |g| of its first ray that hits, the same sign and
     // |g_M| >= 0.25 on every ray that hits, else every lane marches through the caches
     const uint64_t hm = __ballot(hit);
@@ -117,7 +118,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
                 }
                 if (cur_r != 0u) {
                     const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                    const int next = skip_cube(S, u0, g, ig, bb, cur_r, 2, k, n);
+                    const int next = skip_cube_ray(S, SR, g, ig, bb, cur_r, 2, k, n);
                     if (COUNT) cnt += (uint32_t)(next - k);
                     k = next;
                     continue;
@@ -213,7 +214,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
                 }
                 if (cur_r != 0u) {
                     const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                    const int next = skip_cube(S, u0, g, ig, bb, cur_r, 2, k, n);
+                    const int next = skip_cube_ray(S, SR, g, ig, bb, cur_r, 2, k, n);
                     if (COUNT) cnt += (uint32_t)(next - k);
                     k = next;
                     continue;
