@@ -45,8 +45,8 @@ ADJ_FLOPS_PER_SAMPLE = 142
 # to TCC_ATOMIC_sum: every density-gradient atomic goes beyond the L2) and HBM
 # bytes (FETCH_SIZE x 1.9999 + WRITE_SIZE, the bitwise-NOT calibration of the
 # forward's traffic figure), per evaluated sample.
-ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539723 / 19674760,
-                    "hbm_bytes_per_evaluated_sample": (70913.375 * 1048576 / 524316.625 + 653105.03125) * 1024
+ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539636 / 19674760,
+                    "hbm_bytes_per_evaluated_sample": (70766.4375 * 1048576 / 524316.375 + 653101.8125) * 1024
                     / 19674760,
                     "source": "profiles/raycast_bwd_fit_256_counters.md"}
 
@@ -54,10 +54,10 @@ ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539723 / 19674760,
 # FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of
 # --traffic-probe, each scaled by what the same counter reads for a kernel of
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
-# 524316 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
+# 524316.4 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 2883219.3125, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.0,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "8abf653f5968880a"}
+RAYCAST_TRAFFIC = {"fetch_kib": 2916099.625, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.375,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "72e57ac9090a1f76"}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
 RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "raycast_staged.h", "brick_dev.h", "common.h", "entropy_dev.h")
@@ -817,7 +817,7 @@ def main():
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
-                                 "TD_busy": 0.85, "TA_busy": 0.62, "VALU_busy": 0.83,
+                                 "TD_busy": 0.87, "TA_busy": 0.64, "VALU_busy": 0.82,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "render_tuning": res["render_tuning"],
         "raycast_staged": res["raycast_staged"],
