@@ -147,6 +147,25 @@ def test_pyramid_in_disc(shape, rname):
     assert np.array_equal(u16_np(v), a)                  # the input is left as it was
 
 
+@pytest.mark.parametrize("shape", [(45, 97, 131), (40, 64, 512)])
+def test_pyramid_in_disc_eight_levels_with_sums(shape):
+    """The in-disc pass with levels past the fourth (summed from its exact level-4
+    sums) and every level's exact sums, against the oracle on the container-removed
+    volume."""
+    a = _rand_vol(shape, 5)
+    rec = np.array(RECORDS["crosses_border"], dtype=np.int32)
+    cleaned = K.remove_container(a, rec)
+    bits = _keep_variants(a, rec)["lookup"]
+    banner(f"container: 8-level pyramid in disc {shape}")
+    levels, sums = vr.vr_threshold_downsample(to_dev_u16(a), bits_to_dev(bits), 8,
+                                              circle=torch.from_numpy(rec).to(dev()), sums=True)
+    f = O.apply_keep(cleaned, bits)
+    for k in range(1, 9):
+        S = O.box_sums(f, k)
+        assert np.array_equal(sums[k - 1].cpu().numpy(), S), k
+        assert np.array_equal(u16_np(levels[k - 1]), O.level_from_sums(S, k)), k
+
+
 def test_pipeline_with_container_matches_oracle():
     banner("container: preview pipeline on the small contained scene")
     a = synth.to_numpy_u16(synth.make_volume(synth.SMALL_CONTAINED))

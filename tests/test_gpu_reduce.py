@@ -211,7 +211,7 @@ def test_pyramid_rejects_bad_levels():
 
 
 # shapes (nz, ny, nx) whose level-4 grid is ragged, so that the level-5..8 boxes are clipped
-DEEP_SHAPES = [(37, 50, 29), (96, 17, 260), (129, 64, 33), (16, 16, 16)]
+DEEP_SHAPES = [(37, 50, 29), (96, 17, 260), (129, 64, 33), (16, 16, 16), (1, 1, 1), (5, 3, 2)]
 
 
 @pytest.mark.parametrize("shape", DEEP_SHAPES)
