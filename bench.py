@@ -56,11 +56,12 @@ ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539636 / 19674760,
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
 # 524316.4 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 2916099.625, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.375,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "72e57ac9090a1f76"}
+RAYCAST_TRAFFIC = {"fetch_kib": 2840041.4375, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.5625,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "a20cc085bf2e31f8", "mark_above": 3854}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
-RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "raycast_staged.h", "brick_dev.h", "common.h", "entropy_dev.h")
+RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "raycast_staged.h", "brick_dev.h", "brick.hip", "common.h",
+                   "entropy_dev.h")
 
 
 # The paper's own timings (other hardware, other workloads): context beside
@@ -76,14 +77,15 @@ PAPER_FIGURES = {
 }
 
 
-def raycast_traffic():
-    """The counted traffic of the ray caster, or None once its sources changed."""
+def raycast_traffic(mark_above=RAYCAST_TRAFFIC["mark_above"]):
+    """The counted traffic of the ray caster, or None once its sources (or the
+    level its bricks are marked above) differ from those measured."""
     import hashlib
     h = hashlib.sha256()
     for f in RAYCAST_SOURCES:
         with open(os.path.join(ROOT, "paper_2311_15038_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != RAYCAST_TRAFFIC["sources_sha256_16"]:
+    if h.hexdigest()[:16] != RAYCAST_TRAFFIC["sources_sha256_16"] or mark_above != RAYCAST_TRAFFIC["mark_above"]:
         return None
     return RAYCAST_TRAFFIC["bytes"]
 
@@ -152,12 +154,13 @@ def run_gpu(steps, warmup):
     # the depth-window march with LDS staging, on a 4^3-brick copy of the same level
     from paper_2311_15038_amd import vr
     c = pipe.cfg
-    b4 = pipe.render_vol if pipe.render_vol.layout == vr.LAYOUT_BRICK4 else vr.vr_brick_volume(pipe.levels[0])
+    b4 = pipe.render_vol if pipe.render_vol.layout == vr.LAYOUT_BRICK4 else vr.vr_brick_volume(pipe.levels[0], mark_above=pipe.mark_above)
     staged_out = torch.empty_like(pipe.frames)
     staged_ms = _median_ms(lambda: vr.vr_raycast(b4, pipe.tf, pipe.cams, c.width, c.height, c.step,
                                                  ert_eps=c.ert_eps, out=staged_out, staged=True), 3)
     staged_same = bool(torch.equal(staged_out, pipe.frames))
     out = {
+        "mark_above": pipe.mark_above,
         "render_tuning": {"brick_edge": edge, "ms_bricks_plus_frames": {str(k): v for k, v in edge_ms.items()}},
         "raycast_staged": {"ms": staged_ms, "frames_identical": staged_same},
         "samples_per_step": samples,
@@ -809,7 +812,8 @@ def main():
                                 "step 0.5, ERT 2^-14"),
                    "volume": [1024, 1024, 1024], "levels": 4, "views": 36, "image": [512, 512]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": raycast_traffic(),
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": raycast_traffic(res["mark_above"]),
                      "traffic_unit": "B per launch (HBM read + write, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "algorithmic_bytes": res["raycast_alg_bytes"],
                      "kernel": f"raycast_fwd<u16,brick{res['render_tuning']['brick_edge']}>",
@@ -817,9 +821,10 @@ def main():
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
-                                 "TD_busy": 0.87, "TA_busy": 0.64, "VALU_busy": 0.82,
+                                 "TD_busy": 0.86, "TA_busy": 0.63, "VALU_busy": 0.81,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "render_tuning": res["render_tuning"],
+        "brick_mark_above": res["mark_above"],
         "raycast_staged": res["raycast_staged"],
         "raycast_Gsamples_per_s": samples / (rc_ms * 1e-3) / 1e9,
         "raycast_evaluated_Gsamples_per_s": evaluated / (rc_ms * 1e-3) / 1e9,

@@ -285,18 +285,25 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  * volume as 4 x 4 x 4-voxel bricks, brick (bx, by, bz) at element
  * ((bz*nby + by)*nbx + bx)*64 with nbx = ceil(nx / 4) (and so on), voxel (x, y, z) at
  * ((z&3)*16 + (y&3)*4 + (x&3)) inside it (voxels past the volume's end are 0).
- * Optional occupancy: one byte per brick, non-zero iff a non-zero voxel is
- * one of the 8 taps of a trilinear fetch whose base (floor, clamped) tap lies
- * in that brick, followed by one byte per 4 x 4 x 4 bricks (16^3 voxels,
+ * Optional occupancy: one byte per brick, non-zero iff a marking voxel (one
+ * above mark_above: with mark_above 0, any non-zero voxel) is one of the 8
+ * taps of a trilinear fetch whose base (floor, clamped) tap lies in that
+ * brick, followed by one byte per 4 x 4 x 4 bricks (16^3 voxels,
  * [ceil(nbz/4)][ceil(nby/4)][ceil(nbx/4)]) that is non-zero iff any of its
  * bricks is, then one byte per brick (brick order) holding the Chebyshev
  * distance in bricks, max over axes of |b - b'|, to the nearest occupied
  * brick b', capped at VR_BRICK_DIST_CAP (0 for an occupied brick; the cap
  * where none is nearer), then one byte per brick of working storage.  The
- * ray caster passes over samples of unoccupied bricks when the transfer
- * function's first entry has zero extinction: such samples have density 0
- * and change neither colour nor transmittance, so the result is
- * bit-identical.  From an empty brick whose distance is r it leaves in one
+ * ray caster passes over samples of unoccupied bricks when every transfer-
+ * function entry such a sample can reach has zero extinction (and finite
+ * colour): with mark_above 0 the sample has density 0 and reaches entry 0;
+ * with mark_above V > 0 its eight taps are at most V, so its TF coordinate
+ * s * 255 / 65535 stays below floor(V * 255 / 65535 * (1 + 2^-16)) + 1 and it
+ * reaches the entries up to one past that (vr_volume.occupancy_above passes V
+ * to the ray caster, which checks those entries on the device and otherwise
+ * marches every sample).  Such samples change neither colour nor
+ * transmittance, so the result is bit-identical.  A caller whose TF has zero
+ * extinction up to entry z - 1 (z >= 2) may use V = 257 * (z - 1) - 1.  From an empty brick whose distance is r it leaves in one
  * step the cube of bricks within r - 1 of it, all of them empty.
  * Layout VR_LAYOUT_BRICK4_PAIRS orders elements the same way, but element
  * (x, y, z) holds two voxels, (x, y, z) then (min(x + 1, nx - 1), y, z)
@@ -314,11 +321,12 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  *     overwritten.
  *   d_occupancy: NULL or the occupancy_bytes of vr_brick_count_layout,
  *     overwritten.
+ *   mark_above: the marking level V, 0..65535 for u16; 0 for f32.
  * Errors: VR_ERR_NULL, VR_ERR_DTYPE, VR_ERR_DIMS, VR_ERR_RANGE (layout,
- * alignment), VR_ERR_HIP.
+ * alignment, mark_above), VR_ERR_HIP.
  */
 int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t nx, int64_t ny, int64_t nz,
-                    void* d_bricked, uint8_t* d_occupancy, void* stream);
+                    void* d_bricked, uint8_t* d_occupancy, int32_t mark_above, void* stream);
 
 /*
  * Inverse of vr_brick_volume for VR_LAYOUT_BRICK4: writes the [nz][ny][nx]
@@ -354,6 +362,7 @@ typedef struct {
     int64_t nx, ny, nz;
     double spacing[3];         /* world units per voxel along x, y, z (> 0) */
     const uint8_t* occupancy;  /* NULL, or the brick occupancy (brick layouts only) */
+    int32_t occupancy_above;   /* the mark_above the occupancy was built with (0: non-zero voxels) */
 } vr_volume;
 
 /* A pinhole (fov_y_deg > 0) or orthographic (fov_y_deg == 0) camera. */
@@ -459,7 +468,8 @@ int vr_entropy_from_counts(const uint32_t* d_hist, int n_views, int64_t pixels, 
  * bricks, to be brought back with vr_unbrick_volume).  The brick layout is
  * the faster one: a cell's eight taps share one or two cache lines there, and
  * the gradient's atomics go out a cache line at a time.  vol->occupancy may be NULL, or the
- * occupancy grid that vr_brick_volume wrote for the same grid: then, when the
+ * occupancy grid that vr_brick_volume wrote for the same grid (marks of
+ * non-zero voxels: occupancy_above is 0 for f32): then, when the
  * TF's first segment has zero extinction (tf[0].sigma = tf[1].sigma = 0,
  * finite colour), runs of samples whose base tap lies in an empty brick are
  * not marched.  Their colour, transmittance and density gradient are

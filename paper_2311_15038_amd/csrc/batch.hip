@@ -199,7 +199,7 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
             // 8-voxel row pieces [a, b), one per thread
             for (int64_t r = t.a + tid; r < t.b; r += kT)
                 vr::bk::row8_body<uint16_t>(it.level1, it.lx, it.ly, it.lz, it.nbx, it.nby, it.bricked, it.occ,
-                                            it.occ + (int64_t)it.nbx * it.nby * it.nbz, it.nmx, it.nmy, r);
+                                            it.occ + (int64_t)it.nbx * it.nby * it.nbz, it.nmx, it.nmy, 0u, r);
             signal(cnt + C_BRICK);
             break;
         }
@@ -216,7 +216,7 @@ __device__ void run_task(const BatchDev& B, const Task& t, BatchLds& L)
             const int bz = (int)(ss / ((int64_t)it.nslab_x * it.nby));
             vr::bk::slab_body<uint16_t>(it.level1, it.lx, it.ly, it.lz, it.nbx, it.nby, it.bricked, it.occ,
                                         it.occ + (int64_t)it.nbx * it.nby * it.nbz, it.nmx, it.nmy,
-                                        sx * 16, by, bz, active, lt, L.brick[g]);
+                                        0u, sx * 16, by, bz, active, lt, L.brick[g]);
         }
         signal(cnt + C_BRICK);
         break;

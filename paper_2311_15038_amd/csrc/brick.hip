@@ -17,10 +17,10 @@ template <typename T, bool PAIRS, bool VEC>
 __global__ void __launch_bounds__(kThreads)
 brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
              typename ElemOf<T, PAIRS>::type* __restrict__ dst, uint8_t* __restrict__ occ,
-             uint8_t* __restrict__ macro, int nmx, int nmy)
+             uint8_t* __restrict__ macro, int nmx, int nmy, uint32_t above)
 {
     __shared__ SlabLds<T, PAIRS> G;
-    slab_body<T, PAIRS, VEC>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, blockIdx.x * 16, blockIdx.y,
+    slab_body<T, PAIRS, VEC>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, blockIdx.x * 16, blockIdx.y,
                         blockIdx.z, true, threadIdx.x, G);
 }
 
@@ -71,26 +71,28 @@ void launch_dist(hipStream_t s, const uint8_t* in, uint8_t* out, int nbx, int nb
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 brick8_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby, T* __restrict__ dst,
-              uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx, int nmy)
+              uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx, int nmy, uint32_t above)
 {
     const int64_t n = (int64_t)nbx * (nby * 8) * ((nz + 7) / 8 * 8);
     for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads)
-        row8_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, r);
+        row8_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, r);
 }
 
 // Rows load four voxels at a time when nx is a multiple of 4 and src is
 // aligned to four voxels.
 template <typename T, bool PAIRS>
 void launch_brick(dim3 grid, hipStream_t s, const void* src, int nx, int ny, int nz, int nbx, int nby,
-                  void* dst, uint8_t* occ, uint8_t* macro, int nmx, int nmy)
+                  void* dst, uint8_t* occ, uint8_t* macro, int nmx, int nmy, uint32_t above)
 {
     const bool vec = nx % 4 == 0 && reinterpret_cast<uintptr_t>(src) % (4 * sizeof(T)) == 0;
     const auto* sp = static_cast<const T*>(src);
     auto* dp = static_cast<typename ElemOf<T, PAIRS>::type*>(dst);
     if (vec)
-        brick_kernel<T, PAIRS, true><<<grid, kThreads, 0, s>>>(sp, nx, ny, nz, nbx, nby, dp, occ, macro, nmx, nmy);
+        brick_kernel<T, PAIRS, true><<<grid, kThreads, 0, s>>>(sp, nx, ny, nz, nbx, nby, dp, occ, macro, nmx, nmy,
+                                                               above);
     else
-        brick_kernel<T, PAIRS, false><<<grid, kThreads, 0, s>>>(sp, nx, ny, nz, nbx, nby, dp, occ, macro, nmx, nmy);
+        brick_kernel<T, PAIRS, false><<<grid, kThreads, 0, s>>>(sp, nx, ny, nz, nbx, nby, dp, occ, macro, nmx, nmy,
+                                                                above);
 }
 
 }  // namespace
@@ -128,12 +130,16 @@ extern "C" int vr_brick_count_layout(int layout, int64_t nx, int64_t ny, int64_t
 }
 
 extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t nx, int64_t ny,
-                               int64_t nz, void* d_bricked, uint8_t* d_occupancy, void* stream)
+                               int64_t nz, void* d_bricked, uint8_t* d_occupancy, int32_t mark_above,
+                               void* stream)
 {
     vr::clear_error();
     VR_REQUIRE(d_src && d_bricked, VR_ERR_NULL, "vr_brick_volume: NULL pointer");
     VR_REQUIRE(dtype == VR_U16_NORM || dtype == VR_F32, VR_ERR_DTYPE, "vr_brick_volume: dtype %d",
                dtype);
+    VR_REQUIRE(mark_above >= 0 && mark_above <= 65535 && (dtype == VR_U16_NORM || mark_above == 0), VR_ERR_RANGE,
+               "vr_brick_volume: mark_above %d (0..65535 for u16, 0 for f32)", (int)mark_above);
+    const uint32_t above = (uint32_t)mark_above;
     VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS || layout == VR_LAYOUT_BRICK8,
                VR_ERR_RANGE, "vr_brick_volume: layout %d is not a brick layout", layout);
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
@@ -166,17 +172,17 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
         if (dtype == VR_U16_NORM)
             brick8_kernel<uint16_t><<<g8, kThreads, 0, s>>>(static_cast<const uint16_t*>(d_src), inx, iny, inz, nbx,
                                                             nby, static_cast<uint16_t*>(d_bricked), d_occupancy, macro,
-                                                            nmx, nmy);
+                                                            nmx, nmy, above);
         else
             brick8_kernel<float><<<g8, kThreads, 0, s>>>(static_cast<const float*>(d_src), inx, iny, inz, nbx, nby,
                                                          static_cast<float*>(d_bricked), d_occupancy, macro, nmx,
-                                                         nmy);
+                                                         nmy, above);
     } else if (dtype == VR_U16_NORM) {
-        if (pairs) launch_brick<uint16_t, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
-        else launch_brick<uint16_t, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
+        if (pairs) launch_brick<uint16_t, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy, above);
+        else launch_brick<uint16_t, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy, above);
     } else {
-        if (pairs) launch_brick<float, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
-        else launch_brick<float, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy);
+        if (pairs) launch_brick<float, true>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy, above);
+        else launch_brick<float, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy, above);
     }
     int rc = vr::check_launch("vr_brick_volume");
     if (rc || !d_occupancy) return rc;

@@ -1,11 +1,11 @@
 // Device-side render-layout conversion (shared with the batched persistent
 // kernel).  Render layout of a volume level: 4 x 4 x 4-voxel bricks (a 128-byte line
 // for u16) and an occupancy grid that tells the ray caster where every tap of
-// a trilinear fetch is zero.
+// a trilinear fetch is zero (or, for u16 with a marking level V > 0, at most V).
 //
 // Brick (bx, by, bz) starts at element ((bz * nby + by) * nbx + bx) * 64 and
 // voxel (x, y, z) sits at ((z & 3) * 16 + (y & 3) * 4 + (x & 3)) inside it.
-// occupancy[b] != 0 iff some non-zero voxel is one of the eight taps of a
+// occupancy[b] != 0 iff some marking voxel (non-zero; above V) is one of the eight taps of a
 // trilinear fetch whose base tap (the floor corner, clamped to the volume)
 // lies in brick b; a voxel at (x, y, z) is a tap for base taps
 // (x - {0,1}, y - {0,1}, z - {0,1}), so it marks up to eight bricks.  A second
@@ -31,8 +31,10 @@ namespace bk {
 constexpr int kThreads = 256;      // threads of one slab group
 constexpr int kDistCap = VR_BRICK_DIST_CAP;   // cap of the brick distance grid (bricks)
 
-template <typename T>
-__device__ __forceinline__ bool nonzero(T v) { return v != (T)0; }
+// Whether a voxel marks its bricks: a u16 voxel above `above` (0: any non-zero
+// voxel), an f32 voxel that is non-zero (`above` is 0 for f32).
+__device__ __forceinline__ bool marks(uint16_t v, uint32_t above) { return (uint32_t)v > above; }
+__device__ __forceinline__ bool marks(float v, uint32_t) { return v != 0.0f; }
 
 // Element of the pair layout: (voxel x, voxel x + 1) in one load.
 template <typename T> struct PairOf;
@@ -81,8 +83,8 @@ struct SlabLds {
 template <typename T, bool PAIRS = false, bool VEC = false>
 __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
                                  typename ElemOf<T, PAIRS>::type* __restrict__ dst, uint8_t* __restrict__ occ,
-                                 uint8_t* __restrict__ macro, int nmx, int nmy, int bx0, int by, int bz,
-                                 bool active, int t, SlabLds<T, PAIRS>& G)
+                                 uint8_t* __restrict__ macro, int nmx, int nmy, uint32_t above, int bx0, int by,
+                                 int bz, bool active, int t, SlabLds<T, PAIRS>& G)
 {
     typedef typename ElemOf<T, PAIRS>::type P;
     if (t < 17 * 4) G.marks[t] = 0;
@@ -120,10 +122,10 @@ __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int 
         if (occ != nullptr) {
             bool any = false;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) any |= nonzero(v[e]);
+            for (int e = 0; e < 4; ++e) any |= marks(v[e], above);
             if (any) {
                 // a voxel at x marks the base-tap bricks of x and x - 1 (and likewise in y, z)
-                const int xs[2] = {lb + 1, nonzero(v[0]) ? lb : -1};          // index into -1..15 (+1)
+                const int xs[2] = {lb + 1, marks(v[0], above) ? lb : -1};          // index into -1..15 (+1)
                 const int ys[2] = {1, (r & 3) == 0 ? 0 : -1};
                 const int zs[2] = {1, (r >> 2) == 0 ? 0 : -1};
 #pragma unroll
@@ -172,7 +174,7 @@ __device__ inline void slab_body(const T* __restrict__ src, int nx, int ny, int 
 template <typename T>
 __device__ inline void row8_body(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
                                  T* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro,
-                                 int nmx, int nmy, int64_t r)
+                                 int nmx, int nmy, uint32_t above, int64_t r)
 {
     const int bx = (int)(r % nbx);
     const int64_t yz = r / nbx;
@@ -199,10 +201,10 @@ __device__ inline void row8_body(const T* __restrict__ src, int nx, int ny, int 
     if (occ == nullptr) return;
     bool any = false;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) any |= nonzero(v[e]);
+    for (int e = 0; e < 8; ++e) any |= marks(v[e], above);
     if (!any) return;
     const int by = y >> 3, bz = z >> 3;
-    const int xs[2] = {bx, (nonzero(v[0]) && bx > 0) ? bx - 1 : -1};
+    const int xs[2] = {bx, (marks(v[0], above) && bx > 0) ? bx - 1 : -1};
     const int ys[2] = {by, ((y & 7) == 0 && by > 0) ? by - 1 : -1};
     const int zs[2] = {bz, ((z & 7) == 0 && bz > 0) ? bz - 1 : -1};
 #pragma unroll

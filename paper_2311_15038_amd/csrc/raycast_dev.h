@@ -6,6 +6,7 @@
 // so every includer computes bit-identical samples.
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 
 #include "brick_dev.h"
@@ -42,6 +43,7 @@ struct Views {
 struct Scene {
     const void* data;
     const uint8_t* occ;     // brick occupancy or NULL
+    int skip_knots;         // leading TF knots a sample of an unmarked brick can reach (1..256)
     const uint8_t* dist;    // brick distance grid (with occ), or NULL: skip by 16^3 groups instead
     int nx, ny, nz;
     int nbx, nby, nbz;      // bricks per axis (4^3 or 8^3 voxels)
@@ -371,14 +373,21 @@ __device__ __forceinline__ int skip_cube_ray(const Scene& S, const SkipRay& R, c
     return min(max(next, k + 1), n);
 }
 
-// Whether samples of empty bricks may be passed over: the volume is in the
-// brick layout with an occupancy grid and density 0 has zero extinction
-// (finite colour), so such samples leave colour and transmittance
-// bit-for-bit unchanged.
+// Whether samples of unmarked bricks may be passed over: the volume is in a
+// brick layout with an occupancy grid, and every TF knot such a sample can
+// reach (the first S.skip_knots: knot 0 when the marks are of non-zero voxels)
+// has zero extinction and finite colour, so those samples leave colour and
+// transmittance bit-for-bit unchanged.  Called by whole waves (the lanes share
+// the knots out and vote).
 __device__ __forceinline__ bool can_skip(const Scene& S, const TfLds& tf)
 {
-    return S.occ != nullptr && tf.a[0].w == 0.0f && isfinite(tf.a[0].x) && isfinite(tf.a[0].y) &&
-           isfinite(tf.a[0].z);
+    if (S.occ == nullptr) return false;
+    bool ok = true;
+    for (int q = (int)(threadIdx.x & 63); q < S.skip_knots; q += 64) {
+        const float4 a = tf.a[q];
+        ok = ok && a.w == 0.0f && isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
+    }
+    return __all(ok) != 0;
 }
 
 template <bool WIDE>
@@ -640,6 +649,19 @@ inline bool needs_wide(const Scene& S) { return S.wide != 0; }
 
 // ------------------------------------------------------------ host side
 
+// TF knots a sample can reach when all eight of its taps are at most
+// `above` (u16 units): the trilinear lerps keep it at most `above` up to a few
+// float roundings (a relative 2^-16 bounds them with room to spare), so its TF
+// coordinate s * 255 / 65535 lies below k + 1 for the k below, and the lookup
+// blends knots k and k + 1 at most.  With above = 0 the sample is exactly 0
+// and the lookup returns knot 0.
+inline int skip_knots(int above)
+{
+    if (above == 0) return 1;
+    const double x = (double)above * 255.0 / 65535.0 * (1.0 + 1.0 / 65536.0);
+    return std::min(254, (int)std::floor(x)) + 2;
+}
+
 inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera* h_cams, int n_views,
                 const vr_render_opts* o, Scene& S)
 {
@@ -687,8 +709,12 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
                    VR_ERR_RANGE, "raycast: camera %d has fov %g / half height %g", v, c.fov_y_deg,
                    c.ortho_half_h);
     }
+    VR_REQUIRE(vol->occupancy_above >= 0 && vol->occupancy_above <= 65535 &&
+                   (vol->dtype == VR_U16_NORM || vol->occupancy_above == 0),
+               VR_ERR_RANGE, "raycast: occupancy_above %d (0..65535 for u16, 0 for f32)", (int)vol->occupancy_above);
     S.data = vol->data;
     S.occ = vol->occupancy;
+    S.skip_knots = skip_knots(vol->occupancy_above);
     S.nbx = (int)nb[0];
     S.nby = (int)nb[1];
     S.nbz = (int)nb[2];

@@ -40,6 +40,7 @@ class PreviewConfig:
     brick_edge: int = 4             # ... of 4^3 or 8^3 voxels (see tune_brick_edge)
     pairs: bool = False             # ... of x-tap pairs (4^3 only; two voxels per load, twice the memory)
     skip_empty: bool = True         # with the brick occupancy (exact)
+    mark_by_tf: bool = True         # ... marking voxels above the level the TF leaves empty (exact)
     container: bool = False         # remove the sample container (Section III-B)
     container_radii: tuple | None = None   # (r_min, r_max); None: [min side / 8, min side / 2]
     container_shift: int = 4        # edges: |g|^2 >= 2^-shift of the largest
@@ -86,7 +87,11 @@ class PreviewPipeline:
             self.cams = synth.turntable_cameras(rx, ry, rz, n_views=cfg.n_views, fov_deg=cfg.fov_deg)
         nv = len(self.cams)
         self.frames = torch.empty((nv, cfg.height, cfg.width, 4), dtype=torch.float32, device=dev)
-        self.tf = torch.from_numpy(synth.default_tf() if tf is None else tf).to(dev)
+        tf_host = synth.default_tf() if tf is None else tf
+        self.tf = torch.from_numpy(tf_host).to(dev)
+        # bricks whose voxels are all at or below this level hold only samples of zero
+        # extinction under this TF (the ray caster checks the TF again on the device)
+        self.mark_above = vr.tf_mark_level(tf_host) if cfg.skip_empty and cfg.mark_by_tf else 0
         self.samples = torch.zeros(2, dtype=torch.int64, device=dev)
         # best-view snapshot of the frames (Section III-C, Eq. 2)
         self.view_hist = torch.empty((nv, 256), dtype=torch.int32, device=dev)
@@ -159,7 +164,7 @@ class PreviewPipeline:
             src = self.hollow_level
         if self.render_vol is not None:
             vr.vr_brick_volume(src, out=self.render_vol, stream=stream, pairs=self.cfg.pairs,
-                               edge=self.cfg.brick_edge)
+                               edge=self.cfg.brick_edge, mark_above=self.mark_above)
             src = self.render_vol
         vr.vr_raycast(src, self.tf, self.cams, c.width, c.height, c.step,
                       ert_eps=c.ert_eps, out=self.frames, samples=self.samples if count else None,
@@ -191,7 +196,8 @@ class PreviewPipeline:
         src = level
         if self.render_vol is not None:
             out.append(("bricks", lambda: vr.vr_brick_volume(level, out=self.render_vol, stream=stream,
-                                                             pairs=c.pairs, edge=c.brick_edge)))
+                                                             pairs=c.pairs, edge=c.brick_edge,
+                                                             mark_above=self.mark_above)))
             src = self.render_vol
         out.append(("raycast", lambda src=src: vr.vr_raycast(src, self.tf, self.cams, c.width, c.height,
                                                              c.step, ert_eps=c.ert_eps, out=self.frames,
@@ -244,11 +250,11 @@ def tune_brick_edge(pipe: PreviewPipeline, reps: int = 3, use_cache: bool = True
         return int(cache[key]), {}
     times = {}
     for edge in (4, 8):
-        bv = vr.vr_brick_volume(level, edge=edge)
+        bv = vr.vr_brick_volume(level, edge=edge, mark_above=pipe.mark_above)
         out = torch.empty_like(pipe.frames)
 
         def run():
-            vr.vr_brick_volume(level, out=bv, edge=edge)
+            vr.vr_brick_volume(level, out=bv, edge=edge, mark_above=pipe.mark_above)
             vr.vr_raycast(bv, pipe.tf, pipe.cams, c.width, c.height, c.step, ert_eps=c.ert_eps, out=out)
 
         run()

@@ -40,7 +40,7 @@ class VrError(RuntimeError):
 class vr_volume(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("layout", C.c_int32),
                 ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
-                ("spacing", C.c_double * 3), ("occupancy", C.c_void_p)]
+                ("spacing", C.c_double * 3), ("occupancy", C.c_void_p), ("occupancy_above", C.c_int32)]
 
 
 class vr_camera(C.Structure):
@@ -107,7 +107,7 @@ def lib():
                                  C.POINTER(vr_render_opts), vp, vp, vp]
         L.vr_raycast_backward.argtypes = [C.POINTER(vr_volume), vp, C.POINTER(vr_camera), i32,
                                           C.POINTER(vr_render_opts), vp, vp, vp, vp, vp]
-        L.vr_brick_volume.argtypes = [vp, i32, i32, i64, i64, i64, vp, vp, vp]
+        L.vr_brick_volume.argtypes = [vp, i32, i32, i64, i64, i64, vp, vp, i32, vp]
         L.vr_unbrick_volume.argtypes = [vp, i32, i64, i64, i64, vp, vp]
         L.vr_frame_entropy.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.vr_entropy_from_counts.argtypes = [vp, i32, i64, vp, vp, vp]
@@ -395,21 +395,37 @@ def vr_brick_count(nx, ny, nz):
     return int(n.value), int(o.value)
 
 
+def tf_mark_level(tf) -> int:
+    """A brick-marking level V (u16 units) for this TF under which samples of
+    unmarked bricks (all eight taps at most V) leave its render unchanged: with
+    the first z knots of zero extinction and finite colour, 257 (z - 1) - 1
+    (z >= 2; such a sample's TF coordinate stays below z - 1), else 0.
+    tf: [256][4] (r, g, b, sigma), host array or tensor."""
+    a = np.asarray(tf.detach().cpu() if isinstance(tf, torch.Tensor) else tf, dtype=np.float64).reshape(256, 4)
+    ok = (a[:, 3] == 0.0) & np.isfinite(a[:, :3]).all(axis=1)
+    z = 256 if ok.all() else int(np.argmin(ok))
+    return 257 * (z - 1) - 1 if z >= 2 else 0
+
+
 class BrickedVolume:
     """A volume in a brick render layout (4^3 bricks, 4^3 bricks of x-tap pairs,
-    or 8^3 bricks), with its occupancy grid (or None)."""
+    or 8^3 bricks), with its occupancy grid (or None) and the level its marks
+    are above (mark_above)."""
 
-    def __init__(self, data, shape, occupancy=None, layout=None):
+    def __init__(self, data, shape, occupancy=None, layout=None, mark_above=0):
         self.data, self.shape, self.occupancy = data, tuple(shape), occupancy
         self.layout = LAYOUT_BRICK4 if layout is None else layout
+        self.mark_above = int(mark_above)
         self.dtype = data.dtype
         self.device = data.device
 
 
-def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False, edge=4) -> BrickedVolume:
+def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False, edge=4,
+                    mark_above=0) -> BrickedVolume:
     """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy):
     bricks of `edge` (4 or 8) voxels; with pairs, the 4^3 layout of x-tap pairs
-    (twice the memory)."""
+    (twice the memory).  The occupancy marks voxels above mark_above (u16 only;
+    tf_mark_level gives the largest level a TF allows)."""
     nz, ny, nx = src.shape
     dt = U16_NORM if src.dtype in _U16 else F32
     if edge not in (4, 8) or (pairs and edge != 4):
@@ -419,12 +435,13 @@ def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False
     if out is None:
         data = torch.empty(nel, dtype=src.dtype, device=src.device)
         occ = torch.empty(nocc, dtype=torch.uint8, device=src.device) if with_occupancy else None
-        out = BrickedVolume(data, (nz, ny, nx), occ, layout)
+        out = BrickedVolume(data, (nz, ny, nx), occ, layout, mark_above)
     if out.layout != layout:
         raise ValueError("out has a different brick layout")
+    out.mark_above = int(mark_above)
     occp = None if out.occupancy is None else _dev(out.occupancy, "occupancy", torch.uint8, nocc)
     _check(lib().vr_brick_volume(_dev(src, "src", (*_U16, torch.float32)), dt, layout, nx, ny, nz,
-                                 _dev(out.data, "bricked", src.dtype, nel), occp,
+                                 _dev(out.data, "bricked", src.dtype, nel), occp, int(mark_above),
                                  _stream(stream)))
     return out
 
@@ -448,11 +465,11 @@ def vr_unbrick_volume(bricked, out=None, stream=None):
 def make_volume(data, spacing=(1.0, 1.0, 1.0)):
     """vr_volume for a uint16 (normalised) or float32 tensor [nz][ny][nx], or a BrickedVolume."""
     if isinstance(data, BrickedVolume):
-        t, layout, shape = data.data, data.layout, data.shape
+        t, layout, shape, above = data.data, data.layout, data.shape, data.mark_above
         occ = None if data.occupancy is None else _dev(
             data.occupancy, "occupancy", torch.uint8, vr_brick_count_layout(layout, *shape[::-1])[2]).value
     else:
-        t, layout, shape, occ = data, LAYOUT_LINEAR, data.shape, None
+        t, layout, shape, occ, above = data, LAYOUT_LINEAR, data.shape, None, 0
     if t.dtype in _U16:
         dt = U16_NORM
     elif t.dtype == torch.float32:
@@ -461,7 +478,7 @@ def make_volume(data, spacing=(1.0, 1.0, 1.0)):
         raise TypeError(f"unsupported volume dtype {t.dtype}")
     nz, ny, nx = shape
     return vr_volume(_dev(t, "volume").value, dt, layout, nx, ny, nz,
-                     (C.c_double * 3)(*[float(s) for s in spacing]), occ)
+                     (C.c_double * 3)(*[float(s) for s in spacing]), occ, above)
 
 
 def vol_shape(data):

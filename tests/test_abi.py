@@ -86,6 +86,13 @@ def test_raycast_validation_on_the_host(lib):
     vol.spacing[1] = 0.0
     assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -3
     vol.spacing[1] = 1.0
+    # an occupancy marking level is a u16 value, and 0 for f32 volumes
+    vol.occupancy_above = 65536
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -3
+    vol.occupancy_above, vol.dtype = 3, vr.F32
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -3
+    assert "occupancy_above" in lib.vr_last_error().decode()
+    vol.occupancy_above, vol.dtype = 0, vr.U16_NORM
     # the adjoint differentiates f32 grids only
     assert lib.vr_raycast_backward(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16),
                                    C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == -4
@@ -94,12 +101,17 @@ def test_raycast_validation_on_the_host(lib):
 def test_brick_validation_on_the_host(lib):
     from paper_2311_15038_amd import vr
     p = C.c_void_p(256)
-    assert lib.vr_brick_volume(None, vr.U16_NORM, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, None) == -1
-    assert lib.vr_brick_volume(p, 5, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, None) == -4
-    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_LINEAR, 8, 8, 8, p, None, None) == -3
-    assert lib.vr_brick_volume(p, vr.U16_NORM, 7, 8, 8, 8, p, None, None) == -3
-    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 0, 8, 8, p, None, None) == -2
-    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 8, 8, 8, C.c_void_p(258), None, None) == -3
+    assert lib.vr_brick_volume(None, vr.U16_NORM, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, 0, None) == -1
+    assert lib.vr_brick_volume(p, 5, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, 0, None) == -4
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_LINEAR, 8, 8, 8, p, None, 0, None) == -3
+    assert lib.vr_brick_volume(p, vr.U16_NORM, 7, 8, 8, 8, p, None, 0, None) == -3
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 0, 8, 8, p, None, 0, None) == -2
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4_PAIRS, 8, 8, 8, C.c_void_p(258), None, 0, None) == -3
+    # the marking level: u16 values only, and 0 for f32
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, -1, None) == -3
+    assert lib.vr_brick_volume(p, vr.U16_NORM, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, 65536, None) == -3
+    assert lib.vr_brick_volume(p, vr.F32, vr.LAYOUT_BRICK4, 8, 8, 8, p, None, 1, None) == -3
+    assert "mark_above" in lib.vr_last_error().decode()
     assert lib.vr_hollow(None, 8, 8, 8, 1, p, None, None) == -1
     assert lib.vr_hollow(p, 8, 0, 8, 1, C.c_void_p(1 << 20), None, None) == -2
     assert lib.vr_hollow(p, 8, 8, 8, 0, C.c_void_p(1 << 20), None, None) == -3
@@ -160,3 +172,28 @@ def test_container_validation_on_the_host(lib):
     ptrs = (C.c_void_p * 1)(16)
     assert lib.vr_threshold_downsample_in_disc(p, 8, 8, 8, None, None, 1, ptrs, None, None, None) == -1
     assert lib.vr_threshold_downsample_in_disc(p, 8193, 8, 8, None, p, 1, ptrs, None, None, None) == -2
+
+
+def test_tf_mark_level():
+    """The marking level of a TF whose first z knots have zero extinction and finite
+    colour: 257 (z - 1) - 1, so that a sample of taps at most that level has a TF
+    coordinate below z - 1 (exact arithmetic) and blends knots below z only, and the
+    ray caster's reach, floor(V 255 / 65535 (1 + 2^-16)) + 2 knots, stays within z."""
+    import math
+    import numpy as np
+    from paper_2311_15038_amd import vr
+    for z in range(0, 257):
+        tf = np.ones((256, 4), dtype=np.float32)
+        tf[:z, 3] = 0.0
+        V = vr.tf_mark_level(tf)
+        if z < 2:
+            assert V == 0
+            continue
+        assert V == 257 * (z - 1) - 1 and 0 < V <= 65535
+        assert V * 255 < (z - 1) * 65535
+        assert min(254, math.floor(V * 255 / 65535 * (1 + 2.0 ** -16))) + 2 <= z
+    tf = np.zeros((256, 4), dtype=np.float32)
+    tf[5, 0] = np.inf                                 # a colour that is not finite ends the run
+    assert vr.tf_mark_level(tf) == 257 * 4 - 1
+    tf[0, 3] = 0.5
+    assert vr.tf_mark_level(tf) == 0

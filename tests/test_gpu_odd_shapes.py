@@ -65,3 +65,23 @@ def test_second_run_is_bit_identical(odd):
         assert torch.equal(getattr(pipe, k), v), k
     for a, b in zip(levels, pipe.levels):
         assert torch.equal(a, b)
+
+
+def test_tf_marked_bricks_change_nothing(odd):
+    """The step marks bricks above the level its TF leaves at zero extinction; the
+    same step with bricks marked by every non-zero voxel gives the same frames,
+    grey-value counts and taken samples bit for bit, and evaluates no fewer."""
+    pipe, vol, _ = odd
+    assert pipe.mark_above > 0
+    cfg = P.PreviewConfig(n_levels=8, atlas_level=2, render_level=1, n_views=2, width=72, height=40,
+                          mark_by_tf=False)
+    plain = P.PreviewPipeline(vol.shape, cfg, device=dev())
+    assert plain.mark_above == 0
+    pipe.samples.zero_()
+    plain.samples.zero_()
+    pipe.step(vol, count=True)
+    plain.step(vol, count=True)
+    torch.cuda.synchronize()
+    assert torch.equal(pipe.frames, plain.frames) and torch.equal(pipe.view_hist, plain.view_hist)
+    assert pipe.samples[0].item() == plain.samples[0].item()
+    assert pipe.samples[1].item() <= plain.samples[1].item()

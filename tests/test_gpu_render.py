@@ -390,6 +390,91 @@ def test_skip_disabled_when_density_zero_is_not_empty(level1):
     assert np.abs(br.cpu().numpy() - ref).max() <= TOL
 
 
+def _zero_knots(tf):
+    """Leading TF knots with zero extinction and finite colour."""
+    ok = (tf[:, 3] == 0) & np.isfinite(tf[:, :3]).all(axis=1)
+    return 256 if ok.all() else int(np.argmin(ok))
+
+
+@pytest.mark.parametrize("shape", [(29, 23, 37), (64, 64, 64), (90, 70, 110)])
+def test_tf_marked_occupancy_bit_identical(level1, shape):
+    """Bricks marked only by voxels above the level the TF leaves at zero extinction:
+    the occupancy is that of the volume with those voxels zeroed, and the frames and
+    taken counts equal the linear march's bit for bit (4^3, 8^3 and pair bricks)."""
+    banner(f"TF-marked occupancy {shape}")
+    a = level1 if shape == (64, 64, 64) else _sparse_volume(shape, 11)
+    nz, ny, nx = a.shape
+    tf_h = synth.default_tf(sigma_scale=3.0)
+    z = _zero_knots(tf_h)
+    V = vr.tf_mark_level(tf_h)
+    assert z >= 2 and V == 257 * (z - 1) - 1
+    # every sample of taps <= V looks up knots below z - 1 (exact arithmetic)
+    assert V * 255 / 65535 < z - 1
+    tf = _tf_dev(tf_h)
+    cams = np.concatenate([synth.turntable_cameras(nx, ny, nz, n_views=7),
+                           synth.front_ortho_camera(nx, ny, nz)])
+    v = to_dev_u16(a)
+    c0 = torch.zeros(2, dtype=torch.int64, device=dev())
+    lin = vr.vr_raycast(v, tf, cams, 45, 38, 0.5, samples=c0)
+    below = np.where(a > V, a, 0).astype(np.uint16)
+    fewer = []
+    for kw in ({}, {"edge": 8}, {"pairs": True}):
+        layout = vr.LAYOUT_BRICK8 if "edge" in kw else vr.LAYOUT_BRICK4_PAIRS if kw else vr.LAYOUT_BRICK4
+        b0 = vr.vr_brick_volume(v, **kw)
+        bm = vr.vr_brick_volume(v, mark_above=V, **kw)
+        assert bm.mark_above == V and torch.equal(b0.data, bm.data)
+        ref = vr.vr_brick_volume(to_dev_u16(below), **kw)
+        assert torch.equal(_occ_parts_t(bm.occupancy, a.shape, layout), _occ_parts_t(ref.occupancy, a.shape, layout))
+        c1 = torch.zeros(2, dtype=torch.int64, device=dev())
+        c2 = torch.zeros(2, dtype=torch.int64, device=dev())
+        f0 = vr.vr_raycast(b0, tf, cams, 45, 38, 0.5, samples=c1)
+        fm = vr.vr_raycast(bm, tf, cams, 45, 38, 0.5, samples=c2)
+        assert torch.equal(lin, f0) and torch.equal(lin, fm)
+        if not kw:
+            assert torch.equal(lin, vr.vr_raycast(bm, tf, cams, 45, 38, 0.5, staged=True))
+        assert c2[0].item() == c1[0].item() == c0[0].item()
+        assert c2[1].item() <= c1[1].item()
+        fewer.append(c2[1].item() < c1[1].item())
+    if shape != (64, 64, 64):
+        assert all(fewer)                 # the blobs' faint tails no longer hold bricks open
+    if shape == (29, 23, 37):
+        _ref_occ = _brick_ref(below)[1]
+        bm = vr.vr_brick_volume(v, mark_above=V)
+        assert (_occ_parts(bm.occupancy, a.shape) == _ref_occ).all()
+
+
+def _occ_parts_t(occ_t, shape, layout):
+    nz, ny, nx = shape
+    nb, _, nocc = vr.vr_brick_count_layout(layout, nx, ny, nz)
+    return occ_t[:nocc - nb]
+
+
+def test_tf_marked_occupancy_checked_against_the_tf():
+    """Bricks marked for one TF, rendered with a TF that gives extinction to a knot
+    their unmarked samples can reach: the ray caster marches every sample (frames
+    equal to the linear march's, nothing passed over); a TF whose extinction starts
+    just past that reach still passes them over."""
+    banner("TF-marked occupancy under another TF")
+    shape = (40, 36, 44)
+    a = _sparse_volume(shape, 3)
+    nz, ny, nx = shape
+    tf_h = synth.default_tf(sigma_scale=3.0)
+    z = _zero_knots(tf_h)
+    V = vr.tf_mark_level(tf_h)
+    cams = synth.turntable_cameras(nx, ny, nz, n_views=3)
+    v = to_dev_u16(a)
+    bm = vr.vr_brick_volume(v, mark_above=V)
+    for knot, skips in ((z - 1, False), (z - 2, False), (0, False), (z, True)):
+        bad = tf_h.copy()
+        bad[knot, 3] = 0.05
+        tf = _tf_dev(bad)
+        c = torch.zeros(2, dtype=torch.int64, device=dev())
+        lin = vr.vr_raycast(v, tf, cams, 40, 40, 0.5)
+        got = vr.vr_raycast(bm, tf, cams, 40, 40, 0.5, samples=c)
+        assert torch.equal(lin, got), knot
+        assert (c[1].item() < c[0].item()) == skips, (knot, c)
+
+
 @pytest.mark.parametrize("shape", [(64, 64, 64), (37, 60, 83), (70, 33, 81)])
 def test_staged_march_bit_identical(level1, shape):
     """The depth-window march with LDS staging gives the gather march's frames, sample
