@@ -128,13 +128,14 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                 gr[a] = d[a] * S.inv_sp[a];
                 ig[a] = gr[a] != 0.0f ? 1.0f / gr[a] : 0.0f;
             }
-            const SkipRay SR = skip_ray(S, u0, gr, ig);
+            const SkipRay SR = skip_ray(S, u0, gr, ig, 2);
             uint32_t cur_b = 0xFFFFFFFFu;
             uint32_t cur_r = 0u;     // distance byte of brick cur_b (0: occupied)
+            const float half_last = 0.5f * last;
             for (int k = 0; k < n;) {
-                const float len = (k < n - 1) ? S.step : last;
-                const float off = fmaf(0.5f, len, (float)k * S.step);
-                const Cell c = cell_at(S, u0, gr, off);
+                const bool inner = k < n - 1;
+                const float len = inner ? S.step : last;
+                const Cell c = cell_at(S, u0, gr, sample_mid(S, k, inner, half_last));
                 if (skipping) {
                     const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
                     if (b != cur_b) {
@@ -148,7 +149,7 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                         // len * q to the first knot's extinction, added for the whole run
                         // (the run leaves the cube of empty bricks the distance grid gives)
                         const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                        const int next = skip_cube_ray(S, SR, gr, ig, bb, cur_r, 2, k, n);
+                        const int next = skip_cube_ray(S, SR, gr, bb, cur_r, k, n);
                         const float lsum = next < n ? (float)(next - k) * S.step
                                                     : fmaf((float)(n - 1 - k), S.step, last);
                         const float q = g.x * (Tr * tf_s[0].x - (I.x - Pr)) + g.y * (Tr * tf_s[0].y - (I.y - Pg)) +
@@ -166,13 +167,13 @@ raycast_bwd(const Views V, const Scene S, const float4* __restrict__ tf,
                 }
                 Sample sm;
                 sample<float, LAYOUT>(S, vol, c, sm);
-                const TfHit h = tf_lookup(tf_s, sm.s);
-                const float e = __expf(-(h.q.w * len));
-                const float ta = Tr * (1.0f - e);
+                const TfHit h = tf_lookup(tf_s, sm.s * tf_scale<float>());
+                const float e = transmit(h.q.w, len * kNegLog2E);
+                const float te = Tr * e;
+                const float ta = Tr - te;     // Tr (1 - e), as the forward takes it
                 Pr = fmaf(ta, h.q.x, Pr);
                 Pg = fmaf(ta, h.q.y, Pg);
                 Pb = fmaf(ta, h.q.z, Pb);
-                const float te = Tr * e;
                 // dI/drgb_i = T_i alpha_i;  dI/dsigma_i = len (T_{i+1} rgb_i - (I - P_i)) (+ alpha term)
                 const float gs = len * (g.x * (te * h.q.x - (I.x - Pr)) + g.y * (te * h.q.y - (I.y - Pg)) +
                                         g.z * (te * h.q.z - (I.z - Pb)) + ga);

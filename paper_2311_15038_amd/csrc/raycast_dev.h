@@ -116,7 +116,8 @@ __device__ __forceinline__ void tile_pixel(const Scene& S, int nb, int& view, in
 }
 
 // Everything one sample needs: the eight tap offsets, the trilinear weights
-// and the interpolated (normalised) density.
+// and the interpolated voxel value (in the volume's own units: 0..65535 for
+// u16, tf_scale maps it to the TF coordinate).
 struct Sample {
     uint32_t off[8];   // (x, y, z) taps in order x fastest: 000 100 010 110 001 101 011 111
     float wx, wy, wz;
@@ -198,9 +199,13 @@ __device__ __forceinline__ void sample(const Scene& S, const T* __restrict__ vol
     for (int t = 0; t < 8; ++t) v[t] = voxel<T>(vol, sm.off[t]);
     const float c0 = lerpf(lerpf(v[0], v[1], sm.wx), lerpf(v[2], v[3], sm.wx), sm.wy);
     const float c1 = lerpf(lerpf(v[4], v[5], sm.wx), lerpf(v[6], v[7], sm.wx), sm.wy);
-    const float s = lerpf(c0, c1, sm.wz);
-    sm.s = (sizeof(T) == 2) ? s * (1.0f / 65535.0f) : s;
+    sm.s = lerpf(c0, c1, sm.wz);
 }
+
+// TF coordinate per unit of voxel value: 255 / 65535 = 1 / 257 for u16
+// (normalised to [0, 1], then 255 segments), 255 for f32.
+template <typename T>
+__device__ __forceinline__ float tf_scale() { return sizeof(T) == 2 ? 1.0f / 257.0f : 255.0f; }
 
 struct TfHit {
     int k;
@@ -208,24 +213,34 @@ struct TfHit {
     float4 q;
 };
 
-__device__ __forceinline__ TfHit tf_lookup(const float4* tf, float s)
+// TF coordinate x (255 times the normalised density), clamped to [0, 255):
+// the segment k = floor(x) and the weight w = x - k, exact for x >= 0 (one
+// truncation and one fract).  At x >= 255 the coordinate is the float below
+// 255, so k = 254 and w = 1 - 2^-16 (the knot-255 value to a relative 2^-16
+// of the last segment's rise).
+constexpr float kTfXMax = 254.99998474f;   // 255 - 2^-16
+
+__device__ __forceinline__ TfHit tf_hit(float xs)
 {
     TfHit h;
-    const float x = fminf(fmaxf(s, 0.0f), 1.0f) * 255.0f;
-    h.k = min((int)x, 254);
-    h.w = x - (float)h.k;
+    const float x = __builtin_amdgcn_fmed3f(xs, 0.0f, kTfXMax);
+    h.k = (int)x;
+    h.w = __builtin_amdgcn_fractf(x);
+    return h;
+}
+
+__device__ __forceinline__ TfHit tf_lookup(const float4* tf, float x)
+{
+    TfHit h = tf_hit(x);
     const float4 a = tf[h.k], b = tf[h.k + 1];
     h.q = make_float4(lerpf(a.x, b.x, h.w), lerpf(a.y, b.y, h.w), lerpf(a.z, b.z, h.w),
                       lerpf(a.w, b.w, h.w));
     return h;
 }
 
-__device__ __forceinline__ TfHit tf_lookup(const TfLds& t, float s)
+__device__ __forceinline__ TfHit tf_lookup(const TfLds& t, float x)
 {
-    TfHit h;
-    const float x = fminf(fmaxf(s, 0.0f), 1.0f) * 255.0f;
-    h.k = min((int)x, 254);
-    h.w = x - (float)h.k;
+    TfHit h = tf_hit(x);
     const float4 a = t.a[h.k], b = t.a[h.k + 1];
     h.q = make_float4(lerpf(a.x, b.x, h.w), lerpf(a.y, b.y, h.w), lerpf(a.z, b.z, h.w), lerpf(a.w, b.w, h.w));
     return h;
@@ -290,6 +305,27 @@ __device__ __forceinline__ int step_count(float L, float step)
     return max(1, (int)ceilf(L / step));
 }
 
+constexpr float kNegLog2E = -1.44269504088896341f;   // -log2(e)
+
+// Ray distance of the midpoint of sample k: k step + len / 2, len the step
+// or, for the last sample (inner false), the remainder of the segment; one
+// fma of k.
+__device__ __forceinline__ float sample_mid(const Scene& S, float kf, bool inner, float half_last)
+{
+    return fmaf(kf, S.step, inner ? 0.5f * S.step : half_last);
+}
+__device__ __forceinline__ float sample_mid(const Scene& S, int k, bool inner, float half_last)
+{
+    return sample_mid(S, (float)k, inner, half_last);
+}
+
+// The transmittance factor exp(-sigma len) of a sample, as
+// exp2(sigma (-log2(e) len)) with the second factor taken once per ray.
+__device__ __forceinline__ float transmit(float sigma, float nl2_len)
+{
+    return __builtin_amdgcn_exp2f(sigma * nl2_len);
+}
+
 // Index of the first sample that may leave an empty box of cells (cells of
 // 2^sh voxels: bricks, sh = 2, or 16^3 groups of bricks, sh = 4), cells lo..hi
 // per axis.  The base tap stays in the box while u = u0 + s g lies in
@@ -330,47 +366,61 @@ __device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const 
     return skip_span(S, u0, g, ig, cell, cell, ncell, sh, k, n);
 }
 
-// Per-ray constants of skip_cube_ray: for each axis the exit bound of the
-// cells below (or above) c1 is s = (c1 << sh) ig + kb, kb = (-+margin - u0) ig,
-// and nopen is the axis's cell count less one (0 where g = 0: never left).
+// Per-ray constants of skip_cube_ray for cells of 2^sh voxels: on each axis
+// the exit bound of the cells below (or above) face c1 is
+// s = (c1 << sh) / g + (-+margin - u0) / g, kept as s = (c1 - 1) ig2 + kb1
+// with ig2 = 2^sh / g and kb1 = ig2 + (-+margin - u0) / g; nopen is the
+// axis's cell count less one (0 where g = 0: never left).
 struct SkipRay {
-    float kb[3];
+    float kb1[3];
+    float ig2[3];
     uint32_t nopen[3];
 };
 
-__device__ __forceinline__ SkipRay skip_ray(const Scene& S, const float u0[3], const float g[3], const float ig[3])
+__device__ __forceinline__ SkipRay skip_ray(const Scene& S, const float u0[3], const float g[3], const float ig[3],
+                                            int sh)
 {
     SkipRay R;
     const int nb[3] = {S.nbx, S.nby, S.nbz};
+    const float cell = (float)(1 << sh);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        R.kb[a] = ((g[a] > 0.0f ? -kSkipMarginVox : kSkipMarginVox) - u0[a]) * ig[a];
+        R.ig2[a] = ig[a] * cell;
+        R.kb1[a] = fmaf((g[a] > 0.0f ? -kSkipMarginVox : kSkipMarginVox) - u0[a], ig[a], R.ig2[a]);
         R.nopen[a] = g[a] != 0.0f ? (uint32_t)(nb[a] - 1) : 0u;
     }
     return R;
 }
 
-// The first sample that may leave the empty cube of bricks (of 2^sh voxels)
-// around brick bb whose distance byte is r >= 1 (bricks within r - 1 of bb on
-// every axis, clipped to the grid), as skip_span computes it for a box, with
-// the per-ray constants: the cube's exit face on an axis the ray climbs is
-// c1 = bb + r, on one it descends c1 = bb + 1 - r; the face is open (not the
-// grid's edge) when 1 <= c1 <= n - 1, and its bound is one fma.
-__device__ __forceinline__ int skip_cube_ray(const Scene& S, const SkipRay& R, const float g[3], const float ig[3],
-                                             const uint32_t bb[3], uint32_t r, int sh, int k, int n)
+// The first sample that may leave the empty cube of cells around cell bb whose
+// distance byte is r >= 1 (cells within r - 1 of bb on every axis, clipped to
+// the grid), as skip_span computes it for a box, with the per-ray constants:
+// the cube's exit face on an axis the ray climbs is c1 = bb + r, on one it
+// descends c1 = bb + 1 - r; the face is open (not the grid's edge) when
+// 1 <= c1 <= n - 1, one unsigned compare of c1 - 1, and its bound is one fma
+// of c1 - 1.  Faces that are not open count as infinitely far; the nearest
+// open one, less the sample-centre offset, gives the sample index, clamped
+// to k + 1 .. n (indices as floats, exact below 2^24).
+__device__ __forceinline__ float skip_cube_f(const Scene& S, const SkipRay& R, const float g[3],
+                                             const uint32_t bb[3], uint32_t r, float kf, float nf)
 {
-    float s_exit = INFINITY;
+    const int up = (int)r - 1, dn = -(int)r;      // c1 - 1 - bb climbing / descending
+    float sa[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int c1 = g[a] > 0.0f ? (int)(bb[a] + r) : (int)bb[a] + 1 - (int)r;
-        const bool open = (uint32_t)(c1 - 1) < R.nopen[a];
-        const float sa = fmaf((float)(c1 << sh), ig[a], R.kb[a]);
-        s_exit = open ? fminf(s_exit, sa) : s_exit;
+        const int c1m1 = (int)bb[a] + (g[a] > 0.0f ? up : dn);
+        const bool open = (uint32_t)c1m1 < R.nopen[a];
+        sa[a] = open ? fmaf((float)c1m1, R.ig2[a], R.kb1[a]) : INFINITY;
     }
-    const float lim = (s_exit - S.skip_c) * S.inv_step;
-    int next = n;
-    if (lim < (float)n) next = (int)ceilf(lim);
-    return min(max(next, k + 1), n);
+    const float lim = (fminf(fminf(sa[0], sa[1]), sa[2]) - S.skip_c) * S.inv_step;
+    // the middle of ceil(lim), k + 1 and n (lim is +inf where no face is open)
+    return __builtin_amdgcn_fmed3f(ceilf(lim), kf + 1.0f, nf);
+}
+
+__device__ __forceinline__ int skip_cube_ray(const Scene& S, const SkipRay& R, const float g[3],
+                                             const uint32_t bb[3], uint32_t r, int k, int n)
+{
+    return (int)skip_cube_f(S, R, g, bb, r, (float)k, (float)n);
 }
 
 // Whether samples of unmarked bricks may be passed over: the volume is in a
@@ -486,8 +536,7 @@ __device__ __forceinline__ uint32_t word_at(const uint16_t* vol, uint32_t o)
 // The texture path's time follows the 32-bit words it returns per lane, and a
 // 16-bit load costs a whole word.  Where x0 is on the last layer, the word
 // before it is loaded (x0 in its high half, inside the row) and the x1 taps,
-// in the next brick, one by one; where x is clamped (x1 == x0) the x0 tap
-// serves for both.
+// in the next brick, one by one, unless x is clamped (x1 == x0).
 template <typename T, bool WIDE, int B = 2>
 __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict__ vol, const Cell& c,
                                              uint32_t o0, Corners& k)
@@ -503,20 +552,24 @@ __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict
         const uint32_t ob = last ? o0 - 2u : o0;   // start of the word of each row
         const uint32_t w0 = word_at(vol, ob), w2 = word_at(vol, ob + dy);
         const uint32_t w4 = word_at(vol, ob + dz), w6 = word_at(vol, ob + dz + dy);
-        k.v[0] = (float)(last ? (w0 >> 16) : (w0 & 0xFFFFu));
-        k.v[2] = (float)(last ? (w2 >> 16) : (w2 & 0xFFFFu));
-        k.v[4] = (float)(last ? (w4 >> 16) : (w4 & 0xFFFFu));
-        k.v[6] = (float)(last ? (w6 >> 16) : (w6 & 0xFFFFu));
+        const uint32_t sh = last ? 16u : 0u;      // the x0 half of each word
+        k.v[0] = (float)__builtin_amdgcn_ubfe(w0, sh, 16u);
+        k.v[2] = (float)__builtin_amdgcn_ubfe(w2, sh, 16u);
+        k.v[4] = (float)__builtin_amdgcn_ubfe(w4, sh, 16u);
+        k.v[6] = (float)__builtin_amdgcn_ubfe(w6, sh, 16u);
         if (last && dx != 0u) {
             k.v[1] = tap<T, WIDE>(vol, o0 + dx);
             k.v[3] = tap<T, WIDE>(vol, o2 + dx);
             k.v[5] = tap<T, WIDE>(vol, o4 + dx);
             k.v[7] = tap<T, WIDE>(vol, o6 + dx);
         } else {
-            k.v[1] = dx == 0u ? k.v[0] : (float)(w0 >> 16);
-            k.v[3] = dx == 0u ? k.v[2] : (float)(w2 >> 16);
-            k.v[5] = dx == 0u ? k.v[4] : (float)(w4 >> 16);
-            k.v[7] = dx == 0u ? k.v[6] : (float)(w6 >> 16);
+            // where x is clamped (dx == 0: x0 = nx - 1) the high halves are the x0 taps
+            // themselves (last layer) or padding zeros; the x weight is 0 there, since
+            // the position was clamped to nx - 1, and the lerp returns the x0 tap
+            k.v[1] = (float)(w0 >> 16);
+            k.v[3] = (float)(w2 >> 16);
+            k.v[5] = (float)(w4 >> 16);
+            k.v[7] = (float)(w6 >> 16);
         }
         return;
     }
@@ -530,14 +583,12 @@ __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict
     k.v[7] = tap<T, WIDE>(vol, o6 + dx);
 }
 
-// Normalised trilinear density from the corners of cell c.
-template <typename T>
+// Trilinear voxel value (the volume's units) from the corners of cell c.
 __device__ __forceinline__ float interp_corners(const Corners& k, const Cell& c)
 {
     const float c0 = lerpf(lerpf(k.v[0], k.v[1], c.wx), lerpf(k.v[2], k.v[3], c.wx), c.wy);
     const float c1 = lerpf(lerpf(k.v[4], k.v[5], c.wx), lerpf(k.v[6], k.v[7], c.wx), c.wy);
-    const float sv = lerpf(c0, c1, c.wz);
-    return (sizeof(T) == 2) ? sv * (1.0f / 65535.0f) : sv;
+    return lerpf(c0, c1, c.wz);
 }
 
 // Front-to-back march of the ray through pixel (i, j): returns its RGBA and,
@@ -563,17 +614,20 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
         ig[a] = g[a] != 0.0f ? 1.0f / g[a] : 0.0f;
     }
     const bool skipping = skip && Lay<LAYOUT>::bricked;
-    const SkipRay SR = skip_ray(S, u0, g, ig);
+    const SkipRay SR = skip_ray(S, u0, g, ig, Lay<LAYOUT>::bs);
+    const float half_last = 0.5f * last;
+    const float nl2_step = S.step * kNegLog2E, nl2_last = last * kNegLog2E;
     float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t cur_b = 0xFFFFFFFFu;
     uint32_t cur_r = 0u;         // distance byte of brick cur_b (0: occupied)
     Corners kc;                  // corners of the last sampled cell (consecutive samples share
     kc.key_o = 0xFFFFFFFFu;      // a cell about half the time at half-voxel steps)
-    int k = 0;
-    while (k < n) {
-        const float len = (k < n - 1) ? S.step : last;
-        const float off = fmaf(0.5f, len, (float)k * S.step);
-        const Cell c = cell_at(S, u0, g, off);
+    // the sample index as a float (exact: at most 2^24 samples per ray)
+    const float nf = (float)n, nf1 = (float)(n - 1);
+    float kf = 0.0f;
+    while (kf < nf) {
+        const bool inner = kf < nf1;
+        const Cell c = cell_at(S, u0, g, sample_mid(S, kf, inner, half_last));
         float sv;
         if constexpr (Lay<LAYOUT>::bricked) {
             constexpr int B = Lay<LAYOUT>::bs;
@@ -588,27 +642,28 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
                     cur_r = DIST ? (uint32_t)S.dist[b] : (S.occ[b] != 0 ? 0u : 1u);
                 }
                 if (cur_r != 0u) {
-                    int next;
+                    float next;
                     if constexpr (DIST) {
                         // empty brick: leave the cube of empty bricks around it
                         const uint32_t bb[3] = {c.x0 >> B, c.y0 >> B, c.z0 >> B};
-                        next = skip_cube_ray(S, SR, g, ig, bb, cur_r, B, k, n);
+                        next = skip_cube_f(S, SR, g, bb, cur_r, kf, nf);
                     } else {
+                        const int k = (int)kf;
                         // empty brick: leave its group of 4^3 bricks if that is empty too, else the brick
                         const uint32_t m[3] = {c.x0 >> (B + 2), c.y0 >> (B + 2), c.z0 >> (B + 2)};
                         const uint32_t mi = mul_idx<WIDE>(mul_idx<WIDE>(m[2], (uint32_t)S.nmy) + m[1],
                                                           (uint32_t)S.nmx) + m[0];
                         if (S.occ[S.macro_off + mi] == 0) {
                             const int nm[3] = {S.nmx, S.nmy, S.nmz};
-                            next = skip_to(S, u0, g, ig, m, nm, B + 2, k, n);
+                            next = (float)skip_to(S, u0, g, ig, m, nm, B + 2, k, n);
                         } else {
                             const uint32_t bb[3] = {c.x0 >> B, c.y0 >> B, c.z0 >> B};
                             const int nb[3] = {S.nbx, S.nby, S.nbz};
-                            next = skip_to(S, u0, g, ig, bb, nb, B, k, n);
+                            next = (float)skip_to(S, u0, g, ig, bb, nb, B, k, n);
                         }
                     }
-                    if (COUNT) cnt += (uint32_t)(next - k);
-                    k = next;
+                    if (COUNT) cnt += (uint32_t)(next - kf);
+                    kf = next;
                     continue;
                 }
             }
@@ -620,24 +675,25 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
                 else load_corners<T, WIDE, B>(S, vol, c, o0, kc);
                 kc.key_o = o0;
             }
-            sv = interp_corners<T>(kc, c);
+            sv = interp_corners(kc, c);
         } else {
             Sample sm;
             sample<T, LAYOUT>(S, vol, c, sm);
             sv = sm.s;
         }
-        const TfHit h = tf_lookup(tf, sv);
-        const float e = __expf(-(h.q.w * len));
-        const float ta = Tr * (1.0f - e);
+        const TfHit h = tf_lookup(tf, sv * tf_scale<T>());
+        const float e = transmit(h.q.w, inner ? nl2_step : nl2_last);
+        const float te = Tr * e;   // transmittance after the sample
+        const float ta = Tr - te;  // its opacity-weighted share, Tr (1 - e)
         cr = fmaf(ta, h.q.x, cr);
         cg = fmaf(ta, h.q.y, cg);
         cb = fmaf(ta, h.q.z, cb);
-        Tr = Tr * e;
+        Tr = te;
         if (COUNT) {
             ++cnt;
             ++evals;
         }
-        ++k;
+        kf += 1.0f;
         if (Tr < S.eps) break;
     }
     return make_float4(fmaf(Tr, S.bg[0], cr), fmaf(Tr, S.bg[1], cg), fmaf(Tr, S.bg[2], cb),

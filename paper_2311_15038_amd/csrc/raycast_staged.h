@@ -52,13 +52,14 @@ __device__ __forceinline__ float wave_max_f(float v)
 
 __device__ __forceinline__ uint32_t cell_axis(const Cell& c, int a) { return a == 0 ? c.x0 : a == 1 ? c.y0 : c.z0; }
 
-// The ray's cell at sample k (the march's own arithmetic).
+// The ray's cell at sample k and its exp2 factor -log2(e) len (the march's own
+// arithmetic).
 __device__ __forceinline__ Cell cell_of(const Scene& S, const float u0[3], const float g[3], int k, int n, float last,
-                                        float& len)
+                                        float& nl2_len)
 {
-    len = (k < n - 1) ? S.step : last;
-    const float off = fmaf(0.5f, len, (float)k * S.step);
-    return cell_at(S, u0, g, off);
+    const bool inner = k < n - 1;
+    nl2_len = inner ? S.step * kNegLog2E : last * kNegLog2E;
+    return cell_at(S, u0, g, sample_mid(S, k, inner, 0.5f * last));
 }
 
 template <bool COUNT>
@@ -77,7 +78,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
         g[a] = d[a] * S.inv_sp[a];
         ig[a] = g[a] != 0.0f ? 1.0f / g[a] : 0.0f;
     }
-    const SkipRay SR = skip_ray(S, u0, g, ig);
+    const SkipRay SR = skip_ray(S, u0, g, ig, 2);
     // the wave's march axis: the largest |g| of its first ray that hits, the same sign and
     // |g_M| >= 0.25 on every ray that hits, else every lane marches through the caches
     const uint64_t hm = __ballot(hit);
@@ -108,8 +109,8 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
         // advance over empty bricks to the next sample that must be evaluated
         int cm = 0;
         while (k < n) {
-            float len;
-            const Cell c = cell_of(S, u0, g, k, n, last, len);
+            float nl2_len;
+            const Cell c = cell_of(S, u0, g, k, n, last, nl2_len);
             const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
             if (skip) {
                 if (b != cur_b) {
@@ -118,7 +119,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
                 }
                 if (cur_r != 0u) {
                     const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                    const int next = skip_cube_ray(S, SR, g, ig, bb, cur_r, 2, k, n);
+                    const int next = skip_cube_ray(S, SR, g, bb, cur_r, k, n);
                     if (COUNT) cnt += (uint32_t)(next - k);
                     k = next;
                     continue;
@@ -202,8 +203,8 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
         // the samples of this window
         const int wcut_lo = wlo, wcut_hi = sgn > 0 ? min(wfirst + D - 1, nM - 1) : wfirst;
         while (k < n) {
-            float len;
-            const Cell c = cell_of(S, u0, g, k, n, last, len);
+            float nl2_len;
+            const Cell c = cell_of(S, u0, g, k, n, last, nl2_len);
             const int cmv = (int)cell_axis(c, M);
             if (cmv < wcut_lo || cmv > wcut_hi) break;
             const uint32_t b = ((c.z0 >> 2) * (uint32_t)S.nby + (c.y0 >> 2)) * (uint32_t)S.nbx + (c.x0 >> 2);
@@ -214,7 +215,7 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
                 }
                 if (cur_r != 0u) {
                     const uint32_t bb[3] = {c.x0 >> 2, c.y0 >> 2, c.z0 >> 2};
-                    const int next = skip_cube_ray(S, SR, g, ig, bb, cur_r, 2, k, n);
+                    const int next = skip_cube_ray(S, SR, g, bb, cur_r, k, n);
                     if (COUNT) cnt += (uint32_t)(next - k);
                     k = next;
                     continue;
@@ -239,14 +240,15 @@ __device__ float4 march_staged(const Scene& S, const View& v, const uint16_t* __
             } else {
                 load_corners<uint16_t, false>(S, vol, c, base_offset<false, uint16_t>(c, b), kc);
             }
-            const float sv = interp_corners<uint16_t>(kc, c);
-            const TfHit h = tf_lookup(tf, sv);
-            const float e = __expf(-(h.q.w * len));
-            const float ta = Tr * (1.0f - e);
+            const float sv = interp_corners(kc, c);
+            const TfHit h = tf_lookup(tf, sv * tf_scale<uint16_t>());
+            const float e = transmit(h.q.w, nl2_len);
+            const float te = Tr * e;   // transmittance after the sample
+            const float ta = Tr - te;  // its opacity-weighted share, Tr (1 - e)
             cr = fmaf(ta, h.q.x, cr);
             cg = fmaf(ta, h.q.y, cg);
             cb = fmaf(ta, h.q.z, cb);
-            Tr = Tr * e;
+            Tr = te;
             if (COUNT) {
                 ++cnt;
                 ++evals;
