@@ -56,8 +56,8 @@ ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539636 / 19674760,
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
 # 524316.4 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 2840041.4375, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.5625,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "a20cc085bf2e31f8", "mark_above": 3854}
+RAYCAST_TRAFFIC = {"fetch_kib": 2856693.0625, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.6875,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "aa959aef6729139d", "mark_above": 3854}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
 RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "raycast_staged.h", "brick_dev.h", "brick.hip", "common.h",
@@ -821,7 +821,7 @@ def main():
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
-                                 "TD_busy": 0.86, "TA_busy": 0.63, "VALU_busy": 0.81,
+                                 "TD_busy": 0.85, "TA_busy": 0.62, "VALU_busy": 0.77,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "render_tuning": res["render_tuning"],
         "brick_mark_above": res["mark_above"],
