@@ -284,7 +284,10 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  * Render layout (not in the paper; a memory layout for the ray caster): the
  * volume as 4 x 4 x 4-voxel bricks, brick (bx, by, bz) at element
  * ((bz*nby + by)*nbx + bx)*64 with nbx = ceil(nx / 4) (and so on), voxel (x, y, z) at
- * ((z&3)*16 + (y&3)*4 + (x&3)) inside it (voxels past the volume's end are 0).
+ * ((z&3)*16 + (y&3)*4 + (x&3)) inside it (voxels past the volume's end are 0),
+ * then an apron of nbx*nby + nbx + 1 bricks of zeros: the ray caster reads the
+ * far taps of cells on the volume's last voxel layer there (and in the padding
+ * voxels) without a bounds check, with weight 0.
  * Optional occupancy: one byte per brick, non-zero iff a marking voxel (one
  * above mark_above: with mark_above 0, any non-zero voxel) is one of the 8
  * taps of a trilinear fetch whose base (floor, clamped) tap lies in that
@@ -311,13 +314,15 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  * of a trilinear fetch come in one load, at twice the memory.
  * Layout VR_LAYOUT_BRICK8 is the same with 8 x 8 x 8-voxel bricks: brick
  * (bx, by, bz) at element ((bz*nby + by)*nbx + bx)*512 with nbx = ceil(nx / 8),
- * voxel (x, y, z) at ((z&7)*64 + (y&7)*8 + (x&7)) inside it; its occupancy is
- * the same four grids over these bricks (groups of 4 x 4 x 4 of them, 32^3
- * voxels), sized by vr_brick_count_layout.
+ * voxel (x, y, z) at ((z&7)*64 + (y&7)*8 + (x&7)) inside it, then the same
+ * apron in these bricks; its occupancy is the same four grids over these
+ * bricks (groups of 4 x 4 x 4 of them, 32^3 voxels), sized by
+ * vr_brick_count_layout.
  *   d_src: [nz][ny][nx] of u16 (dtype VR_U16_NORM) or f32 (VR_F32).
  *   layout: VR_LAYOUT_BRICK4, VR_LAYOUT_BRICK4_PAIRS or VR_LAYOUT_BRICK8.
- *   d_bricked: the elements of vr_brick_count_layout (for 4^3 bricks
- *     vr_brick_count(...) * 64, x2 voxels for pairs), 16-byte aligned,
+ *   d_bricked: the elements of vr_brick_count_layout (bricks and apron;
+ *     for 4^3 bricks (n_bricks + nbx*nby + nbx + 1) * 64, x2 voxels for
+ *     pairs), 16-byte aligned,
  *     overwritten.
  *   d_occupancy: NULL or the occupancy_bytes of vr_brick_count_layout,
  *     overwritten.
@@ -348,8 +353,9 @@ int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_
 
 /* vr_brick_count for any brick layout: bricks of the layout's edge (4 for
  * VR_LAYOUT_BRICK4 and VR_LAYOUT_BRICK4_PAIRS, 8 for VR_LAYOUT_BRICK8),
- * elements of the bricked volume (nullable; bricks x edge^3, doubled for the
- * pair layout), and the occupancy's bytes (nullable).
+ * elements of the bricked volume (nullable; (bricks + nbx*nby + nbx + 1) x
+ * edge^3 with the apron, doubled for the pair layout), and the occupancy's
+ * bytes (nullable).
  * Errors: VR_ERR_NULL, VR_ERR_DIMS, VR_ERR_RANGE (layout). */
 int vr_brick_count_layout(int layout, int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_t* elements,
                           int64_t* occupancy_bytes);

@@ -393,7 +393,9 @@ int layout_plan(const vr_batch_item* items, int n_items, const vr_batch_config* 
         it.nslab_x = (it.nbx + 15) / 16;
         const int64_t nbricks = (int64_t)it.nbx * it.nby * it.nbz;
         it.occ_bytes = nbricks + (int64_t)it.nmx * it.nmy * nmz;
-        it.bricked = static_cast<uint16_t*>(C.take((size_t)nbricks * be * be * be * 2));
+        // the bricks and their apron (not cleared: the ray caster gives apron taps weight 0)
+        it.bricked = static_cast<uint16_t*>(
+            C.take((size_t)(nbricks + vr::bk::apron_bricks(it.nbx, it.nby)) * be * be * be * 2));
         it.occ = static_cast<uint8_t*>(C.take((size_t)it.occ_bytes));
         it.frames = in.d_frames;
         it.n_views = in.n_views;

@@ -13,6 +13,13 @@ __global__ void __launch_bounds__(kThreads) fill_u8(uint8_t* __restrict__ p, int
         p[i] = 0;
 }
 
+// Zeros in 16-byte pieces (the apron: whole bricks, 16-byte aligned).
+__global__ void __launch_bounds__(kThreads) fill_16(uint4* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 template <typename T, bool PAIRS, bool VEC>
 __global__ void __launch_bounds__(kThreads)
 brick_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
@@ -124,7 +131,8 @@ extern "C" int vr_brick_count_layout(int layout, int64_t nx, int64_t ny, int64_t
     const int e = layout == VR_LAYOUT_BRICK8 ? 8 : 4;
     const int64_t bx = (nx + e - 1) / e, by = (ny + e - 1) / e, bz = (nz + e - 1) / e;
     *n_bricks = bx * by * bz;
-    if (elements) *elements = bx * by * bz * e * e * e * (layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
+    if (elements)
+        *elements = (bx * by * bz + apron_bricks(bx, by)) * e * e * e * (layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
     if (occupancy_bytes) *occupancy_bytes = 3 * bx * by * bz + ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 3) / 4);
     return VR_OK;
 }
@@ -185,7 +193,17 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
         else launch_brick<float, false>(grid, s, d_src, inx, iny, inz, nbx, nby, d_bricked, d_occupancy, macro, nmx, nmy, above);
     }
     int rc = vr::check_launch("vr_brick_volume");
-    if (rc || !d_occupancy) return rc;
+    if (rc) return rc;
+    {   // the apron after the last brick: zeros
+        const int64_t ebytes = (dtype == VR_U16_NORM ? 2 : 4) * (pairs ? 2 : 1);
+        const int64_t abytes = apron_bricks(nbx, nby) * (be * be * be) * ebytes;
+        const int64_t g = std::min<int64_t>(cap, vr::ceil_div<int64_t>(abytes / 16, kThreads));
+        fill_16<<<(unsigned)std::max<int64_t>(g, 1), kThreads, 0, s>>>(
+            reinterpret_cast<uint4*>(static_cast<uint8_t*>(d_bricked) + bricks * (be * be * be) * ebytes),
+            abytes / 16);
+        rc = vr::check_launch("vr_brick_volume: apron");
+        if (rc || !d_occupancy) return rc;
+    }
     // the distance grid: x from the marks, y into the working bytes, z back
     uint8_t* dist = d_occupancy + bricks + groups;
     uint8_t* work = dist + bricks;

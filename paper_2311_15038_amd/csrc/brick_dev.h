@@ -31,6 +31,13 @@ namespace bk {
 constexpr int kThreads = 256;      // threads of one slab group
 constexpr int kDistCap = VR_BRICK_DIST_CAP;   // cap of the brick distance grid (bricks)
 
+// Bricks of the apron that follows the last brick of a bricked volume: one
+// brick layer, one brick row and one brick.  A trilinear cell on the volume's
+// last voxel layer (x, y or z) may then read its far taps one brick, brick row
+// or brick layer on without a bounds check: those taps have weight 0, since
+// the sample position was clamped to the last voxel centre there.
+inline int64_t apron_bricks(int64_t nbx, int64_t nby) { return nbx * nby + nbx + 1; }
+
 // Whether a voxel marks its bricks: a u16 voxel above `above` (0: any non-zero
 // voxel), an f32 voxel that is non-zero (`above` is 0 for f32).
 __device__ __forceinline__ bool marks(uint16_t v, uint32_t above) { return (uint32_t)v > above; }

@@ -536,18 +536,20 @@ __device__ __forceinline__ uint32_t word_at(const uint16_t* vol, uint32_t o)
 // The texture path's time follows the 32-bit words it returns per lane, and a
 // 16-bit load costs a whole word.  Where x0 is on the last layer, the word
 // before it is loaded (x0 in its high half, inside the row) and the x1 taps,
-// in the next brick, one by one, unless x is clamped (x1 == x0).
+// in the next brick, one by one.  This path takes no clamps: on the volume's
+// last voxel layer (x0 = nx - 1, and likewise y, z) the far taps are read from
+// the brick's padding, the next brick, brick row or layer, or the apron after
+// the last brick, and have weight 0, since the position was clamped to that
+// layer's voxel centre.  The other paths clamp the far taps (x1 == x0).
 template <typename T, bool WIDE, int B = 2>
 __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict__ vol, const Cell& c,
                                              uint32_t o0, Corners& k)
 {
     constexpr uint32_t E = WIDE ? 1u : (uint32_t)sizeof(T);
     constexpr uint32_t e = 1u << B, M = e - 1u;
-    const uint32_t dx = (c.x1 == c.x0) ? 0u : ((c.x0 & M) == M ? (e * e * e - M) * E : E);
-    const uint32_t dy = (c.y1 == c.y0) ? 0u : ((c.y0 & M) == M ? (S.row_e - M * e) * E : e * E);
-    const uint32_t dz = (c.z1 == c.z0) ? 0u : ((c.z0 & M) == M ? (S.slab_e - M * e * e) * E : e * e * E);
-    const uint32_t o2 = o0 + dy, o4 = o0 + dz, o6 = o4 + dy;
     if constexpr (sizeof(T) == 2 && !WIDE) {
+        const uint32_t dy = (c.y0 & M) == M ? (S.row_e - M * e) * E : e * E;
+        const uint32_t dz = (c.z0 & M) == M ? (S.slab_e - M * e * e) * E : e * e * E;
         const bool last = (c.x0 & M) == M;
         const uint32_t ob = last ? o0 - 2u : o0;   // start of the word of each row
         const uint32_t w0 = word_at(vol, ob), w2 = word_at(vol, ob + dy);
@@ -557,15 +559,14 @@ __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict
         k.v[2] = (float)__builtin_amdgcn_ubfe(w2, sh, 16u);
         k.v[4] = (float)__builtin_amdgcn_ubfe(w4, sh, 16u);
         k.v[6] = (float)__builtin_amdgcn_ubfe(w6, sh, 16u);
-        if (last && dx != 0u) {
+        if (last) {
+            constexpr uint32_t dx = (e * e * e - M) * E;
+            const uint32_t o2 = o0 + dy, o4 = o0 + dz;
             k.v[1] = tap<T, WIDE>(vol, o0 + dx);
             k.v[3] = tap<T, WIDE>(vol, o2 + dx);
             k.v[5] = tap<T, WIDE>(vol, o4 + dx);
-            k.v[7] = tap<T, WIDE>(vol, o6 + dx);
+            k.v[7] = tap<T, WIDE>(vol, o4 + dy + dx);
         } else {
-            // where x is clamped (dx == 0: x0 = nx - 1) the high halves are the x0 taps
-            // themselves (last layer) or padding zeros; the x weight is 0 there, since
-            // the position was clamped to nx - 1, and the lerp returns the x0 tap
             k.v[1] = (float)(w0 >> 16);
             k.v[3] = (float)(w2 >> 16);
             k.v[5] = (float)(w4 >> 16);
@@ -573,6 +574,10 @@ __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict
         }
         return;
     }
+    const uint32_t dx = (c.x1 == c.x0) ? 0u : ((c.x0 & M) == M ? (e * e * e - M) * E : E);
+    const uint32_t dy = (c.y1 == c.y0) ? 0u : ((c.y0 & M) == M ? (S.row_e - M * e) * E : e * E);
+    const uint32_t dz = (c.z1 == c.z0) ? 0u : ((c.z0 & M) == M ? (S.slab_e - M * e * e) * E : e * e * E);
+    const uint32_t o2 = o0 + dy, o4 = o0 + dz, o6 = o4 + dy;
     k.v[0] = tap<T, WIDE>(vol, o0);
     k.v[1] = tap<T, WIDE>(vol, o0 + dx);
     k.v[2] = tap<T, WIDE>(vol, o2);

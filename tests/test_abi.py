@@ -127,9 +127,10 @@ def test_brick_validation_on_the_host(lib):
     assert n.value == 3 * 2 * 1 and o.value == 6 + 1 + 6 + 6
     e = C.c_int64(0)
     assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK8, 9, 5, 17, C.byref(n), C.byref(e), C.byref(o)) == 0
-    assert n.value == 2 * 1 * 3 and e.value == 6 * 512 and o.value == 3 * 6 + 1
+    # the bricks, then the apron: one brick layer, one brick row and one brick
+    assert n.value == 2 * 1 * 3 and e.value == (6 + 2 * 1 + 2 + 1) * 512 and o.value == 3 * 6 + 1
     assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK4_PAIRS, 9, 5, 4, C.byref(n), C.byref(e), None) == 0
-    assert n.value == 6 and e.value == 6 * 128
+    assert n.value == 6 and e.value == (6 + 3 * 2 + 3 + 1) * 128
     assert lib.vr_brick_count_layout(vr.LAYOUT_LINEAR, 9, 5, 4, C.byref(n), None, None) == -3
     assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK8, 0, 5, 4, C.byref(n), None, None) == -2
 

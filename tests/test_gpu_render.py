@@ -135,14 +135,20 @@ def test_raycast_rejects_bad_args(level1):
 
 
 # ------------------------------------------------------------ brick render layout
+def _apron(nbx, nby, elems_per_brick, dtype):
+    """The zeros after the last brick: one brick layer, one brick row and one brick."""
+    return np.zeros((nbx * nby + nbx + 1) * elems_per_brick, dtype=dtype)
+
+
 def _brick_ref(a, e=4):
-    """The brick layout (bricks of e^3 voxels) and the dilated occupancy, written out
-    with NumPy."""
+    """The brick layout (bricks of e^3 voxels, then the apron of zeros) and the dilated
+    occupancy, written out with NumPy."""
     nz, ny, nx = a.shape
     nbz, nby, nbx = (nz + e - 1) // e, (ny + e - 1) // e, (nx + e - 1) // e
     pad = np.zeros((nbz * e, nby * e, nbx * e), dtype=a.dtype)
     pad[:nz, :ny, :nx] = a
     br = pad.reshape(nbz, e, nby, e, nbx, e).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
+    br = np.concatenate([br, _apron(nbx, nby, e ** 3, a.dtype)])
     occ = np.zeros((nbz, nby, nbx), dtype=np.uint8)
     for z, y, x in np.argwhere(a != 0):
         for zz in (z - 1, z):
@@ -268,7 +274,8 @@ def _pairs_ref(a):
     pad = np.zeros((nbz * 4, nby * 4, nbx * 4, 2), dtype=a.dtype)
     pad[:nz, :ny, :nx, 0] = a
     pad[:nz, :ny, :nx, 1] = hi
-    return pad.reshape(nbz, 4, nby, 4, nbx, 4, 2).transpose(0, 2, 4, 1, 3, 5, 6).reshape(-1)
+    br = pad.reshape(nbz, 4, nby, 4, nbx, 4, 2).transpose(0, 2, 4, 1, 3, 5, 6).reshape(-1)
+    return np.concatenate([br, _apron(nbx, nby, 128, a.dtype)])
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (29, 23, 37), (5, 3, 4), (7, 5, 12)])
@@ -339,6 +346,37 @@ def test_brick_and_skip_bit_identical(level1, shape):
         assert np.abs(skip.cpu().numpy() - ref).max() <= TOL
         # the count the skipping march reports (passed-over samples included) is the oracle's
         assert int(lohi[:, 0].sum()) <= c1[0].item() <= int(lohi[:, 1].sum()), (c1, n_ref.sum(), lohi.sum(0))
+
+
+@pytest.mark.parametrize("shape,edge", [((64, 64, 64), 4), ((29, 23, 37), 4), ((32, 40, 48), 8), ((21, 30, 13), 8)])
+def test_far_taps_past_the_volume_have_no_weight(shape, edge):
+    """The u16 march reads the far taps of cells on the volume's last voxel layer from
+    the bricks' padding, the next brick, brick row or layer, or the apron after the last
+    brick, with weight 0: filling all of those with 65535 leaves the frames equal to the
+    linear march's bit for bit."""
+    banner(f"far taps past the volume {shape} bricks {edge}")
+    a = _sparse_volume(shape, 13)
+    a[0, :, :] = 20000            # faces with content, so that rays sample the last layers
+    a[:, -1, :] = 30000
+    a[:, :, -1] = 25000
+    a[-1, :, :] = 15000
+    nz, ny, nx = shape
+    tf = _tf_dev(synth.default_tf(sigma_scale=0.3))
+    cams = np.concatenate([synth.turntable_cameras(nx, ny, nz, n_views=6),
+                           _grazing_cameras(nx, ny, nz)[::3]])
+    v = to_dev_u16(a)
+    lin = vr.vr_raycast(v, tf, cams, 48, 40, 0.5)
+    bv = vr.vr_brick_volume(v, edge=edge)
+    e = edge
+    nbz, nby, nbx = (nz + e - 1) // e, (ny + e - 1) // e, (nx + e - 1) // e
+    pad = np.full((nbz * e, nby * e, nbx * e), 65535, dtype=np.uint16)
+    pad[:nz, :ny, :nx] = a
+    br = pad.reshape(nbz, e, nby, e, nbx, e).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
+    br = np.concatenate([br, np.full((nbx * nby + nbx + 1) * e ** 3, 65535, dtype=np.uint16)])
+    assert br.size == bv.data.numel()
+    bv.data.copy_(to_dev_u16(br))
+    assert torch.equal(lin, vr.vr_raycast(bv, tf, cams, 48, 40, 0.5))
+    assert lin[..., 3].max().item() > 0.1
 
 
 def _grazing_cameras(nx, ny, nz):
