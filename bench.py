@@ -114,9 +114,9 @@ def run_gpu(steps, warmup):
     pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(), device=dev)
     # the brick size of the rendered level, picked by timing both on this step's level
     pipe.step(vol)
-    edge, edge_ms = P.tune_brick_edge(pipe, use_cache=False, log=log)
-    if edge != pipe.cfg.brick_edge:
-        pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(brick_edge=edge), device=dev)
+    bricks, bricks_ms = P.tune_bricks(pipe, use_cache=False, log=log)
+    if P.BRICK_CHOICES[bricks] != dict(brick_edge=pipe.cfg.brick_edge, overlap=pipe.overlap):
+        pipe = P.PreviewPipeline(vol.shape, P.PreviewConfig(**P.BRICK_CHOICES[bricks]), device=dev)
 
     # sample count of one step (same every step: deterministic)
     pipe.samples.zero_()
@@ -161,7 +161,9 @@ def run_gpu(steps, warmup):
     staged_same = bool(torch.equal(staged_out, pipe.frames))
     out = {
         "mark_above": pipe.mark_above,
-        "render_tuning": {"brick_edge": edge, "ms_bricks_plus_frames": {str(k): v for k, v in edge_ms.items()}},
+        "render_tuning": {"bricks": bricks, "choices": {k: P.BRICK_LAYOUT_NAMES[k] for k in P.BRICK_CHOICES},
+                          "ms_bricks_plus_frames": bricks_ms},
+        "raycast_kernel": f"raycast_fwd<u16,{P.BRICK_LAYOUT_NAMES[bricks]}>",
         "raycast_staged": {"ms": staged_ms, "frames_identical": staged_same},
         "samples_per_step": samples,
         "evaluated_per_step": evaluated,
@@ -177,7 +179,9 @@ def run_gpu(steps, warmup):
     vol_b = nx * ny * nz * 2
     lv_b = sum(l.numel() * 2 for l in pipe.levels)
     rv = pipe.render_vol
-    out["raycast_alg_bytes"] = (rv.data.numel() * rv.data.element_size()
+    # the rendered level once (whatever its brick layout adds: overlap, apron), its
+    # occupancy grids and the frames
+    out["raycast_alg_bytes"] = (pipe.levels[pipe.cfg.render_level - 1].numel() * 2
                                 + (rv.occupancy.numel() if rv.occupancy is not None else 0)
                                 + pipe.frames.numel() * 4)
     out["kernel_bytes"] = {"histograms": vol_b + nx * ny * 3 * 2,
@@ -816,7 +820,7 @@ def main():
                      "traffic": raycast_traffic(res["mark_above"]),
                      "traffic_unit": "B per launch (HBM read + write, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "algorithmic_bytes": res["raycast_alg_bytes"],
-                     "kernel": f"raycast_fwd<u16,brick{res['render_tuning']['brick_edge']}>",
+                     "kernel": res["raycast_kernel"],
                      "flops_per_sample": FLOPS_PER_SAMPLE,
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,

@@ -71,7 +71,8 @@ enum {
     VR_LAYOUT_LINEAR = 0,      /* [nz][ny][nx], x fastest */
     VR_LAYOUT_BRICK4 = 1,      /* 4x4x4 bricks, see vr_brick_volume */
     VR_LAYOUT_BRICK4_PAIRS = 2, /* 4x4x4 bricks of x-tap pairs, see vr_brick_volume */
-    VR_LAYOUT_BRICK8 = 3       /* 8x8x8 bricks, see vr_brick_volume */
+    VR_LAYOUT_BRICK8 = 3,      /* 8x8x8 bricks, see vr_brick_volume */
+    VR_LAYOUT_BRICK4_OVERLAP = 4 /* 4x4x4 bricks overlapping by one voxel in x, see vr_brick_volume */
 };
 
 /*
@@ -318,8 +319,18 @@ int vr_pack_slicemap(const uint16_t* d_level, int64_t nx, int64_t ny, int64_t nz
  * apron in these bricks; its occupancy is the same four grids over these
  * bricks (groups of 4 x 4 x 4 of them, 32^3 voxels), sized by
  * vr_brick_count_layout.
+ * Layout VR_LAYOUT_BRICK4_OVERLAP (u16 only) stores 4 x 4 x 4-voxel bricks
+ * that overlap by one voxel in x: brick (bx, by, bz) holds voxels
+ * x = 3 bx .. 3 bx + 3 (0 past the volume's end), y = 4 by .. 4 by + 3 and
+ * z = 4 bz .. 4 bz + 3, voxel (x, y, z) at ((z&3)*16 + (y&3)*4 + (x - 3 bx))
+ * inside it, with nbx = (nx - 1) / 3 + 1, in the brick order and with the
+ * apron of VR_LAYOUT_BRICK4.  A brick serves the trilinear cells whose base
+ * tap has x in 3 bx .. 3 bx + 2 (and y, z in the brick), so both x taps of a
+ * cell lie in one brick row and one 32-bit load brings them.  Its occupancy
+ * is the four grids over these bricks.
  *   d_src: [nz][ny][nx] of u16 (dtype VR_U16_NORM) or f32 (VR_F32).
- *   layout: VR_LAYOUT_BRICK4, VR_LAYOUT_BRICK4_PAIRS or VR_LAYOUT_BRICK8.
+ *   layout: VR_LAYOUT_BRICK4, VR_LAYOUT_BRICK4_PAIRS, VR_LAYOUT_BRICK8 or
+ *     VR_LAYOUT_BRICK4_OVERLAP (u16).
  *   d_bricked: the elements of vr_brick_count_layout (bricks and apron;
  *     for 4^3 bricks (n_bricks + nbx*nby + nbx + 1) * 64, x2 voxels for
  *     pairs), 16-byte aligned,
@@ -352,7 +363,9 @@ int vr_unbrick_volume(const void* d_bricked, int dtype, int64_t nx, int64_t ny, 
 int vr_brick_count(int64_t nx, int64_t ny, int64_t nz, int64_t* n_bricks, int64_t* occupancy_bytes);
 
 /* vr_brick_count for any brick layout: bricks of the layout's edge (4 for
- * VR_LAYOUT_BRICK4 and VR_LAYOUT_BRICK4_PAIRS, 8 for VR_LAYOUT_BRICK8),
+ * VR_LAYOUT_BRICK4 and VR_LAYOUT_BRICK4_PAIRS, 8 for VR_LAYOUT_BRICK8, 4
+ * overlapping in x, (nx - 1) / 3 + 1 of them along x, for
+ * VR_LAYOUT_BRICK4_OVERLAP),
  * elements of the bricked volume (nullable; (bricks + nbx*nby + nbx + 1) x
  * edge^3 with the apron, doubled for the pair layout), and the occupancy's
  * bytes (nullable).
@@ -364,7 +377,7 @@ int vr_brick_count_layout(int layout, int64_t nx, int64_t ny, int64_t nz, int64_
 typedef struct {
     const void* data;          /* device pointer in `layout` */
     int32_t dtype;
-    int32_t layout;            /* VR_LAYOUT_LINEAR, VR_LAYOUT_BRICK4, VR_LAYOUT_BRICK4_PAIRS or VR_LAYOUT_BRICK8 */
+    int32_t layout;            /* VR_LAYOUT_LINEAR or a brick layout (VR_LAYOUT_BRICK4_OVERLAP: u16 only) */
     int64_t nx, ny, nz;
     double spacing[3];         /* world units per voxel along x, y, z (> 0) */
     const uint8_t* occupancy;  /* NULL, or the brick occupancy (brick layouts only) */

@@ -85,6 +85,17 @@ brick8_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nb
         row8_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, r);
 }
 
+// Overlap layout: one thread per 4-voxel row piece (grid-stride).
+__global__ void __launch_bounds__(kThreads)
+brick_ovl_kernel(const uint16_t* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
+                 uint16_t* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx,
+                 int nmy, uint32_t above)
+{
+    const int64_t n = (int64_t)nbx * (nby * 4) * ((nz + 3) / 4 * 4);
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads)
+        row_ovl_body(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, r);
+}
+
 // Rows load four voxels at a time when nx is a multiple of 4 and src is
 // aligned to four voxels.
 template <typename T, bool PAIRS>
@@ -123,13 +134,16 @@ extern "C" int vr_brick_count_layout(int layout, int64_t nx, int64_t ny, int64_t
 {
     vr::clear_error();
     VR_REQUIRE(n_bricks != nullptr, VR_ERR_NULL, "vr_brick_count_layout: n_bricks is NULL");
-    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS || layout == VR_LAYOUT_BRICK8,
+    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS || layout == VR_LAYOUT_BRICK8 ||
+                   layout == VR_LAYOUT_BRICK4_OVERLAP,
                VR_ERR_RANGE, "vr_brick_count_layout: layout %d is not a brick layout", layout);
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
                VR_ERR_DIMS, "vr_brick_count_layout: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
                (long long)nz);
     const int e = layout == VR_LAYOUT_BRICK8 ? 8 : 4;
-    const int64_t bx = (nx + e - 1) / e, by = (ny + e - 1) / e, bz = (nz + e - 1) / e;
+    int64_t nb[3];
+    brick_grid(layout, nx, ny, nz, nb);
+    const int64_t bx = nb[0], by = nb[1], bz = nb[2];
     *n_bricks = bx * by * bz;
     if (elements)
         *elements = (bx * by * bz + apron_bricks(bx, by)) * e * e * e * (layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
@@ -148,13 +162,18 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
     VR_REQUIRE(mark_above >= 0 && mark_above <= 65535 && (dtype == VR_U16_NORM || mark_above == 0), VR_ERR_RANGE,
                "vr_brick_volume: mark_above %d (0..65535 for u16, 0 for f32)", (int)mark_above);
     const uint32_t above = (uint32_t)mark_above;
-    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS || layout == VR_LAYOUT_BRICK8,
+    VR_REQUIRE(layout == VR_LAYOUT_BRICK4 || layout == VR_LAYOUT_BRICK4_PAIRS || layout == VR_LAYOUT_BRICK8 ||
+                   layout == VR_LAYOUT_BRICK4_OVERLAP,
                VR_ERR_RANGE, "vr_brick_volume: layout %d is not a brick layout", layout);
+    VR_REQUIRE(layout != VR_LAYOUT_BRICK4_OVERLAP || dtype == VR_U16_NORM, VR_ERR_DTYPE,
+               "vr_brick_volume: VR_LAYOUT_BRICK4_OVERLAP holds u16 volumes only");
     VR_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && nx < (1 << 30) && ny < (1 << 30) && nz < (1 << 30),
                VR_ERR_DIMS, "vr_brick_volume: dims %lld x %lld x %lld", (long long)nx, (long long)ny,
                (long long)nz);
     const int be = layout == VR_LAYOUT_BRICK8 ? 8 : 4;
-    const int nbx = (int)((nx + be - 1) / be), nby = (int)((ny + be - 1) / be), nbz = (int)((nz + be - 1) / be);
+    int64_t nbg[3];
+    brick_grid(layout, nx, ny, nz, nbg);
+    const int nbx = (int)nbg[0], nby = (int)nbg[1], nbz = (int)nbg[2];
     const int nmx = (nbx + 3) / 4, nmy = (nby + 3) / 4, nmz = (nbz + 3) / 4;
     const int64_t bricks = (int64_t)nbx * nby * nbz;
     const int64_t groups = (int64_t)nmx * nmy * nmz;
@@ -174,7 +193,13 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
     uint8_t* macro = d_occupancy ? d_occupancy + bricks : nullptr;
     const bool pairs = layout == VR_LAYOUT_BRICK4_PAIRS;
     const int inx = (int)nx, iny = (int)ny, inz = (int)nz;
-    if (layout == VR_LAYOUT_BRICK8) {
+    if (layout == VR_LAYOUT_BRICK4_OVERLAP) {
+        const int64_t pieces = (int64_t)nbx * (nby * 4) * (nbz * 4);
+        const unsigned g4 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap * 4, vr::ceil_div<int64_t>(pieces, kThreads)));
+        brick_ovl_kernel<<<g4, kThreads, 0, s>>>(static_cast<const uint16_t*>(d_src), inx, iny, inz, nbx, nby,
+                                                 static_cast<uint16_t*>(d_bricked), d_occupancy, macro, nmx, nmy,
+                                                 above);
+    } else if (layout == VR_LAYOUT_BRICK8) {
         const int64_t pieces = (int64_t)nbx * (nby * 8) * (nbz * 8);
         const unsigned g8 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap * 4, vr::ceil_div<int64_t>(pieces, kThreads)));
         if (dtype == VR_U16_NORM)

@@ -38,6 +38,19 @@ constexpr int kDistCap = VR_BRICK_DIST_CAP;   // cap of the brick distance grid 
 // the sample position was clamped to the last voxel centre there.
 inline int64_t apron_bricks(int64_t nbx, int64_t nby) { return nbx * nby + nbx + 1; }
 
+// Bricks per axis of a brick layout (host): ceil(n / edge), except along x in
+// the overlap layout, where brick bx serves base taps 3 bx .. 3 bx + 2.
+inline void brick_grid(int layout, int64_t nx, int64_t ny, int64_t nz, int64_t nb[3])
+{
+    const int64_t e = layout == VR_LAYOUT_BRICK8 ? 8 : 4;
+    nb[0] = layout == VR_LAYOUT_BRICK4_OVERLAP ? (nx - 1) / 3 + 1 : (nx + e - 1) / e;
+    nb[1] = (ny + e - 1) / e;
+    nb[2] = (nz + e - 1) / e;
+}
+
+// Brick x of base tap x in the overlap layout: x / 3 (exact for 32-bit x).
+__device__ __forceinline__ uint32_t ovl_bx(uint32_t x) { return __umulhi(x, 0xAAAAAAABu) >> 1; }
+
 // Whether a voxel marks its bricks: a u16 voxel above `above` (0: any non-zero
 // voxel), an f32 voxel that is non-zero (`above` is 0 for f32).
 __device__ __forceinline__ bool marks(uint16_t v, uint32_t above) { return (uint32_t)v > above; }
@@ -224,6 +237,52 @@ __device__ inline void row8_body(const T* __restrict__ src, int nx, int ny, int 
                     occ[((int64_t)zs[c] * nby + ys[b]) * nbx + xs[a]] = 1;
                     macro[((int64_t)(zs[c] >> 2) * nmy + (ys[b] >> 2)) * nmx + (xs[a] >> 2)] = 1;
                 }
+}
+
+// Overlap layout: row piece r = ((z * 4 nby) + y) * nbx + bx holds voxels
+// 3 bx .. 3 bx + 3 of row (y, z) of the volume padded to whole bricks (0 past
+// its end), one brick row, stored as one 8-byte vector at element
+// ((z & 3) * 4 + (y & 3)) * 4 of brick (bx, y >> 2, z >> 2); the pieces
+// r < nbx * 4 nby * 4 nbz cover every brick.  The four voxels are the x taps of
+// every cell the brick serves in that row, so a marking voxel marks the
+// piece's own brick, and the brick below in y or z when the row is the first
+// of its brick there (its cells at y - 1 or z - 1 take it as their far tap),
+// with the group marks of each.
+__device__ inline void row_ovl_body(const uint16_t* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
+                                    uint16_t* __restrict__ dst, uint8_t* __restrict__ occ,
+                                    uint8_t* __restrict__ macro, int nmx, int nmy, uint32_t above, int64_t r)
+{
+    const int bx = (int)(r % nbx);
+    const int64_t yz = r / nbx;
+    const int py = nby * 4;
+    const int y = (int)(yz % py), z = (int)(yz / py);
+    const bool rowok = y < ny && z < nz;
+    const uint16_t* row = src + ((int64_t)(rowok ? z : 0) * ny + (rowok ? y : 0)) * nx;
+    const int x0 = bx * 3;
+    uint16_t v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (rowok && x0 + e < nx) ? row[x0 + e] : (uint16_t)0;
+    const int64_t brick = ((int64_t)(z >> 2) * nby + (y >> 2)) * nbx + bx;
+    uint2 w;
+    w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+    w.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+    *reinterpret_cast<uint2*>(dst + (brick << 6) + (((z & 3) << 4) | ((y & 3) << 2))) = w;
+    if (occ == nullptr) return;
+    bool any = false;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) any |= marks(v[e], above);
+    if (!any) return;
+    const int by = y >> 2, bz = z >> 2;
+    const int ys[2] = {by, ((y & 3) == 0 && by > 0) ? by - 1 : -1};
+    const int zs[2] = {bz, ((z & 3) == 0 && bz > 0) ? bz - 1 : -1};
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if (ys[b] >= 0 && zs[c] >= 0) {
+                occ[((int64_t)zs[c] * nby + ys[b]) * nbx + bx] = 1;
+                macro[((int64_t)(zs[c] >> 2) * nmy + (ys[b] >> 2)) * nmx + (bx >> 2)] = 1;
+            }
 }
 
 }  // namespace bk

@@ -128,13 +128,15 @@ void launch_fwd(unsigned blocks, hipStream_t s, const Views& V, const Scene& S, 
         else raycast_fwd_staged<false><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
         return;
     }
-    if (cnt) {
-        if (wide) raycast_fwd<T, LAYOUT, true, true><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
-        else raycast_fwd<T, LAYOUT, true, false><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
-    } else {
-        if (wide) raycast_fwd<T, LAYOUT, false, true><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
-        else raycast_fwd<T, LAYOUT, false, false><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+    if constexpr (!Lay<LAYOUT>::ovl) {   // the overlap layout takes 32-bit offsets only (checked by the scene)
+        if (wide) {
+            if (cnt) raycast_fwd<T, LAYOUT, true, true><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+            else raycast_fwd<T, LAYOUT, false, true><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+            return;
+        }
     }
+    if (cnt) raycast_fwd<T, LAYOUT, true, false><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
+    else raycast_fwd<T, LAYOUT, false, false><<<blocks, kThreads, 0, s>>>(V, S, tf, out, cnt);
 }
 
 }  // namespace
@@ -179,6 +181,8 @@ extern "C" int vr_raycast(const vr_volume* vol, const float* d_tf, const vr_came
             if (L == VR_LAYOUT_BRICK4_PAIRS) launch_fwd<uint16_t, VR_LAYOUT_BRICK4_PAIRS>(nb, s, V, S, tf, out, cnt, false);
             else if (L == VR_LAYOUT_BRICK4) launch_fwd<uint16_t, VR_LAYOUT_BRICK4>(nb, s, V, S, tf, out, cnt, staged);
             else if (L == VR_LAYOUT_BRICK8) launch_fwd<uint16_t, VR_LAYOUT_BRICK8>(nb, s, V, S, tf, out, cnt, false);
+            else if (L == VR_LAYOUT_BRICK4_OVERLAP)
+                launch_fwd<uint16_t, VR_LAYOUT_BRICK4_OVERLAP>(nb, s, V, S, tf, out, cnt, false);
             else launch_fwd<uint16_t, VR_LAYOUT_LINEAR>(nb, s, V, S, tf, out, cnt, false);
         } else {
             if (L == VR_LAYOUT_BRICK4_PAIRS) launch_fwd<float, VR_LAYOUT_BRICK4_PAIRS>(nb, s, V, S, tf, out, cnt, false);

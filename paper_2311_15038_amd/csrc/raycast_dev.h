@@ -22,6 +22,7 @@ constexpr int kMaxViews = VR_MAX_VIEWS_PER_LAUNCH;
 template <int LAYOUT>
 struct Lay {
     static constexpr bool bricked = LAYOUT != VR_LAYOUT_LINEAR;
+    static constexpr bool ovl = LAYOUT == VR_LAYOUT_BRICK4_OVERLAP;   // 4^3 bricks, 3 cells apart in x
     static constexpr int bs = LAYOUT == VR_LAYOUT_BRICK8 ? 3 : 2;
     static constexpr uint32_t edge = 1u << bs;
     static constexpr uint32_t mask = edge - 1u;
@@ -366,11 +367,12 @@ __device__ __forceinline__ int skip_to(const Scene& S, const float u0[3], const 
     return skip_span(S, u0, g, ig, cell, cell, ncell, sh, k, n);
 }
 
-// Per-ray constants of skip_cube_ray for cells of 2^sh voxels: on each axis
-// the exit bound of the cells below (or above) face c1 is
-// s = (c1 << sh) / g + (-+margin - u0) / g, kept as s = (c1 - 1) ig2 + kb1
-// with ig2 = 2^sh / g and kb1 = ig2 + (-+margin - u0) / g; nopen is the
-// axis's cell count less one (0 where g = 0: never left).
+// Per-ray constants of skip_cube_ray for bricks of e_a voxels along axis a
+// (2^sh, or 3 along x in the overlap layout): on each axis the exit bound of
+// the bricks below (or above) face c1 is s = c1 e_a / g + (-+margin - u0) / g,
+// kept as s = (c1 - 1) ig2 + kb1 with ig2 = e_a / g and
+// kb1 = ig2 + (-+margin - u0) / g; nopen is the axis's brick count less one
+// (0 where g = 0: never left).
 struct SkipRay {
     float kb1[3];
     float ig2[3];
@@ -378,18 +380,25 @@ struct SkipRay {
 };
 
 __device__ __forceinline__ SkipRay skip_ray(const Scene& S, const float u0[3], const float g[3], const float ig[3],
-                                            int sh)
+                                            float cx, float cy, float cz)
 {
     SkipRay R;
     const int nb[3] = {S.nbx, S.nby, S.nbz};
-    const float cell = (float)(1 << sh);
+    const float cell[3] = {cx, cy, cz};   // cells (voxels) per brick along each axis
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        R.ig2[a] = ig[a] * cell;
+        R.ig2[a] = ig[a] * cell[a];
         R.kb1[a] = fmaf((g[a] > 0.0f ? -kSkipMarginVox : kSkipMarginVox) - u0[a], ig[a], R.ig2[a]);
         R.nopen[a] = g[a] != 0.0f ? (uint32_t)(nb[a] - 1) : 0u;
     }
     return R;
+}
+
+__device__ __forceinline__ SkipRay skip_ray(const Scene& S, const float u0[3], const float g[3], const float ig[3],
+                                            int sh)
+{
+    const float c = (float)(1 << sh);
+    return skip_ray(S, u0, g, ig, c, c, c);
 }
 
 // The first sample that may leave the empty cube of cells around cell bb whose
@@ -588,6 +597,34 @@ __device__ __forceinline__ void load_corners(const Scene& S, const T* __restrict
     k.v[7] = tap<T, WIDE>(vol, o6 + dx);
 }
 
+// Overlap layout (u16, byte offsets): base tap offset of cell c in brick b,
+// xi = x0 - 3 bx its column in the brick (0..2).
+__device__ __forceinline__ uint32_t base_offset_ovl(const Cell& c, uint32_t b, uint32_t xi)
+{
+    return ((b << 6) | ((c.z0 & 3u) << 4) | ((c.y0 & 3u) << 2) | xi) * 2u;
+}
+
+// Corners of cell c in the overlap layout: both x taps of each corner row lie
+// in one brick row (the cell's column is 0..2 of the brick's 4), so each row
+// is one 32-bit load, with no special case in x.  The far taps in y and z
+// follow load_corners (no clamps: on the volume's last layer they have weight 0).
+__device__ __forceinline__ void load_corners_ovl(const Scene& S, const uint16_t* __restrict__ vol, const Cell& c,
+                                                 uint32_t o0, Corners& k)
+{
+    const uint32_t dy = (c.y0 & 3u) == 3u ? (S.row_e - 12u) * 2u : 8u;
+    const uint32_t dz = (c.z0 & 3u) == 3u ? (S.slab_e - 48u) * 2u : 32u;
+    const uint32_t w0 = word_at(vol, o0), w2 = word_at(vol, o0 + dy);
+    const uint32_t w4 = word_at(vol, o0 + dz), w6 = word_at(vol, o0 + dz + dy);
+    k.v[0] = (float)(w0 & 0xFFFFu);
+    k.v[1] = (float)(w0 >> 16);
+    k.v[2] = (float)(w2 & 0xFFFFu);
+    k.v[3] = (float)(w2 >> 16);
+    k.v[4] = (float)(w4 & 0xFFFFu);
+    k.v[5] = (float)(w4 >> 16);
+    k.v[6] = (float)(w6 & 0xFFFFu);
+    k.v[7] = (float)(w6 >> 16);
+}
+
 // Trilinear voxel value (the volume's units) from the corners of cell c.
 __device__ __forceinline__ float interp_corners(const Corners& k, const Cell& c)
 {
@@ -619,7 +656,8 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
         ig[a] = g[a] != 0.0f ? 1.0f / g[a] : 0.0f;
     }
     const bool skipping = skip && Lay<LAYOUT>::bricked;
-    const SkipRay SR = skip_ray(S, u0, g, ig, Lay<LAYOUT>::bs);
+    const SkipRay SR = Lay<LAYOUT>::ovl ? skip_ray(S, u0, g, ig, 3.0f, 4.0f, 4.0f)
+                                        : skip_ray(S, u0, g, ig, Lay<LAYOUT>::bs);
     const float half_last = 0.5f * last;
     const float nl2_step = S.step * kNegLog2E, nl2_last = last * kNegLog2E;
     float Tr = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
@@ -636,11 +674,13 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
         float sv;
         if constexpr (Lay<LAYOUT>::bricked) {
             constexpr int B = Lay<LAYOUT>::bs;
-            // brick index: full multiplies when WIDE, else two 24-bit products (fewer
-            // than 2^24 bricks) summed at once
-            const uint32_t b = WIDE ? ((c.z0 >> B) * (uint32_t)S.nby + (c.y0 >> B)) * (uint32_t)S.nbx + (c.x0 >> B)
-                                    : __umul24(c.z0 >> B, S.nbxy) + __umul24(c.y0 >> B, (uint32_t)S.nbx) +
-                                          (c.x0 >> B);
+            constexpr bool OVL = Lay<LAYOUT>::ovl;
+            static_assert(!OVL || (DIST && !WIDE && sizeof(T) == 2), "overlap bricks: u16, 32-bit offsets, distance grid");
+            // brick x (x0 / 3 for overlapping bricks) and index: full multiplies when
+            // WIDE, else two 24-bit products (fewer than 2^24 bricks) summed at once
+            const uint32_t bxo = OVL ? vr::bk::ovl_bx(c.x0) : (c.x0 >> B);
+            const uint32_t b = WIDE ? ((c.z0 >> B) * (uint32_t)S.nby + (c.y0 >> B)) * (uint32_t)S.nbx + bxo
+                                    : __umul24(c.z0 >> B, S.nbxy) + __umul24(c.y0 >> B, (uint32_t)S.nbx) + bxo;
             if (skipping) {
                 if (b != cur_b) {
                     cur_b = b;
@@ -650,7 +690,7 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
                     float next;
                     if constexpr (DIST) {
                         // empty brick: leave the cube of empty bricks around it
-                        const uint32_t bb[3] = {c.x0 >> B, c.y0 >> B, c.z0 >> B};
+                        const uint32_t bb[3] = {bxo, c.y0 >> B, c.z0 >> B};
                         next = skip_cube_f(S, SR, g, bb, cur_r, kf, nf);
                     } else {
                         const int k = (int)kf;
@@ -673,10 +713,12 @@ __device__ __forceinline__ float4 march(const Scene& S, const View& v, const T* 
                 }
             }
             constexpr bool PAIRS = LAYOUT == VR_LAYOUT_BRICK4_PAIRS;
-            const uint32_t o0 = PAIRS ? base_offset<WIDE, typename vr::bk::PairOf<T>::type>(c, b)
-                                      : base_offset<WIDE, T, B>(c, b);
+            const uint32_t o0 = OVL     ? base_offset_ovl(c, b, c.x0 - 3u * bxo)
+                                : PAIRS ? base_offset<WIDE, typename vr::bk::PairOf<T>::type>(c, b)
+                                        : base_offset<WIDE, T, B>(c, b);
             if (o0 != kc.key_o) {
-                if (PAIRS) load_corners_pairs<T, WIDE>(S, vol, c, o0, kc);
+                if constexpr (OVL) load_corners_ovl(S, reinterpret_cast<const uint16_t*>(vol), c, o0, kc);
+                else if constexpr (PAIRS) load_corners_pairs<T, WIDE>(S, vol, c, o0, kc);
                 else load_corners<T, WIDE, B>(S, vol, c, o0, kc);
                 kc.key_o = o0;
             }
@@ -731,16 +773,20 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
     VR_REQUIRE(vol->dtype == VR_U16_NORM || vol->dtype == VR_F32, VR_ERR_DTYPE,
                "raycast: unknown dtype %d", vol->dtype);
     VR_REQUIRE(vol->layout == VR_LAYOUT_LINEAR || vol->layout == VR_LAYOUT_BRICK4 ||
-                   vol->layout == VR_LAYOUT_BRICK4_PAIRS || vol->layout == VR_LAYOUT_BRICK8,
+                   vol->layout == VR_LAYOUT_BRICK4_PAIRS || vol->layout == VR_LAYOUT_BRICK8 ||
+                   vol->layout == VR_LAYOUT_BRICK4_OVERLAP,
                VR_ERR_RANGE, "raycast: unknown layout %d", vol->layout);
     VR_REQUIRE(vol->nx >= 1 && vol->ny >= 1 && vol->nz >= 1 && vol->nx < (1 << 30) &&
                    vol->ny < (1 << 30) && vol->nz < (1 << 30),
                VR_ERR_DIMS, "raycast: volume dims %lld x %lld x %lld", (long long)vol->nx,
                (long long)vol->ny, (long long)vol->nz);
     const int bs = brick_shift(vol->layout);
-    const int64_t be = int64_t(1) << bs, bvox = int64_t(1) << (3 * bs);   // brick edge and voxels
-    const int64_t nb[3] = {(vol->nx + be - 1) >> bs, (vol->ny + be - 1) >> bs, (vol->nz + be - 1) >> bs};
+    const int64_t bvox = int64_t(1) << (3 * bs);   // voxels per brick
+    int64_t nb[3];
+    vr::bk::brick_grid(vol->layout, vol->nx, vol->ny, vol->nz, nb);
     const bool bricked = vol->layout != VR_LAYOUT_LINEAR;
+    VR_REQUIRE(vol->layout != VR_LAYOUT_BRICK4_OVERLAP || vol->dtype == VR_U16_NORM, VR_ERR_DTYPE,
+               "raycast: VR_LAYOUT_BRICK4_OVERLAP holds u16 volumes only");
     const int64_t elems = bricked ? nb[0] * nb[1] * nb[2] * bvox : vol->nx * vol->ny * vol->nz;
     VR_REQUIRE(elems <= (int64_t)0xFFFFFFFFu, VR_ERR_DIMS,
                "raycast: volume of %lld elements exceeds 32-bit offsets", (long long)elems);
@@ -803,10 +849,14 @@ inline int build_scene(const vr_volume* vol, const float* d_tf, const vr_camera*
         S.occ = nullptr;
         S.dist = nullptr;
     }
-    {   // 32-bit byte offsets and 24-bit brick-index products, unless the volume is too large
+    {   // 32-bit byte offsets (to the end of the apron) and 24-bit brick-index products,
+        // unless the volume is too large
         const int64_t bricks = nb[0] * nb[1] * nb[2];
         const int64_t elem_bytes = (vol->dtype == VR_U16_NORM ? 2 : 4) * (vol->layout == VR_LAYOUT_BRICK4_PAIRS ? 2 : 1);
-        S.wide = (bricks > (int64_t(1) << 24) || bricks * bvox * elem_bytes > (int64_t(1) << 32)) ? 1 : 0;
+        const int64_t bytes = (bricks + vr::bk::apron_bricks(nb[0], nb[1])) * bvox * elem_bytes;
+        S.wide = (bricks > (int64_t(1) << 24) || bytes > (int64_t(1) << 32)) ? 1 : 0;
+        VR_REQUIRE(!(bricked && S.wide && vol->layout == VR_LAYOUT_BRICK4_OVERLAP), VR_ERR_DIMS,
+                   "raycast: VR_LAYOUT_BRICK4_OVERLAP needs fewer than 2^24 bricks and 4 GiB");
     }
     S.view_hist = o->view_hist;
     S.W = o->width;

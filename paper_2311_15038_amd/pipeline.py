@@ -37,7 +37,8 @@ class PreviewConfig:
     ortho: bool = False
     ert_eps: float = 2.0 ** -14
     bricked: bool = True            # render from a brick layout
-    brick_edge: int = 4             # ... of 4^3 or 8^3 voxels (see tune_brick_edge)
+    brick_edge: int = 4             # ... of 4^3 or 8^3 voxels (see tune_bricks)
+    overlap: bool = True            # ... 4^3 bricks overlapping by one voxel in x (4/3 of the memory)
     pairs: bool = False             # ... of x-tap pairs (4^3 only; two voxels per load, twice the memory)
     skip_empty: bool = True         # with the brick occupancy (exact)
     mark_by_tf: bool = True         # ... marking voxels above the level the TF leaves empty (exact)
@@ -109,8 +110,10 @@ class PreviewPipeline:
             self.hollow_level = torch.empty((rz, ry, rx), dtype=torch.uint16, device=dev)
             self.hollow_kept = torch.zeros(1, dtype=torch.int64, device=dev)
         self.render_vol = None
+        # overlapping bricks are 4^3 plain ones (not pairs, not 8^3)
+        self.overlap = cfg.overlap and cfg.brick_edge == 4 and not cfg.pairs
         if cfg.bricked:
-            layout = (vr.LAYOUT_BRICK4_PAIRS if cfg.pairs else
+            layout = (vr.LAYOUT_BRICK4_PAIRS if cfg.pairs else vr.LAYOUT_BRICK4_OVERLAP if self.overlap else
                       vr.LAYOUT_BRICK8 if cfg.brick_edge == 8 else vr.LAYOUT_BRICK4)
             nb, nel, nocc = vr.vr_brick_count_layout(layout, rx, ry, rz)
             occ = torch.empty(nocc, dtype=torch.uint8, device=dev) if cfg.skip_empty else None
@@ -164,7 +167,7 @@ class PreviewPipeline:
             src = self.hollow_level
         if self.render_vol is not None:
             vr.vr_brick_volume(src, out=self.render_vol, stream=stream, pairs=self.cfg.pairs,
-                               edge=self.cfg.brick_edge, mark_above=self.mark_above)
+                               edge=self.cfg.brick_edge, mark_above=self.mark_above, overlap=self.overlap)
             src = self.render_vol
         vr.vr_raycast(src, self.tf, self.cams, c.width, c.height, c.step,
                       ert_eps=c.ert_eps, out=self.frames, samples=self.samples if count else None,
@@ -197,7 +200,7 @@ class PreviewPipeline:
         if self.render_vol is not None:
             out.append(("bricks", lambda: vr.vr_brick_volume(level, out=self.render_vol, stream=stream,
                                                              pairs=c.pairs, edge=c.brick_edge,
-                                                             mark_above=self.mark_above)))
+                                                             mark_above=self.mark_above, overlap=self.overlap)))
             src = self.render_vol
         out.append(("raycast", lambda src=src: vr.vr_raycast(src, self.tf, self.cams, c.width, c.height,
                                                              c.step, ert_eps=c.ert_eps, out=self.frames,
@@ -223,12 +226,20 @@ class PreviewPipeline:
         return vol + top + vol + lv + at_in + at_out
 
 
-def tune_brick_edge(pipe: PreviewPipeline, reps: int = 3, use_cache: bool = True, log=None):
-    """Pick the brick size (4 or 8 voxels a side) of the rendered level for this
-    pipeline: times the brick copy plus the frames for each on the pipeline's own
-    level (run a step or `reduce` first) with HIP events, and keeps the faster.
-    Results are cached beside the batch tuner's, keyed by GPU architecture, level
-    shape, frame size and views.  Returns (edge, {edge: ms})."""
+# Brick layouts the tuner chooses from: 4^3 bricks overlapping by one voxel in
+# x, plain 4^3 bricks, 8^3 bricks.
+BRICK_CHOICES = {"4o": dict(brick_edge=4, overlap=True), "4": dict(brick_edge=4, overlap=False),
+                 "8": dict(brick_edge=8, overlap=False)}
+BRICK_LAYOUT_NAMES = {"4o": "brick4_overlap", "4": "brick4", "8": "brick8"}
+
+
+def tune_bricks(pipe: PreviewPipeline, reps: int = 3, use_cache: bool = True, log=None):
+    """Pick the brick layout of the rendered level for this pipeline (a key of
+    BRICK_CHOICES): times the brick copy plus the frames for each on the
+    pipeline's own level (run a step or `reduce` first) with HIP events, and
+    keeps the fastest.  Results are cached beside the batch tuner's, keyed by GPU
+    architecture, level shape, frame size and views.  Returns
+    (choice, {choice: ms}); PreviewConfig(**BRICK_CHOICES[choice]) applies it."""
     import json
     import os
 
@@ -237,7 +248,7 @@ def tune_brick_edge(pipe: PreviewPipeline, reps: int = 3, use_cache: bool = True
     c = pipe.cfg
     level = pipe.levels[c.render_level - 1]
     arch = torch.cuda.get_device_properties(level.device).gcnArchName.split(":")[0]
-    key = f"{arch}|single|{'x'.join(map(str, level.shape))}|{c.width}x{c.height}x{len(pipe.cams)}"
+    key = f"{arch}|single-layout|{'x'.join(map(str, level.shape))}|{c.width}x{c.height}x{len(pipe.cams)}"
     path = _batch._cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -246,15 +257,16 @@ def tune_brick_edge(pipe: PreviewPipeline, reps: int = 3, use_cache: bool = True
                 cache = json.load(f)
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache:
-        return int(cache[key]), {}
+    if use_cache and cache.get(key) in BRICK_CHOICES:
+        return cache[key], {}
     times = {}
-    for edge in (4, 8):
-        bv = vr.vr_brick_volume(level, edge=edge, mark_above=pipe.mark_above)
+    for choice, kw in BRICK_CHOICES.items():
+        bv = vr.vr_brick_volume(level, edge=kw["brick_edge"], overlap=kw["overlap"], mark_above=pipe.mark_above)
         out = torch.empty_like(pipe.frames)
 
         def run():
-            vr.vr_brick_volume(level, out=bv, edge=edge, mark_above=pipe.mark_above)
+            vr.vr_brick_volume(level, out=bv, edge=kw["brick_edge"], overlap=kw["overlap"],
+                               mark_above=pipe.mark_above)
             vr.vr_raycast(bv, pipe.tf, pipe.cams, c.width, c.height, c.step, ert_eps=c.ert_eps, out=out)
 
         run()
@@ -267,17 +279,17 @@ def tune_brick_edge(pipe: PreviewPipeline, reps: int = 3, use_cache: bool = True
             e1.record()
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1))
-        times[edge] = best
+        times[choice] = best
         if log:
-            log(f"brick edge {edge}: {best:.3f} ms")
+            log(f"bricks {choice}: {best:.3f} ms")
         del bv, out
-    edge = min(times, key=times.get)
+    choice = min(times, key=times.get)
     if use_cache:
-        cache[key] = edge
+        cache[key] = choice
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             with open(path, "w") as f:
                 json.dump(cache, f, indent=1)
         except OSError:
             pass
-    return edge, times
+    return choice, times

@@ -26,7 +26,7 @@ MAX_VIEWS_PER_LAUNCH = 48
 BRICK_DIST_CAP = 8
 RULE_VALLEY, RULE_OTSU, RULE_ITS, RULE_NONE = 0, 1, 2, 3
 U16_NORM, F32 = 0, 1
-LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_BRICK4_PAIRS, LAYOUT_BRICK8 = 0, 1, 2, 3
+LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_BRICK4_PAIRS, LAYOUT_BRICK8, LAYOUT_BRICK4_OVERLAP = 0, 1, 2, 3, 4
 ERRORS = {-1: "VR_ERR_NULL", -2: "VR_ERR_DIMS", -3: "VR_ERR_RANGE", -4: "VR_ERR_DTYPE",
           -5: "VR_ERR_HIP", -6: "VR_ERR_UNSUPPORTED", -7: "VR_ERR_WORKSPACE"}
 
@@ -421,16 +421,18 @@ class BrickedVolume:
 
 
 def vr_brick_volume(src, out=None, with_occupancy=True, stream=None, pairs=False, edge=4,
-                    mark_above=0) -> BrickedVolume:
+                    mark_above=0, overlap=False) -> BrickedVolume:
     """Copy a [nz][ny][nx] u16 or f32 volume into the brick layout (+ occupancy):
     bricks of `edge` (4 or 8) voxels; with pairs, the 4^3 layout of x-tap pairs
-    (twice the memory).  The occupancy marks voxels above mark_above (u16 only;
-    tf_mark_level gives the largest level a TF allows)."""
+    (twice the memory); with overlap, 4^3 bricks overlapping by one voxel in x
+    (u16, 4/3 of the memory).  The occupancy marks voxels above mark_above (u16
+    only; tf_mark_level gives a level a TF allows)."""
     nz, ny, nx = src.shape
     dt = U16_NORM if src.dtype in _U16 else F32
-    if edge not in (4, 8) or (pairs and edge != 4):
-        raise ValueError("bricks are 4^3 (plain or pairs) or 8^3")
-    layout = LAYOUT_BRICK4_PAIRS if pairs else (LAYOUT_BRICK8 if edge == 8 else LAYOUT_BRICK4)
+    if edge not in (4, 8) or ((pairs or overlap) and edge != 4) or (pairs and overlap):
+        raise ValueError("bricks are 4^3 (plain, pairs or overlapping) or 8^3")
+    layout = (LAYOUT_BRICK4_PAIRS if pairs else LAYOUT_BRICK4_OVERLAP if overlap else
+              LAYOUT_BRICK8 if edge == 8 else LAYOUT_BRICK4)
     nb, nel, nocc = vr_brick_count_layout(layout, nx, ny, nz)
     if out is None:
         data = torch.empty(nel, dtype=src.dtype, device=src.device)

@@ -131,6 +131,13 @@ def test_brick_validation_on_the_host(lib):
     assert n.value == 2 * 1 * 3 and e.value == (6 + 2 * 1 + 2 + 1) * 512 and o.value == 3 * 6 + 1
     assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK4_PAIRS, 9, 5, 4, C.byref(n), C.byref(e), None) == 0
     assert n.value == 6 and e.value == (6 + 3 * 2 + 3 + 1) * 128
+    # overlapping 4^3 bricks: brick x serves base taps 3 bx .. 3 bx + 2, (nx - 1) / 3 + 1 of them
+    assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK4_OVERLAP, 9, 5, 4, C.byref(n), C.byref(e), C.byref(o)) == 0
+    assert n.value == 3 * 2 * 1 and e.value == (6 + 3 * 2 + 3 + 1) * 64 and o.value == 3 * 6 + 1
+    assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK4_OVERLAP, 10, 1, 1, C.byref(n), None, None) == 0
+    assert n.value == 4
+    assert lib.vr_brick_volume(C.c_void_p(256), vr.F32, vr.LAYOUT_BRICK4_OVERLAP, 8, 8, 8, C.c_void_p(256), None, 0,
+                               None) == -4
     assert lib.vr_brick_count_layout(vr.LAYOUT_LINEAR, 9, 5, 4, C.byref(n), None, None) == -3
     assert lib.vr_brick_count_layout(vr.LAYOUT_BRICK8, 0, 5, 4, C.byref(n), None, None) == -2
 

@@ -265,6 +265,92 @@ def test_brick_layout_from_unaligned_source():
     assert (bf.data.cpu().numpy() == _brick_ref(a.astype(np.float32) / 5.0)[0]).all()
 
 
+def _ovl_ref(a, pad_value=0):
+    """The overlap layout (4^3 bricks, brick bx holding voxels 3 bx .. 3 bx + 3, then the
+    apron) and its occupancy from the cells each brick serves, written out with NumPy."""
+    nz, ny, nx = a.shape
+    nbx, nby, nbz = (nx - 1) // 3 + 1, (ny + 3) // 4, (nz + 3) // 4
+    pad = np.full((nbz * 4, nby * 4, 3 * nbx + 1), pad_value, dtype=a.dtype)
+    pad[:nz, :ny, :nx] = a
+    cols = np.stack([pad[:, :, 3 * np.arange(nbx) + e] for e in range(4)], axis=-1)   # [Z][Y][nbx][4]
+    br = cols.reshape(nbz, 4, nby, 4, nbx, 4).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
+    br = np.concatenate([br, np.full((nbx * nby + nbx + 1) * 64, pad_value, dtype=a.dtype)])
+    occ = np.zeros((nbz, nby, nbx), dtype=np.uint8)
+    for z, y, x in np.argwhere(a != 0):
+        # cells whose eight taps include (x, y, z): base taps x - {0, 1} (and likewise y, z)
+        for zz in (z - 1, z):
+            for yy in (y - 1, y):
+                for xx in (x - 1, x):
+                    if zz >= 0 and yy >= 0 and xx >= 0:
+                        occ[zz // 4, yy // 4, xx // 3] = 1
+    mz, my, mx = (nbz + 3) // 4, (nby + 3) // 4, (nbx + 3) // 4
+    mpad = np.zeros((mz * 4, my * 4, mx * 4), dtype=np.uint8)
+    mpad[:nbz, :nby, :nbx] = occ
+    macro = mpad.reshape(mz, 4, my, 4, mx, 4).max(axis=(1, 3, 5))
+    cap = vr.BRICK_DIST_CAP
+    marked = np.argwhere(occ != 0)
+    grid = np.indices(occ.shape).reshape(3, -1).T
+    if len(marked):
+        dist = np.abs(grid[:, None, :] - marked[None, :, :]).max(axis=2).min(axis=1)
+    else:
+        dist = np.full(len(grid), cap)
+    dist = np.minimum(dist, cap).astype(np.uint8)
+    return br, np.concatenate([occ.reshape(-1), macro.reshape(-1), dist])
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 6, 13), (1, 1, 1), (1, 1, 2), (3, 2, 3), (5, 7, 4),
+                                   (29, 23, 37), (13, 30, 64)])
+def test_overlap_layout_and_occupancy(shape):
+    banner(f"overlap layout {shape}")
+    rng = np.random.default_rng(33)
+    a = np.zeros(shape, dtype=np.uint16)
+    m = rng.random(shape) < 0.02
+    a[m] = rng.integers(1, 65536, size=int(m.sum()))
+    a[0, 0, 0] = 7
+    a[-1, -1, -1] = 9
+    bv = vr.vr_brick_volume(to_dev_u16(a), overlap=True)
+    assert bv.layout == vr.LAYOUT_BRICK4_OVERLAP
+    br, occ = _ovl_ref(a)
+    got = bv.data.cpu().view(torch.int16).numpy().view(np.uint16)
+    assert got.size == br.size and (got == br).all()
+    assert (_occ_parts(bv.occupancy, shape, vr.LAYOUT_BRICK4_OVERLAP) == occ).all()
+    # marks above a level: the occupancy of the volume with the voxels at or below it zeroed
+    V = 30000
+    bm = vr.vr_brick_volume(to_dev_u16(a), overlap=True, mark_above=V)
+    assert (_occ_parts(bm.occupancy, shape, vr.LAYOUT_BRICK4_OVERLAP) == _ovl_ref(np.where(a > V, a, 0))[1]).all()
+    with pytest.raises(vr.VrError):
+        vr.vr_brick_volume(torch.from_numpy(a.astype(np.float32)).to(dev()), overlap=True)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (29, 23, 37), (40, 17, 50), (90, 70, 110), (16, 12, 5),
+                                   (7, 9, 2), (6, 5, 1)])
+def test_overlap_bit_identical(level1, shape):
+    """Overlapping bricks (with the distance grid and TF-level marks) give the linear
+    march's frames and taken counts bit for bit, on grazing and turntable views."""
+    banner(f"overlap bricks == linear {shape}")
+    a = level1 if shape == (64, 64, 64) else _sparse_volume(shape, 17)
+    nz, ny, nx = a.shape
+    tf_h = synth.default_tf(sigma_scale=3.0)
+    tf = _tf_dev(tf_h)
+    cams = np.concatenate([synth.turntable_cameras(nx, ny, nz, n_views=7),
+                           synth.front_ortho_camera(nx, ny, nz), _grazing_cameras(nx, ny, nz)[::2]])
+    v = to_dev_u16(a)
+    c0 = torch.zeros(2, dtype=torch.int64, device=dev())
+    lin = vr.vr_raycast(v, tf, cams, 45, 38, 0.5, samples=c0)
+    for above in (0, vr.tf_mark_level(tf_h)):
+        bo = vr.vr_brick_volume(v, overlap=True, mark_above=above)
+        c1 = torch.zeros(2, dtype=torch.int64, device=dev())
+        assert torch.equal(lin, vr.vr_raycast(bo, tf, cams, 45, 38, 0.5, samples=c1))
+        assert c1[0].item() == c0[0].item() and c1[1].item() <= c1[0].item()
+        bo.occupancy = None
+        assert torch.equal(lin, vr.vr_raycast(bo, tf, cams, 45, 38, 0.5))
+    if shape in ((29, 23, 37), (16, 12, 5)):
+        # against the oracle on the turntable and orthographic views (rays exactly along
+        # voxel boundaries, as in the grazing views, fall on either side in FP32 and FP64)
+        ref, _ = R.render(a, (1, 1, 1), tf_h.astype(np.float64), cams[:8], 45, 38, 0.5)
+        assert np.abs(lin[:8].cpu().numpy() - ref).max() <= TOL
+
+
 def _pairs_ref(a):
     """The layout of x-tap pairs: element (x, y, z) = (a[z, y, x], a[z, y, min(x + 1, nx - 1)]),
     in brick order, as the interleaved low/high voxels."""
@@ -348,7 +434,8 @@ def test_brick_and_skip_bit_identical(level1, shape):
         assert int(lohi[:, 0].sum()) <= c1[0].item() <= int(lohi[:, 1].sum()), (c1, n_ref.sum(), lohi.sum(0))
 
 
-@pytest.mark.parametrize("shape,edge", [((64, 64, 64), 4), ((29, 23, 37), 4), ((32, 40, 48), 8), ((21, 30, 13), 8)])
+@pytest.mark.parametrize("shape,edge", [((64, 64, 64), 4), ((29, 23, 37), 4), ((32, 40, 48), 8), ((21, 30, 13), 8),
+                                        ((64, 64, 64), 3), ((29, 23, 37), 3)])
 def test_far_taps_past_the_volume_have_no_weight(shape, edge):
     """The u16 march reads the far taps of cells on the volume's last voxel layer from
     the bricks' padding, the next brick, brick row or layer, or the apron after the last
@@ -366,13 +453,17 @@ def test_far_taps_past_the_volume_have_no_weight(shape, edge):
                            _grazing_cameras(nx, ny, nz)[::3]])
     v = to_dev_u16(a)
     lin = vr.vr_raycast(v, tf, cams, 48, 40, 0.5)
-    bv = vr.vr_brick_volume(v, edge=edge)
-    e = edge
-    nbz, nby, nbx = (nz + e - 1) // e, (ny + e - 1) // e, (nx + e - 1) // e
-    pad = np.full((nbz * e, nby * e, nbx * e), 65535, dtype=np.uint16)
-    pad[:nz, :ny, :nx] = a
-    br = pad.reshape(nbz, e, nby, e, nbx, e).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
-    br = np.concatenate([br, np.full((nbx * nby + nbx + 1) * e ** 3, 65535, dtype=np.uint16)])
+    if edge == 3:             # 4^3 bricks overlapping in x
+        bv = vr.vr_brick_volume(v, overlap=True)
+        br = _ovl_ref(a, pad_value=65535)[0]
+    else:
+        bv = vr.vr_brick_volume(v, edge=edge)
+        e = edge
+        nbz, nby, nbx = (nz + e - 1) // e, (ny + e - 1) // e, (nx + e - 1) // e
+        pad = np.full((nbz * e, nby * e, nbx * e), 65535, dtype=np.uint16)
+        pad[:nz, :ny, :nx] = a
+        br = pad.reshape(nbz, e, nby, e, nbx, e).transpose(0, 2, 4, 1, 3, 5).reshape(-1)
+        br = np.concatenate([br, np.full((nbx * nby + nbx + 1) * e ** 3, 65535, dtype=np.uint16)])
     assert br.size == bv.data.numel()
     bv.data.copy_(to_dev_u16(br))
     assert torch.equal(lin, vr.vr_raycast(bv, tf, cams, 48, 40, 0.5))

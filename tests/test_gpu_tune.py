@@ -1,35 +1,40 @@
-"""The single-volume brick-size tuner: it times both brick sizes on the
-pipeline's own level, caches its choice, and either choice renders the same
-frames (bit-identical) as the other."""
+"""The single-volume brick layout tuner: it times the brick layouts (4^3
+bricks overlapping in x, plain 4^3, 8^3) on the pipeline's own level, caches
+its choice, and every choice renders the same frames (bit-identical)."""
 import pytest
 import torch
 
 from paper_2311_15038_amd import pipeline as P
 from paper_2311_15038_amd import synth
+from paper_2311_15038_amd import vr
 
 from gpu_util import banner, dev
 
 pytestmark = pytest.mark.gpu
 
 
-def test_brick_edge_tuner(tmp_path, monkeypatch):
-    banner("single-volume brick-size tuner")
+def test_brick_layout_tuner(tmp_path, monkeypatch):
+    banner("single-volume brick layout tuner")
     monkeypatch.setenv("VR_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
     vol = synth.make_volume(synth.scaled_spec(150, 128, 96, 4200), dev())
     cfg = P.PreviewConfig(n_levels=2, atlas_level=0, n_views=6, width=96, height=80)
     pipe = P.PreviewPipeline(vol.shape, cfg, device=dev())
     pipe.step(vol)
-    edge, times = P.tune_brick_edge(pipe)
-    assert edge in (4, 8) and set(times) == {4, 8} and times[edge] == min(times.values())
-    again, t2 = P.tune_brick_edge(pipe)
-    assert again == edge and t2 == {}                  # served from the cache
+    choice, times = P.tune_bricks(pipe)
+    assert choice in P.BRICK_CHOICES and set(times) == set(P.BRICK_CHOICES)
+    assert times[choice] == min(times.values())
+    again, t2 = P.tune_bricks(pipe)
+    assert again == choice and t2 == {}                # served from the cache
     frames = {}
-    for e in (4, 8):
+    for k, kw in P.BRICK_CHOICES.items():
         p = P.PreviewPipeline(vol.shape, P.PreviewConfig(n_levels=2, atlas_level=0, n_views=6, width=96,
-                                                         height=80, brick_edge=e), device=dev())
+                                                         height=80, **kw), device=dev())
+        assert p.render_vol.layout == {"4o": vr.LAYOUT_BRICK4_OVERLAP, "4": vr.LAYOUT_BRICK4,
+                                       "8": vr.LAYOUT_BRICK8}[k]
         p.step(vol, count=True)
         torch.cuda.synchronize()
-        frames[e] = (p.frames.clone(), p.samples.clone(), p.view_hist.clone())
-    assert torch.equal(frames[4][0], frames[8][0])
-    assert int(frames[4][1][0]) == int(frames[8][1][0])
-    assert torch.equal(frames[4][2], frames[8][2])
+        frames[k] = (p.frames.clone(), p.samples.clone(), p.view_hist.clone())
+    for k in ("4", "8"):
+        assert torch.equal(frames["4o"][0], frames[k][0])
+        assert int(frames["4o"][1][0]) == int(frames[k][1][0])
+        assert torch.equal(frames["4o"][2], frames[k][2])
