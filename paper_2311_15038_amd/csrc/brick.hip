@@ -85,15 +85,16 @@ brick8_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nb
         row8_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, r);
 }
 
-// Overlap layout: one thread per 4-voxel row piece (grid-stride).
+// Overlap layout: one group of 16 bricks along x per workgroup.
+template <bool VEC>
 __global__ void __launch_bounds__(kThreads)
 brick_ovl_kernel(const uint16_t* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
                  uint16_t* __restrict__ dst, uint8_t* __restrict__ occ, uint8_t* __restrict__ macro, int nmx,
                  int nmy, uint32_t above)
 {
-    const int64_t n = (int64_t)nbx * (nby * 4) * ((nz + 3) / 4 * 4);
-    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads)
-        row_ovl_body(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, r);
+    __shared__ OvlLds G;
+    slab_ovl_body<VEC>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, blockIdx.x * 16, blockIdx.y,
+                       blockIdx.z, threadIdx.x, G);
 }
 
 // Rows load four voxels at a time when nx is a multiple of 4 and src is
@@ -194,11 +195,14 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
     const bool pairs = layout == VR_LAYOUT_BRICK4_PAIRS;
     const int inx = (int)nx, iny = (int)ny, inz = (int)nz;
     if (layout == VR_LAYOUT_BRICK4_OVERLAP) {
-        const int64_t pieces = (int64_t)nbx * (nby * 4) * (nbz * 4);
-        const unsigned g4 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap * 4, vr::ceil_div<int64_t>(pieces, kThreads)));
-        brick_ovl_kernel<<<g4, kThreads, 0, s>>>(static_cast<const uint16_t*>(d_src), inx, iny, inz, nbx, nby,
-                                                 static_cast<uint16_t*>(d_bricked), d_occupancy, macro, nmx, nmy,
-                                                 above);
+        const auto* sp = static_cast<const uint16_t*>(d_src);
+        auto* dp = static_cast<uint16_t*>(d_bricked);
+        if (nx % 4 == 0 && reinterpret_cast<uintptr_t>(d_src) % 8 == 0)
+            brick_ovl_kernel<true><<<grid, kThreads, 0, s>>>(sp, inx, iny, inz, nbx, nby, dp, d_occupancy, macro, nmx,
+                                                             nmy, above);
+        else
+            brick_ovl_kernel<false><<<grid, kThreads, 0, s>>>(sp, inx, iny, inz, nbx, nby, dp, d_occupancy, macro,
+                                                              nmx, nmy, above);
     } else if (layout == VR_LAYOUT_BRICK8) {
         const int64_t pieces = (int64_t)nbx * (nby * 8) * (nbz * 8);
         const unsigned g8 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap * 4, vr::ceil_div<int64_t>(pieces, kThreads)));

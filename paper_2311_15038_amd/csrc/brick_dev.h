@@ -239,50 +239,81 @@ __device__ inline void row8_body(const T* __restrict__ src, int nx, int ny, int 
                 }
 }
 
-// Overlap layout: row piece r = ((z * 4 nby) + y) * nbx + bx holds voxels
-// 3 bx .. 3 bx + 3 of row (y, z) of the volume padded to whole bricks (0 past
-// its end), one brick row, stored as one 8-byte vector at element
-// ((z & 3) * 4 + (y & 3)) * 4 of brick (bx, y >> 2, z >> 2); the pieces
-// r < nbx * 4 nby * 4 nbz cover every brick.  The four voxels are the x taps of
-// every cell the brick serves in that row, so a marking voxel marks the
-// piece's own brick, and the brick below in y or z when the row is the first
-// of its brick there (its cells at y - 1 or z - 1 take it as their far tap),
-// with the group marks of each.
-__device__ inline void row_ovl_body(const uint16_t* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
-                                    uint16_t* __restrict__ dst, uint8_t* __restrict__ occ,
-                                    uint8_t* __restrict__ macro, int nmx, int nmy, uint32_t above, int64_t r)
+// Overlap layout: a group of kThreads threads (thread t) converts the 16
+// bricks bx0 .. bx0 + 15 of brick row (by, bz): their 16 voxel rows (4 y x 4 z)
+// hold voxels 3 bx0 .. 3 bx0 + 48 (0 past the volume's end).  Thread t reads
+// four voxels of row t / 16 at 3 bx0 + 4 (t % 16) into LDS (whole rows, in
+// order); brick bi's row r is then voxels 3 bi .. 3 bi + 3 of LDS row r, and
+// threads 0..127 each store 16 bytes (two rows of one brick) of the 16 whole
+// bricks.  Marks: the four voxels of a brick row are the x taps of every cell
+// the brick serves in that row, so a marking voxel marks the row's brick, and
+// the brick below in y or z when the row is the first of its brick there (its
+// cells at y - 1 or z - 1 take the row as their far tap); the group marks of
+// each follow.  VEC: nx is a multiple of 4 and src is aligned to four voxels,
+// so each thread's four voxels are one load.
+struct OvlLds {
+    __align__(16) uint16_t rows[16][64];
+    uint32_t marks[16][4];        // brick bi: own, below in y, below in z, below in both
+};
+
+template <bool VEC>
+__device__ inline void slab_ovl_body(const uint16_t* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
+                                     uint16_t* __restrict__ dst, uint8_t* __restrict__ occ,
+                                     uint8_t* __restrict__ macro, int nmx, int nmy, uint32_t above, int bx0, int by,
+                                     int bz, int t, OvlLds& G)
 {
-    const int bx = (int)(r % nbx);
-    const int64_t yz = r / nbx;
-    const int py = nby * 4;
-    const int y = (int)(yz % py), z = (int)(yz / py);
-    const bool rowok = y < ny && z < nz;
-    const uint16_t* row = src + ((int64_t)(rowok ? z : 0) * ny + (rowok ? y : 0)) * nx;
-    const int x0 = bx * 3;
-    uint16_t v[4];
+    if (t < 64) G.marks[t >> 2][t & 3] = 0u;
+    {
+        const int r = t >> 4, y = by * 4 + (r & 3), z = bz * 4 + (r >> 2);
+        const int x = bx0 * 3 + (t & 15) * 4;
+        const bool rowok = y < ny && z < nz;
+        const uint16_t* row = src + ((int64_t)(rowok ? z : 0) * ny + (rowok ? y : 0)) * nx;
+        uint16_t v[4];
+        if (VEC && rowok && x + 3 < nx) {
+            unpack4(*reinterpret_cast<const uint2*>(row + x), v);
+        } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = (rowok && x0 + e < nx) ? row[x0 + e] : (uint16_t)0;
-    const int64_t brick = ((int64_t)(z >> 2) * nby + (y >> 2)) * nbx + bx;
-    uint2 w;
-    w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-    w.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-    *reinterpret_cast<uint2*>(dst + (brick << 6) + (((z & 3) << 4) | ((y & 3) << 2))) = w;
-    if (occ == nullptr) return;
-    bool any = false;
+            for (int e = 0; e < 4; ++e) v[e] = (rowok && x + e < nx) ? row[x + e] : (uint16_t)0;
+        }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) any |= marks(v[e], above);
-    if (!any) return;
-    const int by = y >> 2, bz = z >> 2;
-    const int ys[2] = {by, ((y & 3) == 0 && by > 0) ? by - 1 : -1};
-    const int zs[2] = {bz, ((z & 3) == 0 && bz > 0) ? bz - 1 : -1};
+        for (int e = 0; e < 4; ++e) G.rows[r][(t & 15) * 4 + e] = v[e];
+    }
+    __syncthreads();
+    {   // marks: thread t looks at row t % 16 of brick t / 16
+        const int bi = t >> 4, r = t & 15;
+        bool any = false;
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-            if (ys[b] >= 0 && zs[c] >= 0) {
-                occ[((int64_t)zs[c] * nby + ys[b]) * nbx + bx] = 1;
-                macro[((int64_t)(zs[c] >> 2) * nmy + (ys[b] >> 2)) * nmx + (bx >> 2)] = 1;
-            }
+        for (int e = 0; e < 4; ++e) any |= marks(G.rows[r][bi * 3 + e], above);
+        if (any && bx0 + bi < nbx) {
+            G.marks[bi][0] = 1u;
+            const bool y0 = (r & 3) == 0 && by > 0, z0 = (r >> 2) == 0 && bz > 0;
+            if (y0) G.marks[bi][1] = 1u;
+            if (z0) G.marks[bi][2] = 1u;
+            if (y0 && z0) G.marks[bi][3] = 1u;
+        }
+    }
+    const int nb_here = min(16, nbx - bx0);
+    if (t < 128) {      // brick t / 8, rows 2 (t % 8) and 2 (t % 8) + 1
+        const int bi = t >> 3, r = (t & 7) * 2;
+        if (bi < nb_here) {
+            uint4 w;
+            w.x = (uint32_t)G.rows[r][bi * 3] | ((uint32_t)G.rows[r][bi * 3 + 1] << 16);
+            w.y = (uint32_t)G.rows[r][bi * 3 + 2] | ((uint32_t)G.rows[r][bi * 3 + 3] << 16);
+            w.z = (uint32_t)G.rows[r + 1][bi * 3] | ((uint32_t)G.rows[r + 1][bi * 3 + 1] << 16);
+            w.w = (uint32_t)G.rows[r + 1][bi * 3 + 2] | ((uint32_t)G.rows[r + 1][bi * 3 + 3] << 16);
+            const int64_t brick = ((int64_t)bz * nby + by) * nbx + bx0 + bi;
+            *reinterpret_cast<uint4*>(dst + (brick << 6) + r * 4) = w;
+        }
+    }
+    __syncthreads();
+    if (occ != nullptr && t < 64) {
+        const int bi = t >> 2, k = t & 3;
+        if (bi < nb_here && G.marks[bi][k]) {
+            const int bx = bx0 + bi, byy = by - (k & 1), bzz = bz - (k >> 1);
+            occ[((int64_t)bzz * nby + byy) * nbx + bx] = 1;
+            macro[((int64_t)(bzz >> 2) * nmy + (byy >> 2)) * nmx + (bx >> 2)] = 1;
+        }
+    }
 }
 
 }  // namespace bk
