@@ -56,8 +56,9 @@ ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539636 / 19674760,
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
 # 524316.4 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 2856693.0625, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.6875,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "aa959aef6729139d", "mark_above": 3854}
+RAYCAST_TRAFFIC = {"fetch_kib": 2844990.75, "write_kib": 156651.5, "fetch_scale": 1048576 / 524316.3125,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "b0849fac0d4a89bf", "mark_above": 3854,
+                   "bricks": "4o"}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
 RAYCAST_SOURCES = ("raycast.hip", "raycast_dev.h", "raycast_staged.h", "brick_dev.h", "brick.hip", "common.h",
@@ -77,15 +78,16 @@ PAPER_FIGURES = {
 }
 
 
-def raycast_traffic(mark_above=RAYCAST_TRAFFIC["mark_above"]):
-    """The counted traffic of the ray caster, or None once its sources (or the
-    level its bricks are marked above) differ from those measured."""
+def raycast_traffic(mark_above=RAYCAST_TRAFFIC["mark_above"], bricks=RAYCAST_TRAFFIC["bricks"]):
+    """The counted traffic of the ray caster, or None once its sources, the level
+    its bricks are marked above or its brick layout differ from those measured."""
     import hashlib
     h = hashlib.sha256()
     for f in RAYCAST_SOURCES:
         with open(os.path.join(ROOT, "paper_2311_15038_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != RAYCAST_TRAFFIC["sources_sha256_16"] or mark_above != RAYCAST_TRAFFIC["mark_above"]:
+    if (h.hexdigest()[:16] != RAYCAST_TRAFFIC["sources_sha256_16"] or mark_above != RAYCAST_TRAFFIC["mark_above"]
+            or bricks != RAYCAST_TRAFFIC["bricks"]):
         return None
     return RAYCAST_TRAFFIC["bytes"]
 
@@ -817,7 +819,7 @@ def main():
                    "volume": [1024, 1024, 1024], "levels": 4, "views": 36, "image": [512, 512]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": raycast_traffic(res["mark_above"]),
+                     "traffic": raycast_traffic(res["mark_above"], res["render_tuning"]["bricks"]),
                      "traffic_unit": "B per launch (HBM read + write, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "algorithmic_bytes": res["raycast_alg_bytes"],
                      "kernel": res["raycast_kernel"],
@@ -825,7 +827,7 @@ def main():
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
-                                 "TD_busy": 0.85, "TA_busy": 0.62, "VALU_busy": 0.77,
+                                 "TD_busy": 0.87, "TA_busy": 0.64, "VALU_busy": 0.80,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "render_tuning": res["render_tuning"],
         "brick_mark_above": res["mark_above"],
