@@ -85,7 +85,7 @@ brick8_kernel(const T* __restrict__ src, int nx, int ny, int nz, int nbx, int nb
         row8_body<T>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, r);
 }
 
-// Overlap layout: one group of 16 bricks along x per workgroup.
+// Overlap layout: one group of kOvlBricks bricks along x per workgroup.
 template <bool VEC>
 __global__ void __launch_bounds__(kThreads)
 brick_ovl_kernel(const uint16_t* __restrict__ src, int nx, int ny, int nz, int nbx, int nby,
@@ -93,8 +93,8 @@ brick_ovl_kernel(const uint16_t* __restrict__ src, int nx, int ny, int nz, int n
                  int nmy, uint32_t above)
 {
     __shared__ OvlLds G;
-    slab_ovl_body<VEC>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, blockIdx.x * 16, blockIdx.y,
-                       blockIdx.z, threadIdx.x, G);
+    slab_ovl_body<VEC>(src, nx, ny, nz, nbx, nby, dst, occ, macro, nmx, nmy, above, blockIdx.x * kOvlBricks,
+                       blockIdx.y, blockIdx.z, threadIdx.x, G);
 }
 
 // Rows load four voxels at a time when nx is a multiple of 4 and src is
@@ -197,12 +197,13 @@ extern "C" int vr_brick_volume(const void* d_src, int dtype, int layout, int64_t
     if (layout == VR_LAYOUT_BRICK4_OVERLAP) {
         const auto* sp = static_cast<const uint16_t*>(d_src);
         auto* dp = static_cast<uint16_t*>(d_bricked);
+        const dim3 og((unsigned)vr::ceil_div(nbx, kOvlBricks), (unsigned)nby, (unsigned)nbz);
         if (nx % 4 == 0 && reinterpret_cast<uintptr_t>(d_src) % 8 == 0)
-            brick_ovl_kernel<true><<<grid, kThreads, 0, s>>>(sp, inx, iny, inz, nbx, nby, dp, d_occupancy, macro, nmx,
-                                                             nmy, above);
+            brick_ovl_kernel<true><<<og, kThreads, 0, s>>>(sp, inx, iny, inz, nbx, nby, dp, d_occupancy, macro, nmx,
+                                                           nmy, above);
         else
-            brick_ovl_kernel<false><<<grid, kThreads, 0, s>>>(sp, inx, iny, inz, nbx, nby, dp, d_occupancy, macro,
-                                                              nmx, nmy, above);
+            brick_ovl_kernel<false><<<og, kThreads, 0, s>>>(sp, inx, iny, inz, nbx, nby, dp, d_occupancy, macro,
+                                                            nmx, nmy, above);
     } else if (layout == VR_LAYOUT_BRICK8) {
         const int64_t pieces = (int64_t)nbx * (nby * 8) * (nbz * 8);
         const unsigned g8 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap * 4, vr::ceil_div<int64_t>(pieces, kThreads)));

@@ -239,21 +239,24 @@ __device__ inline void row8_body(const T* __restrict__ src, int nx, int ny, int 
                 }
 }
 
-// Overlap layout: a group of kThreads threads (thread t) converts the 16
-// bricks bx0 .. bx0 + 15 of brick row (by, bz): their 16 voxel rows (4 y x 4 z)
-// hold voxels 3 bx0 .. 3 bx0 + 48 (0 past the volume's end).  Thread t reads
-// four voxels of row t / 16 at 3 bx0 + 4 (t % 16) into LDS (whole rows, in
-// order); brick bi's row r is then voxels 3 bi .. 3 bi + 3 of LDS row r, and
-// threads 0..127 each store 16 bytes (two rows of one brick) of the 16 whole
-// bricks.  Marks: the four voxels of a brick row are the x taps of every cell
-// the brick serves in that row, so a marking voxel marks the row's brick, and
-// the brick below in y or z when the row is the first of its brick there (its
-// cells at y - 1 or z - 1 take the row as their far tap); the group marks of
-// each follow.  VEC: nx is a multiple of 4 and src is aligned to four voxels,
-// so each thread's four voxels are one load.
+// Overlap layout: a group of kThreads threads (thread t) converts the
+// kOvlBricks bricks bx0 .. bx0 + kOvlBricks - 1 of brick row (by, bz): their 16
+// voxel rows (4 y x 4 z) hold voxels 3 bx0 .. 3 bx0 + 3 kOvlBricks (0 past the
+// volume's end).  With 64 bricks a row's 192 + 1 voxels start on a 384-byte
+// boundary (bx0 is a multiple of 64), so the row reads fill whole cache lines.
+// The rows go through LDS in order, four voxels per load; brick bi's row r is
+// then voxels 3 bi .. 3 bi + 3 of LDS row r, and the bricks leave as 16-byte
+// stores (two rows of one brick each).  Marks: the four voxels of a brick row
+// are the x taps of every cell the brick serves in that row, so a marking
+// voxel marks the row's brick, and the brick below in y or z when the row is
+// the first of its brick there (its cells at y - 1 or z - 1 take the row as
+// their far tap); the group marks of each follow.  VEC: nx is a multiple of 4
+// and src is aligned to four voxels, so each four voxels are one load.
+constexpr int kOvlBricks = 64;
+constexpr int kOvlRow = 3 * kOvlBricks + 4;      // voxels of an LDS row (one load past the last brick)
 struct OvlLds {
-    __align__(16) uint16_t rows[16][64];
-    uint32_t marks[16][4];        // brick bi: own, below in y, below in z, below in both
+    __align__(16) uint16_t rows[16][kOvlRow];
+    uint32_t marks[kOvlBricks][4];   // brick bi: own, below in y, below in z, below in both
 };
 
 template <bool VEC>
@@ -262,10 +265,12 @@ __device__ inline void slab_ovl_body(const uint16_t* __restrict__ src, int nx, i
                                      uint8_t* __restrict__ macro, int nmx, int nmy, uint32_t above, int bx0, int by,
                                      int bz, int t, OvlLds& G)
 {
-    if (t < 64) G.marks[t >> 2][t & 3] = 0u;
-    {
-        const int r = t >> 4, y = by * 4 + (r & 3), z = bz * 4 + (r >> 2);
-        const int x = bx0 * 3 + (t & 15) * 4;
+    constexpr int kQuads = kOvlRow / 4;             // four-voxel loads per row
+    for (int q = t; q < kOvlBricks * 4; q += kThreads) G.marks[q >> 2][q & 3] = 0u;
+    for (int q = t; q < 16 * kQuads; q += kThreads) {
+        const int r = q / kQuads, c = q % kQuads;
+        const int y = by * 4 + (r & 3), z = bz * 4 + (r >> 2);
+        const int x = bx0 * 3 + c * 4;
         const bool rowok = y < ny && z < nz;
         const uint16_t* row = src + ((int64_t)(rowok ? z : 0) * ny + (rowok ? y : 0)) * nx;
         uint16_t v[4];
@@ -276,15 +281,16 @@ __device__ inline void slab_ovl_body(const uint16_t* __restrict__ src, int nx, i
             for (int e = 0; e < 4; ++e) v[e] = (rowok && x + e < nx) ? row[x + e] : (uint16_t)0;
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) G.rows[r][(t & 15) * 4 + e] = v[e];
+        for (int e = 0; e < 4; ++e) G.rows[r][c * 4 + e] = v[e];
     }
     __syncthreads();
-    {   // marks: thread t looks at row t % 16 of brick t / 16
-        const int bi = t >> 4, r = t & 15;
+    const int nb_here = min(kOvlBricks, nbx - bx0);
+    for (int q = t; q < kOvlBricks * 16; q += kThreads) {   // marks: row q % 16 of brick q / 16
+        const int bi = q >> 4, r = q & 15;
         bool any = false;
 #pragma unroll
         for (int e = 0; e < 4; ++e) any |= marks(G.rows[r][bi * 3 + e], above);
-        if (any && bx0 + bi < nbx) {
+        if (any && bi < nb_here) {
             G.marks[bi][0] = 1u;
             const bool y0 = (r & 3) == 0 && by > 0, z0 = (r >> 2) == 0 && bz > 0;
             if (y0) G.marks[bi][1] = 1u;
@@ -292,9 +298,8 @@ __device__ inline void slab_ovl_body(const uint16_t* __restrict__ src, int nx, i
             if (y0 && z0) G.marks[bi][3] = 1u;
         }
     }
-    const int nb_here = min(16, nbx - bx0);
-    if (t < 128) {      // brick t / 8, rows 2 (t % 8) and 2 (t % 8) + 1
-        const int bi = t >> 3, r = (t & 7) * 2;
+    for (int q = t; q < kOvlBricks * 8; q += kThreads) {    // brick q / 8, rows 2 (q % 8) and 2 (q % 8) + 1
+        const int bi = q >> 3, r = (q & 7) * 2;
         if (bi < nb_here) {
             uint4 w;
             w.x = (uint32_t)G.rows[r][bi * 3] | ((uint32_t)G.rows[r][bi * 3 + 1] << 16);
@@ -306,8 +311,9 @@ __device__ inline void slab_ovl_body(const uint16_t* __restrict__ src, int nx, i
         }
     }
     __syncthreads();
-    if (occ != nullptr && t < 64) {
-        const int bi = t >> 2, k = t & 3;
+    if (occ == nullptr) return;
+    for (int q = t; q < kOvlBricks * 4; q += kThreads) {
+        const int bi = q >> 2, k = q & 3;
         if (bi < nb_here && G.marks[bi][k]) {
             const int bx = bx0 + bi, byy = by - (k & 1), bzz = bz - (k >> 1);
             occ[((int64_t)bzz * nby + byy) * nbx + bx] = 1;
