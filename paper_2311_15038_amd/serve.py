@@ -387,7 +387,11 @@ class GpuExecutor:
         self.rule_param = rule_param
         self.top_slices = top_slices
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
-        self.tf = torch.from_numpy(synth.default_tf() if tf is None else tf).to(self.dev)
+        tf_host = synth.default_tf() if tf is None else tf
+        self.tf = torch.from_numpy(tf_host).to(self.dev)
+        # resident levels are kept as 4^3 bricks overlapping in x, marked above the level
+        # the (fixed) TF leaves at zero extinction
+        self.mark_above = vr.tf_mark_level(tf_host)
         self.vols = {}               # vol_id -> dict of device tensors
         self.store = store if store is not None else {}
 
@@ -414,8 +418,8 @@ class GpuExecutor:
     def volume_bytes(self, req):
         n = int(self.edges[req.vol_id])
         lv = self.vr.level_shape((n, n, n), 1)
-        nb, nocc = self.vr.vr_brick_count(lv[2], lv[1], lv[0])
-        return (n ** 3 * 2 + int(np.prod(lv)) * 2 + nb * 64 * 2 + nocc
+        _, nel, nocc = self.vr.vr_brick_count_layout(self.vr.LAYOUT_BRICK4_OVERLAP, lv[2], lv[1], lv[0])
+        return (n ** 3 * 2 + int(np.prod(lv)) * 2 + nel * 2 + nocc
                 + 2 * self.vr.NBINS * 8 + self.vr.KEEP_WORDS * 4 + 16)
 
     def work_bytes(self, req):
@@ -431,7 +435,7 @@ class GpuExecutor:
             H, Ht = vr.vr_histogram_with_top(v, self.top_slices, stream=stream)
             res, bits = vr.vr_select_threshold(H, Ht, self.rule, self.rule_param, stream=stream)
             (L1,) = vr.vr_threshold_downsample(v, bits, 1, stream=stream)
-            bv = vr.vr_brick_volume(L1, stream=stream)
+            bv = vr.vr_brick_volume(L1, stream=stream, overlap=True, mark_above=self.mark_above)
             ready = torch.cuda.Event()
             ready.record(stream)
         self.vols[vol_id] = dict(vol=raw, H=H, Ht=Ht, res=res, bits=bits, L1=L1, bv=bv, ready=ready)
