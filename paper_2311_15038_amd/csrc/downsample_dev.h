@@ -108,6 +108,15 @@ __device__ inline void tile_body(const uint16_t* __restrict__ vol, int nx, int n
                     v[j][r][2] = q.y & 0xFFFFu; v[j][r][3] = q.y >> 16;
                     v[j][r][4] = q.z & 0xFFFFu; v[j][r][5] = q.z >> 16;
                     v[j][r][6] = q.w & 0xFFFFu; v[j][r][7] = q.w >> 16;
+                } else if (y < ny && z < nz && x + 8 <= nx) {
+                    // a whole piece of a row whose start is only 2-byte aligned: one
+                    // 16-byte load (the device runs with unaligned access enabled)
+                    typedef uint4 u32x4_a2 __attribute__((aligned(2)));
+                    const uint4 q = *reinterpret_cast<const u32x4_a2*>(row + x);
+                    v[j][r][0] = q.x & 0xFFFFu; v[j][r][1] = q.x >> 16;
+                    v[j][r][2] = q.y & 0xFFFFu; v[j][r][3] = q.y >> 16;
+                    v[j][r][4] = q.z & 0xFFFFu; v[j][r][5] = q.z >> 16;
+                    v[j][r][6] = q.w & 0xFFFFu; v[j][r][7] = q.w >> 16;
                 } else {
                     const bool rowok = y < ny && z < nz;
 #pragma unroll
