@@ -93,6 +93,13 @@ def test_raycast_validation_on_the_host(lib):
     assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -3
     assert "occupancy_above" in lib.vr_last_error().decode()
     vol.occupancy_above, vol.dtype = 0, vr.U16_NORM
+    # overlapping bricks hold u16 volumes with 32-bit offsets only
+    vol.layout, vol.dtype = vr.LAYOUT_BRICK4_OVERLAP, vr.F32
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -4
+    vol.dtype, vol.nx, vol.ny, vol.nz = vr.U16_NORM, 3 * 1024 + 1, 512, 512   # 1025 x 128 x 128 bricks
+    assert lib.vr_raycast(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16), None, None) == -2
+    assert "2^24 bricks" in lib.vr_last_error().decode()
+    vol.layout, vol.nx, vol.ny, vol.nz = 0, 8, 8, 8
     # the adjoint differentiates f32 grids only
     assert lib.vr_raycast_backward(C.byref(vol), C.c_void_p(16), cams, nv, C.byref(ok), C.c_void_p(16),
                                    C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == -4
