@@ -54,10 +54,10 @@ ADJOINT_COUNTERS = {"atomic_requests_per_evaluated_sample": 17539636 / 19674760,
 # FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of
 # --traffic-probe, each scaled by what the same counter reads for a kernel of
 # known traffic in the same run (1 GiB read, 1 GiB written): FETCH_SIZE read
-# 524316.4 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
+# 524315.9 KiB for it (scale 1.9999), WRITE_SIZE 1048576 KiB (scale 1.000).
 # Valid only for the kernel sources they were taken on (fingerprint below).
-RAYCAST_TRAFFIC = {"fetch_kib": 2850963.4375, "write_kib": 156651.53125, "fetch_scale": 1048576 / 524316.5,
-                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "bf4c8dc4e8d4986e", "mark_above": 3854,
+RAYCAST_TRAFFIC = {"fetch_kib": 2844161.375, "write_kib": 156651.5, "fetch_scale": 1048576 / 524315.875,
+                   "write_scale": 1048576 / 1048576, "sources_sha256_16": "1a83248f16faca31", "mark_above": 3854,
                    "bricks": "4o"}
 RAYCAST_TRAFFIC["bytes"] = int(round((RAYCAST_TRAFFIC["fetch_kib"] * RAYCAST_TRAFFIC["fetch_scale"]
                                       + RAYCAST_TRAFFIC["write_kib"] * RAYCAST_TRAFFIC["write_scale"]) * 1024))
@@ -827,7 +827,7 @@ def main():
                      "samples": "evaluated",
                      "kernel_ms": rc_ms,
                      "limiter": {"unit": "vector-memory pipeline (texture address/data, trilinear gathers)",
-                                 "TD_busy": 0.85, "TA_busy": 0.62, "VALU_busy": 0.80,
+                                 "TD_busy": 0.87, "TA_busy": 0.64, "VALU_busy": 0.81,
                                  "source": "profiles/raycast_fwd_1024_turntable_counters.md"}},
         "render_tuning": res["render_tuning"],
         "brick_mark_above": res["mark_above"],

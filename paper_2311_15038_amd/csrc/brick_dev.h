@@ -244,7 +244,8 @@ __device__ inline void row8_body(const T* __restrict__ src, int nx, int ny, int 
 // voxel rows (4 y x 4 z) hold voxels 3 bx0 .. 3 bx0 + 3 kOvlBricks (0 past the
 // volume's end).  With 64 bricks a row's 192 + 1 voxels start on a 384-byte
 // boundary (bx0 is a multiple of 64), so the row reads fill whole cache lines.
-// The rows go through LDS in order, four voxels per load; brick bi's row r is
+// The rows go through LDS in order, four voxels per load (each thread's loads
+// all issued before its LDS stores); brick bi's row r is
 // then voxels 3 bi .. 3 bi + 3 of LDS row r, and the bricks leave as 16-byte
 // stores (two rows of one brick each).  Marks: the four voxels of a brick row
 // are the x taps of every cell the brick serves in that row, so a marking
@@ -266,22 +267,35 @@ __device__ inline void slab_ovl_body(const uint16_t* __restrict__ src, int nx, i
                                      int bz, int t, OvlLds& G)
 {
     constexpr int kQuads = kOvlRow / 4;             // four-voxel loads per row
+    constexpr int kLoads = (16 * kQuads + kThreads - 1) / kThreads;   // per thread
     for (int q = t; q < kOvlBricks * 4; q += kThreads) G.marks[q >> 2][q & 3] = 0u;
-    for (int q = t; q < 16 * kQuads; q += kThreads) {
-        const int r = q / kQuads, c = q % kQuads;
-        const int y = by * 4 + (r & 3), z = bz * 4 + (r >> 2);
-        const int x = bx0 * 3 + c * 4;
-        const bool rowok = y < ny && z < nz;
-        const uint16_t* row = src + ((int64_t)(rowok ? z : 0) * ny + (rowok ? y : 0)) * nx;
-        uint16_t v[4];
-        if (VEC && rowok && x + 3 < nx) {
-            unpack4(*reinterpret_cast<const uint2*>(row + x), v);
-        } else {
+    // All of a thread's loads are issued before the first LDS store, so that
+    // they are in flight together.
+    uint2 w[kLoads];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (rowok && x + e < nx) ? row[x + e] : (uint16_t)0;
+    for (int k = 0; k < kLoads; ++k) {
+        const int q = t + k * kThreads;
+        w[k] = make_uint2(0u, 0u);
+        if (q < 16 * kQuads) {
+            const int r = q / kQuads, c = q % kQuads;
+            const int y = by * 4 + (r & 3), z = bz * 4 + (r >> 2);
+            const int x = bx0 * 3 + c * 4;
+            const bool rowok = y < ny && z < nz;
+            const uint16_t* row = src + ((int64_t)(rowok ? z : 0) * ny + (rowok ? y : 0)) * nx;
+            if (VEC && rowok && x + 3 < nx) {
+                w[k] = *reinterpret_cast<const uint2*>(row + x);
+            } else {
+                uint32_t v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (rowok && x + e < nx) ? (uint32_t)row[x + e] : 0u;
+                w[k] = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+            }
         }
+    }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) G.rows[r][c * 4 + e] = v[e];
+    for (int k = 0; k < kLoads; ++k) {   // voxels 4 c .. 4 c + 3 of row r: one 8-byte store
+        const int q = t + k * kThreads;
+        if (q < 16 * kQuads) *reinterpret_cast<uint2*>(&G.rows[q / kQuads][(q % kQuads) * 4]) = w[k];
     }
     __syncthreads();
     const int nb_here = min(kOvlBricks, nbx - bx0);
